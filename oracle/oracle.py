@@ -1,0 +1,136 @@
+"""ctypes wrapper of the CPU oracle (gdn_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: used by tests/, the smoke check and the CPU-baseline
+leg of the benchmark. The product path never imports this module.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SOURCES = [os.path.join(HERE, "gdn_oracle.c")]
+
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+          "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
+          "-Wno-unused-parameter"]
+
+
+def build(quiet: bool = True) -> str:
+    """Compile liboracle.so with gcc (plain C, no FMA contraction)."""
+    cmd = ["gcc", *CFLAGS, *SOURCES, "-o", LIB_PATH + ".tmp", "-lm"]
+    subprocess.run(cmd, check=True, capture_output=quiet)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class Params(C.Structure):
+    _fields_ = [("k", C.c_int32), ("leaf_cap", C.c_int32),
+                ("min_leaf_side", C.c_double), ("beta", C.c_double),
+                ("min_vox_count", C.c_int32), ("rho_percentile", C.c_double),
+                ("alpha", C.c_double), ("sigma", C.c_double),
+                ("eps", C.c_double), ("keep_ratio", C.c_double)]
+
+
+_P = C.c_void_p
+
+
+class Out(C.Structure):
+    _fields_ = [("key", _P), ("order", _P), ("leaf_of", _P), ("occ", _P),
+                ("p1", _P), ("nbr_idx", _P), ("nbr_d2", _P), ("r2k", _P),
+                ("rho", _P), ("p2", _P), ("score", _P), ("stage", _P),
+                ("keep", _P), ("kept_idx", _P),
+                ("leaf_begin", _P), ("leaf_end", _P), ("leaf_level", _P),
+                ("leaf_prefix", _P), ("leaf_h", _P), ("leaf_n1", _P),
+                ("leaf_n2", _P), ("leaf_m", _P), ("leaf_rho_med", _P),
+                ("leaf_ncand", _P),
+                ("n_kept", C.c_int64), ("n_leaves", C.c_int64),
+                ("pairs", C.c_uint64), ("threads", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        _lib = C.CDLL(LIB_PATH)
+        _lib.orc_denoise.argtypes = [_P, C.c_int64, C.POINTER(Params), C.POINTER(Out)]
+        _lib.orc_denoise.restype = C.c_int
+        _lib.orc_default_params.argtypes = [C.POINTER(Params)]
+        _lib.orc_morton_interleave.argtypes = [C.c_uint32] * 3
+        _lib.orc_morton_interleave.restype = C.c_uint64
+        _lib.orc_percentile_rank.argtypes = [C.c_int64, C.c_double]
+        _lib.orc_percentile_rank.restype = C.c_int64
+    return _lib
+
+
+def default_params() -> dict:
+    p = Params()
+    lib().orc_default_params(C.byref(p))
+    return {f: getattr(p, f) for f, _ in Params._fields_}
+
+
+def morton(qx: int, qy: int, qz: int) -> int:
+    return int(lib().orc_morton_interleave(qx, qy, qz))
+
+
+def percentile_rank(n: int, q: float) -> int:
+    return int(lib().orc_percentile_rank(n, q))
+
+
+def denoise(xyz: np.ndarray, **params) -> dict:
+    """Run the whole oracle pipeline; returns every intermediate array.
+
+    Per-point arrays are in original point order. Rows of ``nbr_idx`` /
+    ``nbr_d2`` / ``r2k`` / ``rho`` for points outside P1 are left at their
+    fill values (0xFFFFFFFF / NaN).
+    """
+    xyz = np.ascontiguousarray(xyz, dtype=np.float32)
+    n = xyz.shape[0]
+    p = default_params()
+    unknown = set(params) - set(p)
+    if unknown:
+        raise TypeError(f"unknown parameters {sorted(unknown)}")
+    p.update(params)
+    P = Params(**p)
+    k = P.k
+    m = max(n, 1)
+    a = dict(
+        key=np.zeros(m, np.uint64), order=np.zeros(m, np.uint32),
+        leaf_of=np.zeros(m, np.uint32), occ=np.zeros(m, np.uint32),
+        p1=np.zeros(m, np.uint8),
+        nbr_idx=np.full((m, k), 0xFFFFFFFF, np.uint32),
+        nbr_d2=np.full((m, k), np.nan, np.float32),
+        r2k=np.full(m, np.nan, np.float32), rho=np.full(m, np.nan, np.float64),
+        p2=np.zeros(m, np.uint8), score=np.zeros(m, np.float64),
+        stage=np.zeros(m, np.uint8), keep=np.zeros(m, np.uint8),
+        kept_idx=np.zeros(m, np.uint32),
+        leaf_begin=np.zeros(m, np.uint32), leaf_end=np.zeros(m, np.uint32),
+        leaf_level=np.zeros(m, np.uint32), leaf_prefix=np.zeros(m, np.uint64),
+        leaf_h=np.zeros(m, np.float32), leaf_n1=np.zeros(m, np.uint32),
+        leaf_n2=np.zeros(m, np.uint32), leaf_m=np.zeros(m, np.uint32),
+        leaf_rho_med=np.zeros(m, np.float64), leaf_ncand=np.zeros(m, np.uint32),
+    )
+    o = Out(**{name: arr.ctypes.data for name, arr in a.items()})
+    rc = lib().orc_denoise(xyz.ctypes.data if n else None, n, C.byref(P), C.byref(o))
+    if rc != 0:
+        raise ValueError("oracle rejected the parameters")
+    nl = o.n_leaves
+    res = {}
+    for name, arr in a.items():
+        if name.startswith("leaf_") and name != "leaf_of":
+            res[name] = arr[:nl].copy()
+        elif name == "kept_idx":
+            res[name] = arr[:o.n_kept].copy()
+        else:
+            res[name] = arr[:n].copy()
+    res.update(n_kept=o.n_kept, n_leaves=nl, pairs=int(o.pairs),
+               threads=o.threads, params=p)
+    return res
