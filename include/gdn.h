@@ -1,0 +1,126 @@
+/*
+ * gdn.h - C ABI of the MI355X (gfx950) library for the adaptive dual-weight
+ * gravitational point-cloud denoiser (arxiv 2512.10386, Section 3).
+ *
+ * Problem statement (Sec. 3): a frame P = {p_1..p_N} of xyz points goes in;
+ * out come the denoised subset P_denoise (Eq. 22) as a keep-mask and a list of
+ * kept indices, and the per-point weighted gravitational score F_i (Eq. 21).
+ *
+ * Conventions for every call:
+ *   - Array arguments are DEVICE pointers on the context's GPU, allocated and
+ *     owned by the caller. The library allocates no device memory on the
+ *     denoise path: all scratch lives in the caller's workspace.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *     No call synchronises the host except gdn_create/gdn_destroy.
+ *   - Parameter and size errors are reported synchronously by the return
+ *     value, with nothing enqueued. Conditions only the GPU can see
+ *     (non-finite coordinates, an exhausted internal wait) are recorded in a
+ *     device status word readable with gdn_debug_dump(GDN_DUMP_STATUS).
+ *   - A context is not thread-safe; use one context per host thread/stream.
+ *   - No C++ exception crosses this interface.
+ */
+#ifndef GDN_H
+#define GDN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GDN_OK = 0,
+    GDN_EINVAL = 1,      /* bad parameter, size or pointer */
+    GDN_ENOMEM = 2,      /* workspace too small */
+    GDN_ECAPACITY = 3,   /* input larger than the library supports */
+    GDN_EHIP = 4,        /* a HIP runtime call failed */
+    GDN_EINTERNAL = 5
+} gdn_status;
+
+/* Device status word bits (GDN_DUMP_STATUS). */
+#define GDN_DEV_NONFINITE   1u  /* some coordinate was NaN/inf: outputs unspecified */
+#define GDN_DEV_WAIT_LIMIT  2u  /* an inter-workgroup wait hit its spin limit */
+
+typedef struct {
+    int32_t k;              /* K of Eq. 13 and Eq. 15: neighbours per point, 1..64 */
+    int32_t leaf_cap;       /* octree: max points per leaf (Sec. 3), >= 1 */
+    double  min_leaf_side;  /* octree: min leaf side in input units; <= 0: depth 21 */
+    double  beta;           /* voxel enlargement coefficient of Eq. 11, > 0 */
+    int32_t min_vox_count;  /* n_v of Eq. 12, >= 1 */
+    double  rho_percentile; /* q of Eq. 14 in PERCENT (MATLAB prctile), 0..100 */
+    double  alpha;          /* density-weight exponent of Eq. 17, >= 0 */
+    double  sigma;          /* bandwidth scale of Eq. 18, > 0 */
+    double  eps;            /* epsilon of Eq. 17 and Eq. 20, >= 0 */
+    double  keep_ratio;     /* lambda: top fraction of P2 kept per leaf, (0, 1] */
+} gdn_params;
+
+typedef struct gdn_ctx gdn_ctx;
+
+/* Defaults: k=12, rho_percentile=0.2, min_vox_count=4 (the paper's defaults,
+ * Sec. 4.3.1); beta=1, alpha=1, sigma=1, eps=1e-12, keep_ratio=0.98,
+ * leaf_cap=512, min_leaf_side=0 (not valued in the paper). */
+gdn_status gdn_default_params(gdn_params *out);
+
+/* Create a context bound to HIP device `device`. */
+gdn_status gdn_create(gdn_ctx **out, int device);
+void gdn_destroy(gdn_ctx *ctx);
+
+/* Workspace bytes gdn_denoise needs for a frame of n points (n <= 2^30-1). */
+gdn_status gdn_workspace_size(gdn_ctx *ctx, const gdn_params *p, int64_t n, size_t *bytes);
+
+/*
+ * Denoise one frame.
+ *   xyz       [n][3] float32, row-major, input points (read only)
+ *   workspace >= gdn_workspace_size bytes, 256-byte aligned; contents on entry
+ *             are ignored; it holds this frame's intermediates until reused
+ *   keep      [n] uint8: 1 if the point is in P_denoise (Eq. 22)
+ *   score     [n] float32: F_i of Eq. 21 for points scored (the set P2 of
+ *             Eq. 14); -1 for points removed before scoring
+ *   stage     [n] uint8 or NULL: 0 removed by the voxel filter (Eq. 12),
+ *             1 removed by the density filter (Eq. 14), 2 removed by the
+ *             per-leaf top-lambda rule, 3 kept
+ *   kept_idx  [n] uint32: the first *n_kept entries are the kept point
+ *             indices in ascending order
+ *   n_kept    device int64 scalar
+ * Returns GDN_EINVAL for bad parameters/null pointers, GDN_ENOMEM if
+ * workspace_bytes is too small, GDN_ECAPACITY if n > 2^30-1.
+ */
+gdn_status gdn_denoise(gdn_ctx *ctx, const gdn_params *p, const float *xyz, int64_t n,
+                       void *workspace, size_t workspace_bytes,
+                       uint8_t *keep, float *score, uint8_t *stage,
+                       uint32_t *kept_idx, int64_t *n_kept, void *stream);
+
+/* Intermediates of the last gdn_denoise on this context (its workspace must
+ * be untouched since). Per-point arrays are in ORIGINAL point order. */
+enum {
+    GDN_DUMP_STATUS = 0,     /* uint32 device status word (GDN_DEV_*) */
+    GDN_DUMP_COUNTS = 1,     /* int64[4]: n_leaves, |P1|, kNN pair count W, n_kept */
+    GDN_DUMP_KEYS = 2,       /* uint64[n] Morton keys */
+    GDN_DUMP_ORDER = 3,      /* uint32[n] original index at each sorted position */
+    GDN_DUMP_LEAF_OF = 4,    /* uint32[n] leaf id of each point */
+    GDN_DUMP_LEAF_TABLE = 5, /* uint32[n_leaves][4]: begin, end, level, fp32 bits of h */
+    GDN_DUMP_OCC = 6,        /* uint32[n] voxel occupancy n(voxel(p)) of Eq. 12 */
+    GDN_DUMP_P1 = 7,         /* uint8[n] */
+    GDN_DUMP_NBR_IDX = 8,    /* uint32[n][k] neighbours (original idx) of P1 points,
+                                (d2, idx) ascending, 0xFFFFFFFF padding */
+    GDN_DUMP_NBR_D2 = 9,     /* float[n][k] fp32 squared distances, +inf padding */
+    GDN_DUMP_R2K = 10,       /* float[n] squared k-th distance (+inf: fewer than k) */
+    GDN_DUMP_RHO = 11,       /* double[n] density of Eq. 13 */
+    GDN_DUMP_P2 = 12,        /* uint8[n] */
+    GDN_DUMP_LEAF_RHO_MED = 13, /* double[n_leaves] median density of Eq. 16 */
+    GDN_DUMP_SCORE64 = 14,   /* double[n] score of Eq. 21 (-1 if not scored) */
+    GDN_DUMP_LEAF_NCAND = 15 /* uint32[n_leaves] candidate count |C_t| */
+};
+/* Copy one intermediate into device buffer dst (dst_bytes must hold it;
+ * rows not defined for a point are filled with the padding values). */
+gdn_status gdn_debug_dump(gdn_ctx *ctx, int what, void *dst, size_t dst_bytes, void *stream);
+
+const char *gdn_status_string(gdn_status s);
+/* Message of the last failed call on ctx ("" if none). */
+const char *gdn_last_error(gdn_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,204 @@
+"""Thin ctypes binding of libgdn.so (include/gdn.h).
+
+The functions named gdn_* mirror the C ABI one to one and only marshal
+arguments; every step of the denoiser runs in the library's HIP kernels.
+``Denoiser`` adds torch-side allocation of outputs and workspace on the
+current stream. Importing this module does not load the library; the first
+call does, and raises if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgdn.so")
+
+GDN_OK, GDN_EINVAL, GDN_ENOMEM, GDN_ECAPACITY, GDN_EHIP, GDN_EINTERNAL = range(6)
+GDN_DEV_NONFINITE = 1
+GDN_DEV_WAIT_LIMIT = 2
+
+DUMP = dict(STATUS=0, COUNTS=1, KEYS=2, ORDER=3, LEAF_OF=4, LEAF_TABLE=5, OCC=6, P1=7,
+            NBR_IDX=8, NBR_D2=9, R2K=10, RHO=11, P2=12, LEAF_RHO_MED=13, SCORE64=14,
+            LEAF_NCAND=15)
+
+
+class gdn_params(C.Structure):
+    _fields_ = [("k", C.c_int32), ("leaf_cap", C.c_int32),
+                ("min_leaf_side", C.c_double), ("beta", C.c_double),
+                ("min_vox_count", C.c_int32), ("rho_percentile", C.c_double),
+                ("alpha", C.c_double), ("sigma", C.c_double),
+                ("eps", C.c_double), ("keep_ratio", C.c_double)]
+
+
+class GdnError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"gdn status {status}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libgdn.so; raise if it is missing (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2512_10386_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, sz = C.c_void_p, C.c_int64, C.c_size_t
+        L.gdn_default_params.argtypes = [C.POINTER(gdn_params)]
+        L.gdn_create.argtypes = [C.POINTER(vp), C.c_int]
+        L.gdn_destroy.argtypes = [vp]
+        L.gdn_destroy.restype = None
+        L.gdn_workspace_size.argtypes = [vp, C.POINTER(gdn_params), i64, C.POINTER(sz)]
+        L.gdn_denoise.argtypes = [vp, C.POINTER(gdn_params), vp, i64, vp, sz, vp, vp, vp, vp, vp, vp]
+        L.gdn_debug_dump.argtypes = [vp, C.c_int, vp, sz, vp]
+        L.gdn_status_string.argtypes = [C.c_int]
+        L.gdn_status_string.restype = C.c_char_p
+        L.gdn_last_error.argtypes = [vp]
+        L.gdn_last_error.restype = C.c_char_p
+        for f in ("gdn_default_params", "gdn_create", "gdn_workspace_size", "gdn_denoise",
+                  "gdn_debug_dump"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(ctx, status):
+    if status != GDN_OK:
+        msg = lib().gdn_last_error(ctx).decode() if ctx else ""
+        if not msg:
+            msg = lib().gdn_status_string(status).decode()
+        raise GdnError(status, msg)
+
+
+# ------------------------------------------------------------ C ABI mirror
+
+
+def gdn_default_params() -> gdn_params:
+    p = gdn_params()
+    _check(None, lib().gdn_default_params(C.byref(p)))
+    return p
+
+
+def gdn_create(device: int = 0) -> int:
+    h = C.c_void_p()
+    _check(None, lib().gdn_create(C.byref(h), device))
+    return h.value
+
+
+def gdn_destroy(ctx: int) -> None:
+    lib().gdn_destroy(ctx)
+
+
+def gdn_workspace_size(ctx: int, p: gdn_params, n: int) -> int:
+    b = C.c_size_t()
+    _check(ctx, lib().gdn_workspace_size(ctx, C.byref(p), n, C.byref(b)))
+    return b.value
+
+
+def gdn_denoise(ctx, p, xyz, n, workspace, workspace_bytes, keep, score, stage,
+                kept_idx, n_kept, stream) -> None:
+    _check(ctx, lib().gdn_denoise(ctx, C.byref(p), xyz, n, workspace, workspace_bytes,
+                                  keep, score, stage, kept_idx, n_kept, stream))
+
+
+def gdn_debug_dump(ctx, what, dst, dst_bytes, stream) -> None:
+    _check(ctx, lib().gdn_debug_dump(ctx, what, dst, dst_bytes, stream))
+
+
+def make_params(**kw) -> gdn_params:
+    p = gdn_default_params()
+    names = {f for f, _ in gdn_params._fields_}
+    for key, v in kw.items():
+        if key not in names:
+            raise TypeError(f"unknown parameter {key!r}")
+        setattr(p, key, v)
+    return p
+
+
+# ------------------------------------------------------------ torch wrapper
+
+
+@dataclass
+class Result:
+    keep: "object"      # uint8 [n]
+    score: "object"     # float32 [n]
+    stage: "object"     # uint8 [n]
+    kept_idx: "object"  # int32 view of uint32 [n]; first n_kept entries valid
+    n_kept: "object"    # int64 [1] device scalar
+
+
+class Denoiser:
+    """One library context plus a reusable workspace on a CUDA (HIP) device."""
+
+    def __init__(self, device: int = 0, **params):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.ctx = gdn_create(device)
+        self.params = make_params(**params)
+        self._ws = None
+
+    def close(self):
+        if self.ctx:
+            gdn_destroy(self.ctx)
+            self.ctx = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, **params):
+        self.params = make_params(**params)
+
+    def workspace(self, n: int):
+        need = gdn_workspace_size(self.ctx, self.params, n)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = self.torch.empty(max(need, 256), dtype=self.torch.uint8, device=self.device)
+        return self._ws, need
+
+    def __call__(self, xyz, out: Result | None = None) -> Result:
+        torch = self.torch
+        if xyz.device != self.device or xyz.dtype != torch.float32 or xyz.dim() != 2 or xyz.shape[1] != 3:
+            raise ValueError("xyz must be a float32 [n, 3] tensor on the context's device")
+        xyz = xyz.contiguous()
+        n = xyz.shape[0]
+        ws, need = self.workspace(n)
+        if out is None:
+            out = Result(keep=torch.empty(n, dtype=torch.uint8, device=self.device),
+                         score=torch.empty(n, dtype=torch.float32, device=self.device),
+                         stage=torch.empty(n, dtype=torch.uint8, device=self.device),
+                         kept_idx=torch.empty(max(n, 1), dtype=torch.int32, device=self.device),
+                         n_kept=torch.empty(1, dtype=torch.int64, device=self.device))
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        gdn_denoise(self.ctx, self.params, xyz.data_ptr(), n, ws.data_ptr(), ws.numel(),
+                    out.keep.data_ptr(), out.score.data_ptr(), out.stage.data_ptr(),
+                    out.kept_idx.data_ptr(), out.n_kept.data_ptr(), stream)
+        return out
+
+    def dump(self, what: str, n: int):
+        """Intermediates of the last frame (original point order), as a tensor."""
+        torch = self.torch
+        k = self.params.k
+        spec = {
+            "STATUS": (torch.int32, (1,)), "COUNTS": (torch.int64, (4,)),
+            "KEYS": (torch.int64, (n,)), "ORDER": (torch.int32, (n,)),
+            "LEAF_OF": (torch.int32, (n,)), "LEAF_TABLE": (torch.int32, (n, 4)),
+            "OCC": (torch.int32, (n,)), "P1": (torch.uint8, (n,)),
+            "NBR_IDX": (torch.int32, (n, k)), "NBR_D2": (torch.float32, (n, k)),
+            "R2K": (torch.float32, (n,)), "RHO": (torch.float64, (n,)),
+            "P2": (torch.uint8, (n,)), "LEAF_RHO_MED": (torch.float64, (n,)),
+            "SCORE64": (torch.float64, (n,)), "LEAF_NCAND": (torch.int32, (n,)),
+        }
+        dt, shape = spec[what]
+        t = torch.empty(shape, dtype=dt, device=self.device)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        gdn_debug_dump(self.ctx, DUMP[what], t.data_ptr(), t.numel() * t.element_size(), stream)
+        return t

@@ -1,0 +1,221 @@
+// Shared device helpers and the workspace plan of the gfx950 denoiser.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gdn {
+
+constexpr int MORTON_BITS = 21;
+constexpr uint32_t QMAX = (1u << MORTON_BITS) - 1u;
+
+// Tile sizes.
+constexpr int SORT_BLOCK = 256;               // radix-sort workgroup
+constexpr int SORT_ITEMS = 16;                // keys per thread
+constexpr int SORT_TILE = SORT_BLOCK * SORT_ITEMS;
+constexpr int SORT_PASSES = 8;                // 8-bit digits over the 63-bit key
+constexpr int SCAN_BLOCK = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
+constexpr int KNN_TQ = 256;                   // queries per kNN work item
+constexpr int KNN_CT = 1024;                  // candidates per LDS tile
+constexpr int KNN_CC0 = 4096;                 // initial candidate chunk
+constexpr int KNN_NCH_MAX = 32;               // max candidate chunks per leaf
+constexpr int HALO = 27;
+constexpr int VOX_BLOCK = 256;
+constexpr int VOX_LDS_SLOTS = 4096;           // LDS hash slots (leaves <= 2048 pts)
+constexpr int SEL_BLOCK = 256;
+
+// Status word packing for decoupled look-back: 2 flag bits + 30 value bits.
+constexpr uint32_t LB_FLAG_AGG = 1u << 30;
+constexpr uint32_t LB_FLAG_PRE = 2u << 30;
+constexpr uint32_t LB_VALUE = (1u << 30) - 1u;
+constexpr uint32_t SPIN_LIMIT = 1u << 22;
+
+constexpr uint32_t DEV_NONFINITE = 1u;
+constexpr uint32_t DEV_WAIT_LIMIT = 2u;
+
+// Scalars the kernels share through device memory (inside the zeroed block).
+struct Counters {
+    uint32_t bbox_max[3];   // ordered-uint max of x, y, z
+    uint32_t bbox_nmin[3];  // ordered-uint max of ~x (i.e. the min)
+    uint32_t nonfinite;
+    uint32_t status;
+    uint32_t n_leaves;
+    uint32_t n_p1;
+    uint32_t n_items;
+    uint32_t n_kept;
+    uint32_t sort_tile_ctr[SORT_PASSES];
+    uint32_t scan_tile_ctr[4];
+    unsigned long long pairs;
+    uint32_t knn_next;        // dynamic work-queue cursor of the kNN kernel
+    uint32_t pad[5];
+};
+
+// Frame constants derived on the device from the bounding box.
+struct FrameConst {
+    float lo[3];
+    int32_t dmax;
+    double S;
+    double scale;
+};
+
+struct KnnItem {
+    uint32_t leaf, q0, q1, chunk;
+};
+
+// Method parameters as the kernels use them.
+struct Params {
+    int32_t k;
+    int32_t leaf_cap;
+    double min_leaf_side;
+    double beta;
+    int32_t min_vox_count;
+    double rho_percentile;
+    double alpha;
+    double sigma;
+    double eps;
+    double keep_ratio;
+};
+
+// Pointers into the caller's workspace for one frame of n points.
+struct Plan {
+    uint32_t n;
+    int k;
+    size_t bytes;
+    // zero-initialised block
+    char* zero_begin;
+    size_t zero_bytes;
+    Counters* ctr;
+    uint32_t* sort_hist;      // [SORT_PASSES][256]
+    uint32_t* sort_status;    // [SORT_PASSES][sort_tiles][256]
+    uint32_t* scan_status;    // [4][scan_tiles]
+    uint32_t sort_tiles, scan_tiles;
+    // frame
+    FrameConst* fc;
+    // sort (sorted order = s)
+    uint64_t* keys_a;
+    uint64_t* keys_b;
+    uint32_t* idx_a;
+    uint32_t* idx_b;
+    float4* pos4;             // [n] sorted x, y, z, original index bits
+    uint32_t* leaf_of;        // [n] sorted
+    uint32_t* occ;            // [n] sorted
+    uint8_t* p1;              // [n] sorted
+    uint32_t* p1pos;          // [n+1] exclusive scan of p1
+    // leaves (at most n)
+    uint32_t* leaf_begin;     // [n+1]
+    uint32_t* leaf_level;     // [n]
+    uint64_t* leaf_prefix;    // [n]
+    float* leaf_h;            // [n]
+    uint32_t* leaf_nr;        // [n] number of candidate ranges
+    uint2* leaf_ranges;       // [n][HALO] compacted candidate ranges
+    uint32_t* leaf_ncand;     // [n]
+    uint32_t* leaf_nch;       // [n] candidate chunks
+    uint32_t* leaf_cc;        // [n] chunk length
+    uint32_t* leaf_plist;     // [n] first partial list of the leaf
+    double* leaf_rho_med;     // [n]
+    float* leaf_r2cut;        // [n]
+    uint32_t* leaf_m;         // [n]
+    uint64_t* vox_keys;       // [2n] global hash fallback
+    uint32_t* vox_cnt;        // [2n]
+    // compacted P1 (query/candidate index q)
+    float4* cand4;            // [n]
+    uint32_t* cand_leaf;      // [n]
+    uint32_t* nbr;            // [n][k] original indices
+    float* nbr_d2;            // [n][k]
+    float* r2k;               // [n]
+    double* rho_c;            // [n]
+    double* r64_c;            // [n]
+    double* afac_c;           // [n] (rho_i / (rho_med^2 + eps))^(alpha/2)
+    uint8_t* p2;              // [n]
+    uint8_t* stage_c;         // [n] 1 density-removed, 2 score-removed, 3 kept
+    double* score_c;          // [n]
+    double* rho_o;            // [n] original order
+    double* gpow_o;           // [n] original order rho^(alpha/2)
+    // kNN work
+    KnnItem* items;           // [items_max]
+    uint32_t items_max;
+    uint64_t* plist;          // [plist_max][k] partial top-k keys
+    uint32_t plist_max;
+};
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ uint32_t f32_ordered(float f) {
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float f32_from_ordered(uint32_t o) {
+    uint32_t u = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
+    return __uint_as_float(u);
+}
+
+__device__ __forceinline__ uint32_t ld_acquire_agent(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_release_agent(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wave-level inclusive scan (wave64).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block exclusive scan of one value per thread (blockDim multiple of 64, <= 1024).
+// `smem` needs blockDim/64 + 1 words. Returns the exclusive prefix; *total gets
+// the block sum. Contains __syncthreads.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* smem, uint32_t* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) smem[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int w = 0; w < nw; ++w) { uint32_t t = smem[w]; smem[w] = run; run += t; }
+        smem[nw] = run;
+    }
+    __syncthreads();
+    uint32_t ex = smem[wave] + inc - v;
+    *total = smem[nw];
+    __syncthreads();
+    return ex;
+}
+
+// 3D bit interleave (x in the lowest bit), magic-number spreading.
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+    uint64_t x = v & 0x1FFFFFu;
+    x = (x | (x << 32)) & 0x1F00000000FFFFull;
+    x = (x | (x << 16)) & 0x1F0000FF0000FFull;
+    x = (x | (x << 8)) & 0x100F00F00F00F00Full;
+    x = (x | (x << 4)) & 0x10C30C30C30C30C3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+__device__ __forceinline__ uint32_t compact3(uint64_t x) {
+    x &= 0x1249249249249249ull;
+    x = (x ^ (x >> 2)) & 0x10C30C30C30C30C3ull;
+    x = (x ^ (x >> 4)) & 0x100F00F00F00F00Full;
+    x = (x ^ (x >> 8)) & 0x1F0000FF0000FFull;
+    x = (x ^ (x >> 16)) & 0x1F00000000FFFFull;
+    x = (x ^ (x >> 32)) & 0x1FFFFFull;
+    return (uint32_t)x;
+}
+__device__ __forceinline__ uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+    return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
+}  // namespace gdn

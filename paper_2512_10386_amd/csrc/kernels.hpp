@@ -1,0 +1,37 @@
+// Host-side launchers of the denoiser's kernels (one group per source file).
+#pragma once
+
+#include "common.hpp"
+
+namespace gdn {
+
+// frame.hip: zero-fill, frame bbox, Morton keys, radix sort, permute
+void launch_zero(const Plan& P, hipStream_t st);
+void launch_bbox(const Plan& P, const float* xyz, hipStream_t st);
+void launch_morton(const Plan& P, const Params& prm, const float* xyz, hipStream_t st);
+void launch_sort(const Plan& P, hipStream_t st);
+void launch_permute(const Plan& P, const float* xyz, hipStream_t st);
+
+// octree.hip: leaves, voxel filter, P1 compaction, halo ranges, kNN plan
+void launch_leaves(const Plan& P, const Params& prm, hipStream_t st);
+void launch_voxel(const Plan& P, const Params& prm, hipStream_t st);
+void launch_p1_compact(const Plan& P, hipStream_t st);
+void launch_halo(const Plan& P, hipStream_t st);
+void launch_knn_plan(const Plan& P, hipStream_t st);
+
+// knn.hip: brute-force kNN over leaf + halo candidates, partial-list merge
+void launch_knn(const Plan& P, int k, int num_cus, hipStream_t st);
+
+// score.hip: density, percentile/median, score, top-lambda, outputs
+void launch_density(const Plan& P, const Params& prm, const float* xyz, hipStream_t st);
+void launch_leaf_select(const Plan& P, const Params& prm, hipStream_t st);
+void launch_score(const Plan& P, const Params& prm, const float* xyz, hipStream_t st);
+void launch_topl(const Plan& P, const Params& prm, hipStream_t st);
+void launch_outputs(const Plan& P, uint8_t* keep, float* score, uint8_t* stage,
+                    uint32_t* kept_idx, int64_t* n_kept, hipStream_t st);
+void launch_write_zero_count(int64_t* n_kept, hipStream_t st);
+
+// dump.hip: intermediates back in original point order
+int launch_dump(const Plan& P, int what, void* dst, size_t dst_bytes, hipStream_t st);
+
+}  // namespace gdn

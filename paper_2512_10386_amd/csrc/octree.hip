@@ -1,0 +1,426 @@
+// Octree partition (Sec. 3), per-leaf adaptive voxel filter (Eq. 10-12),
+// compaction of P1, the 27-cell halo candidate ranges of each leaf and the
+// kNN work plan.
+#include "kernels.hpp"
+#include "scan.hpp"
+
+namespace gdn {
+
+// Number of leading octal digits two 63-bit Morton keys share (21 if equal).
+__device__ __forceinline__ int common_digits(uint64_t a, uint64_t b) {
+    if (a == b) return MORTON_BITS;
+    return (__clzll((long long)(a ^ b)) - 1) / 3;
+}
+
+// ---------------------------------------------------------------- leaves
+//
+// Leaves are the non-empty nodes reached by splitting every node that holds
+// more than leaf_cap points above the depth limit. In the sorted key order a
+// leaf boundary falls between positions j-1 and j exactly when the deepest
+// cell holding both (level l = their common digits) is split, i.e. l < dmax
+// and that cell holds more than leaf_cap points. The cell count is tested
+// with one windowed binary search (window leaf_cap + 1).
+
+struct BoundaryGet {
+    const uint64_t* keys;
+    const FrameConst* fc;
+    uint32_t n, cap;
+    __device__ uint32_t operator()(uint32_t j) const {
+        if (j == 0) return 1u;
+        const uint64_t a = keys[j - 1], b = keys[j];
+        const int l = common_digits(a, b);
+        if (l >= fc->dmax) return 0u;
+        const int sh = 3 * (MORTON_BITS - l);
+        const uint64_t P = b >> sh;
+        uint32_t lo = (j - 1 > cap) ? j - 1 - cap : 0u;
+        uint32_t hi = j - 1;
+        while (lo < hi) {
+            uint32_t mid = (lo + hi) >> 1;
+            if ((keys[mid] >> sh) < P) lo = mid + 1;
+            else hi = mid;
+        }
+        const uint64_t probe = (uint64_t)lo + cap;
+        return (probe < n && (keys[probe] >> sh) == P) ? 1u : 0u;
+    }
+};
+
+struct BoundaryEmit {
+    uint32_t* leaf_of;
+    uint32_t* leaf_begin;
+    __device__ void operator()(uint32_t j, uint32_t ex, uint32_t f) const {
+        leaf_of[j] = ex + f - 1u;
+        if (f) leaf_begin[ex] = j;
+    }
+};
+
+struct BoundaryFin {
+    Counters* c;
+    uint32_t* leaf_begin;
+    uint32_t n;
+    __device__ void operator()(uint32_t total) const {
+        c->n_leaves = total;
+        leaf_begin[total] = n;
+    }
+};
+
+// Level and prefix of each leaf [s, e): with m = the larger of the common
+// digits across its two borders, the leaf is the level-(m+1) cell unless it
+// is an over-full cell at the depth limit.
+__global__ __launch_bounds__(256) void leaf_table_kernel(Plan P, uint32_t cap) {
+    const uint32_t nl = P.ctr->n_leaves;
+    const int dmax = P.fc->dmax;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nl; t += gridDim.x * blockDim.x) {
+        const uint32_t s = P.leaf_begin[t], e = P.leaf_begin[t + 1];
+        int m = -1;
+        if (s > 0) m = common_digits(P.keys_a[s - 1], P.keys_a[s]);
+        if (e < P.n) m = max(m, common_digits(P.keys_a[e - 1], P.keys_a[e]));
+        int level = (e - s <= cap) ? m + 1 : dmax;
+        level = level < 0 ? 0 : (level > MORTON_BITS ? MORTON_BITS : level);
+        P.leaf_level[t] = (uint32_t)level;
+        P.leaf_prefix[t] = P.keys_a[s] >> (3 * (MORTON_BITS - level));
+    }
+}
+
+void launch_leaves(const Plan& P, const Params& prm, hipStream_t st) {
+    BoundaryGet g{P.keys_a, P.fc, P.n, (uint32_t)prm.leaf_cap};
+    BoundaryEmit e{P.leaf_of, P.leaf_begin};
+    BoundaryFin f{P.ctr, P.leaf_begin, P.n};
+    launch_scan(g, e, f, nullptr, P.n, P.scan_status, &P.ctr->scan_tile_ctr[0], &P.ctr->status, st);
+    unsigned blocks = (P.n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(leaf_table_kernel, dim3(blocks), dim3(256), 0, st, P, (uint32_t)prm.leaf_cap);
+}
+
+// ---------------------------------------------------------------- voxel filter
+//
+// One workgroup per leaf: tight fp32 bbox of the leaf's points, V_t (Eq. 10),
+// h = beta * (V_t / N_t)^(1/3) rounded to fp32 (Eq. 11), voxel index
+// floor((x - min) / h) per axis in FP64, occupancy n(voxel(p)) by an
+// LDS-private hash (a per-leaf global region for leaves too big for LDS), and
+// P1 = occupancy >= n_v (Eq. 12).
+
+__device__ __forceinline__ uint32_t vox_hash(uint64_t k) {
+    return (uint32_t)((k * 0x9E3779B97F4A7C15ull) >> 32);
+}
+
+__device__ __forceinline__ uint64_t vox_key(float4 p, float mx_, float my_, float mz_, double h) {
+    double v[3] = {floor(((double)p.x - (double)mx_) / h), floor(((double)p.y - (double)my_) / h),
+                   floor(((double)p.z - (double)mz_) / h)};
+    uint64_t k = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double f = v[a];
+        if (!(f >= 0.0)) f = 0.0;
+        if (f > (double)QMAX) f = (double)QMAX;
+        k |= (uint64_t)f << (21 * a);
+    }
+    return k;
+}
+
+__global__ __launch_bounds__(VOX_BLOCK) void voxel_kernel(Plan P, double beta, uint32_t nv) {
+    __shared__ unsigned long long s_key[VOX_LDS_SLOTS];
+    __shared__ uint32_t s_cnt[VOX_LDS_SLOTS];
+    __shared__ float s_red[6][VOX_BLOCK / 64];
+    __shared__ float s_mn[3];
+    __shared__ float s_h;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t nl = P.ctr->n_leaves;
+    constexpr unsigned long long EMPTY = ~0ull;
+    for (uint32_t t = blockIdx.x; t < nl; t += gridDim.x) {
+        const uint32_t b = P.leaf_begin[t], e = P.leaf_begin[t + 1], nt = e - b;
+        float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (uint32_t s = b + tid; s < e; s += VOX_BLOCK) {
+            float4 p = P.pos4[s];
+            mn[0] = fminf(mn[0], p.x); mx[0] = fmaxf(mx[0], p.x);
+            mn[1] = fminf(mn[1], p.y); mx[1] = fmaxf(mx[1], p.y);
+            mn[2] = fminf(mn[2], p.z); mx[2] = fmaxf(mx[2], p.z);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                mn[a] = fminf(mn[a], __shfl_xor(mn[a], o, 64));
+                mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], o, 64));
+            }
+        if (lane == 0)
+            for (int a = 0; a < 3; ++a) { s_red[a][wave] = mn[a]; s_red[3 + a][wave] = mx[a]; }
+        __syncthreads();
+        if (tid == 0) {
+            double H[3];
+            for (int a = 0; a < 3; ++a) {
+                float lo = s_red[a][0], hi = s_red[3 + a][0];
+                for (int w = 1; w < VOX_BLOCK / 64; ++w) { lo = fminf(lo, s_red[a][w]); hi = fmaxf(hi, s_red[3 + a][w]); }
+                s_mn[a] = lo;
+                H[a] = (double)hi - (double)lo;
+            }
+            double V = (H[0] * H[1]) * H[2];
+            float h32 = (float)(beta * cbrt(V / (double)nt));
+            if (!(h32 > 0.0f) || !isfinite(h32)) h32 = 0.0f;
+            s_h = h32;
+            P.leaf_h[t] = h32;
+        }
+        __syncthreads();
+        const float h32 = s_h;
+        if (h32 == 0.0f) {
+            for (uint32_t s = b + tid; s < e; s += VOX_BLOCK) {
+                P.occ[s] = nt;
+                P.p1[s] = nt >= nv;
+            }
+        } else {
+            const double h = (double)h32;
+            const float m0 = s_mn[0], m1 = s_mn[1], m2 = s_mn[2];
+            const bool lds = nt <= VOX_LDS_SLOTS / 2;
+            const uint32_t slots = lds ? (uint32_t)VOX_LDS_SLOTS : 2u * nt;
+            unsigned long long* tk = lds ? s_key : (unsigned long long*)(P.vox_keys + 2 * (size_t)b);
+            uint32_t* tc = lds ? s_cnt : P.vox_cnt + 2 * (size_t)b;
+            for (uint32_t i = tid; i < slots; i += VOX_BLOCK) { tk[i] = EMPTY; tc[i] = 0u; }
+            __syncthreads();
+            for (uint32_t s = b + tid; s < e; s += VOX_BLOCK) {
+                const unsigned long long k = vox_key(P.pos4[s], m0, m1, m2, h);
+                uint32_t slot = vox_hash(k) % slots;
+                for (uint32_t probe = 0; probe < slots; ++probe) {
+                    unsigned long long prev = atomicCAS(&tk[slot], EMPTY, k);
+                    if (prev == EMPTY || prev == k) {
+                        atomicAdd(&tc[slot], 1u);
+                        break;
+                    }
+                    slot = (slot + 1 == slots) ? 0u : slot + 1;
+                }
+            }
+            __syncthreads();
+            for (uint32_t s = b + tid; s < e; s += VOX_BLOCK) {
+                const unsigned long long k = vox_key(P.pos4[s], m0, m1, m2, h);
+                uint32_t slot = vox_hash(k) % slots;
+                uint32_t c = 0;
+                for (uint32_t probe = 0; probe < slots; ++probe) {
+                    if (tk[slot] == k) { c = tc[slot]; break; }
+                    slot = (slot + 1 == slots) ? 0u : slot + 1;
+                }
+                P.occ[s] = c;
+                P.p1[s] = c >= nv;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+void launch_voxel(const Plan& P, const Params& prm, hipStream_t st) {
+    unsigned blocks = P.n < 2048 ? P.n : 2048;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(voxel_kernel, dim3(blocks), dim3(VOX_BLOCK), 0, st, P, prm.beta,
+                       (uint32_t)prm.min_vox_count);
+}
+
+// ---------------------------------------------------------------- P1 compaction
+
+struct P1Get {
+    const uint8_t* p1;
+    __device__ uint32_t operator()(uint32_t s) const { return p1[s]; }
+};
+struct P1Emit {
+    uint32_t* p1pos;
+    const float4* pos4;
+    const uint32_t* leaf_of;
+    float4* cand4;
+    uint32_t* cand_leaf;
+    __device__ void operator()(uint32_t s, uint32_t ex, uint32_t f) const {
+        p1pos[s] = ex;
+        if (f) {
+            cand4[ex] = pos4[s];
+            cand_leaf[ex] = leaf_of[s];
+        }
+    }
+};
+struct P1Fin {
+    Counters* c;
+    uint32_t* p1pos;
+    uint32_t n;
+    __device__ void operator()(uint32_t total) const {
+        c->n_p1 = total;
+        p1pos[n] = total;
+    }
+};
+
+void launch_p1_compact(const Plan& P, hipStream_t st) {
+    launch_scan(P1Get{P.p1}, P1Emit{P.p1pos, P.pos4, P.leaf_of, P.cand4, P.cand_leaf},
+                P1Fin{P.ctr, P.p1pos, P.n}, nullptr, P.n, P.scan_status + P.scan_tiles,
+                &P.ctr->scan_tile_ctr[1], &P.ctr->status, st);
+}
+
+// ---------------------------------------------------------------- halo ranges
+//
+// Candidates of leaf t at level d: the P1 points of the 3x3x3 block of
+// level-d cells around the leaf's cell (clipped to the root cube). Each cell
+// is one contiguous Morton key range: two binary searches give its sorted
+// positions, the P1 prefix sums its compacted range. Ranges are sorted and
+// joined where contiguous.
+
+__device__ __forceinline__ uint32_t lower_bound_u64(const uint64_t* a, uint32_t n, uint64_t x) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+constexpr int HALO_LEAVES = 8;  // leaves per 256-thread block (32 threads each)
+
+__global__ __launch_bounds__(256) void halo_kernel(Plan P) {
+    __shared__ uint2 s_r[HALO_LEAVES][HALO];
+    const int tid = threadIdx.x, grp = tid >> 5, g = tid & 31;
+    const uint32_t nl = P.ctr->n_leaves;
+    for (uint32_t base = blockIdx.x * HALO_LEAVES; base < nl; base += gridDim.x * HALO_LEAVES) {
+        const uint32_t t = base + grp;
+        if (t < nl && g < HALO) {
+            const int d = (int)P.leaf_level[t];
+            const uint64_t pre = P.leaf_prefix[t];
+            const int64_t cx = compact3(pre), cy = compact3(pre >> 1), cz = compact3(pre >> 2);
+            const int64_t nx = cx + (g % 3) - 1, ny = cy + (g / 3) % 3 - 1, nz = cz + g / 9 - 1;
+            const int64_t side = (int64_t)1 << d;
+            uint2 r = make_uint2(0u, 0u);
+            if (nx >= 0 && ny >= 0 && nz >= 0 && nx < side && ny < side && nz < side) {
+                const int sh = 3 * (MORTON_BITS - d);
+                const uint64_t klo = morton3((uint32_t)nx, (uint32_t)ny, (uint32_t)nz) << sh;
+                const uint64_t khi = klo + (1ull << sh);
+                const uint32_t lo = lower_bound_u64(P.keys_a, P.n, klo);
+                const uint32_t hi = lower_bound_u64(P.keys_a, P.n, khi);
+                r = make_uint2(P.p1pos[lo], P.p1pos[hi]);
+            }
+            s_r[grp][g] = r;
+        }
+        __syncthreads();
+        if (t < nl && g == 0) {
+            // insertion sort of the non-empty ranges, in place (slot j <= i)
+            uint2* v = s_r[grp];
+            int m = 0;
+            for (int i = 0; i < HALO; ++i) {
+                const uint2 r = v[i];
+                if (r.y > r.x) {
+                    int j = m++;
+                    while (j > 0 && v[j - 1].x > r.x) { v[j] = v[j - 1]; --j; }
+                    v[j] = r;
+                }
+            }
+            int out = 0;
+            uint32_t tot = 0;
+            for (int i = 0; i < m; ++i) {
+                if (out > 0 && v[i].x == P.leaf_ranges[(size_t)t * HALO + out - 1].y) {
+                    P.leaf_ranges[(size_t)t * HALO + out - 1].y = v[i].y;
+                } else {
+                    P.leaf_ranges[(size_t)t * HALO + out] = v[i];
+                    ++out;
+                }
+                tot += v[i].y - v[i].x;
+            }
+            P.leaf_nr[t] = (uint32_t)out;
+            P.leaf_ncand[t] = tot;
+        }
+        __syncthreads();
+    }
+}
+
+void launch_halo(const Plan& P, hipStream_t st) {
+    unsigned blocks = (P.n + HALO_LEAVES - 1) / HALO_LEAVES;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(halo_kernel, dim3(blocks), dim3(256), 0, st, P);
+}
+
+// ---------------------------------------------------------------- kNN plan
+//
+// One workgroup. Work items are (leaf, tile of up to KNN_TQ queries,
+// candidate chunk). Leaves whose candidate set exceeds the chunk length are
+// split into chunks whose partial top-k lists are merged afterwards; the chunk
+// length doubles until the partial lists and items fit their workspace.
+
+constexpr int PLAN_BLOCK = 1024;
+
+__global__ __launch_bounds__(PLAN_BLOCK) void knn_plan_kernel(Plan P) {
+    __shared__ unsigned long long s_red[PLAN_BLOCK / 64][3];
+    __shared__ uint32_t s_scan[PLAN_BLOCK / 64 + 1];
+    __shared__ uint32_t s_cc, s_done, s_carry_l, s_carry_i;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t nl = P.ctr->n_leaves;
+    if (tid == 0) { s_cc = KNN_CC0; s_done = 0; }
+    __syncthreads();
+    for (int iter = 0; iter < 40; ++iter) {
+        const uint32_t cc = s_cc;
+        unsigned long long lists = 0, items = 0, pairs = 0;
+        for (uint32_t t = tid; t < nl; t += PLAN_BLOCK) {
+            const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
+            const uint32_t n1 = qe - qb, nc = P.leaf_ncand[t];
+            if (n1 == 0) continue;
+            uint32_t nch = (nc + cc - 1) / cc;
+            if (nch < 1) nch = 1;
+            if (nch > KNN_NCH_MAX) nch = KNN_NCH_MAX;
+            if (nch > 1) lists += (unsigned long long)n1 * nch;
+            items += (unsigned long long)((n1 + KNN_TQ - 1) / KNN_TQ) * nch;
+            pairs += (unsigned long long)n1 * (nc - 1);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            lists += __shfl_xor(lists, o, 64);
+            items += __shfl_xor(items, o, 64);
+            pairs += __shfl_xor(pairs, o, 64);
+        }
+        if (lane == 0) { s_red[wave][0] = lists; s_red[wave][1] = items; s_red[wave][2] = pairs; }
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long L = 0, I = 0, W = 0;
+            for (int w = 0; w < PLAN_BLOCK / 64; ++w) { L += s_red[w][0]; I += s_red[w][1]; W += s_red[w][2]; }
+            if ((L <= P.plist_max && I <= P.items_max) || cc >= 0x40000000u) {
+                s_done = 1;
+                P.ctr->pairs = W;
+            } else {
+                s_cc = cc * 2;
+            }
+        }
+        __syncthreads();
+        if (s_done) break;
+    }
+    const uint32_t cc = s_cc;
+    // exclusive offsets of partial lists and items, leaf by leaf
+    if (tid == 0) { s_carry_l = 0; s_carry_i = 0; }
+    __syncthreads();
+    for (uint32_t t0 = 0; t0 < nl; t0 += PLAN_BLOCK) {
+        const uint32_t t = t0 + tid;
+        uint32_t nl1 = 0, ni = 0, nch = 1, qb = 0, qe = 0, nc = 0;
+        if (t < nl) {
+            qb = P.p1pos[P.leaf_begin[t]];
+            qe = P.p1pos[P.leaf_begin[t + 1]];
+            nc = P.leaf_ncand[t];
+            const uint32_t n1 = qe - qb;
+            nch = (nc + cc - 1) / cc;
+            if (nch < 1) nch = 1;
+            if (nch > KNN_NCH_MAX) nch = KNN_NCH_MAX;
+            if (n1 == 0) nch = 1;
+            nl1 = (nch > 1) ? n1 * nch : 0u;
+            ni = n1 ? ((n1 + KNN_TQ - 1) / KNN_TQ) * nch : 0u;
+        }
+        uint32_t totl, toti;
+        const uint32_t exl = block_excl_scan(nl1, s_scan, &totl);
+        const uint32_t exi = block_excl_scan(ni, s_scan, &toti);
+        const uint32_t offl = s_carry_l + exl, offi = s_carry_i + exi;
+        if (t < nl) {
+            P.leaf_nch[t] = nch;
+            P.leaf_cc[t] = (nc + nch - 1) / nch;
+            P.leaf_plist[t] = offl;
+            uint32_t w = offi;
+            for (uint32_t q0 = qb; q0 < qe; q0 += KNN_TQ) {
+                const uint32_t q1 = min(qe, q0 + KNN_TQ);
+                for (uint32_t c = 0; c < nch; ++c) P.items[w++] = KnnItem{t, q0, q1, c};
+            }
+        }
+        __syncthreads();
+        if (tid == 0) { s_carry_l += totl; s_carry_i += toti; }
+        __syncthreads();
+    }
+    if (tid == 0) P.ctr->n_items = s_carry_i;
+}
+
+void launch_knn_plan(const Plan& P, hipStream_t st) {
+    hipLaunchKernelGGL(knn_plan_kernel, dim3(1), dim3(PLAN_BLOCK), 0, st, P);
+}
+
+}  // namespace gdn

@@ -1,0 +1,138 @@
+"""HIP path vs the CPU oracle, element by element, through the C ABI.
+
+Keys, order, leaves, voxel sizes, occupancy, P1, kNN index sets and squared
+distances, r^2_K and P2 must be bit-exact; densities and medians agree to FP64
+rounding; scores to 1e-5 relative; keep labels may differ only for points whose
+score is within 1e-5 of their leaf's cut.
+"""
+import numpy as np
+import pytest
+
+from paper_2512_10386_amd import synth
+from tests.parity import compare, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def den():
+    from paper_2512_10386_amd.binding import Denoiser
+    d = Denoiser(0)
+    yield d
+    d.close()
+
+
+def check(den, oracle, xyz, **params):
+    print(f"[parity] n={len(xyz)} params={params}", flush=True)
+    den.set_params(**params)
+    g = run_gpu(den, xyz)
+    ref = oracle.denoise(xyz, **params)
+    st = compare(g, ref)
+    print(f"[parity] ok n={len(xyz)} leaves={ref['n_leaves']} pairs={ref['pairs']} {st}", flush=True)
+    return g, ref
+
+
+def test_sphere_plane_20k_k16(den, oracle):
+    xyz, _, p = synth.make("sphere_plane_20k")
+    check(den, oracle, xyz, **p)
+
+
+def test_lidar_120k_k32_full_size(den, oracle):
+    xyz, _, p = synth.make("lidar_120k")
+    g, ref = check(den, oracle, xyz, **p)
+    assert ref["n_leaves"] > 100 and ref["pairs"] > 1e8
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 4095, 4096, 4097, 12345])
+def test_ragged_sizes(den, oracle, n):
+    xyz, _ = synth.sphere_plane(seed=100 + n, n_sphere=max(n * 6 // 10, 1), n_plane=n * 2 // 10,
+                                n_out=n - max(n * 6 // 10, 1) - n * 2 // 10)
+    assert len(xyz) == n
+    check(den, oracle, xyz, k=4, leaf_cap=64, min_vox_count=1)
+
+
+def test_empty_frame(den, oracle):
+    g = run_gpu(den, np.zeros((0, 3), np.float32))
+    assert g["n_kept"] == 0
+
+
+@pytest.mark.parametrize("k", [1, 8, 12, 33, 64])
+def test_k_range(den, oracle, k):
+    xyz, _ = synth.sphere_plane(seed=200 + k, n_sphere=3000, n_plane=1000, n_out=1000)
+    check(den, oracle, xyz, k=k, leaf_cap=256, min_vox_count=2)
+
+
+def test_fewer_points_than_k(den, oracle):
+    xyz, _ = synth.uniform_cube(5, 20)
+    check(den, oracle, xyz, k=32, leaf_cap=8, min_vox_count=1)
+
+
+def test_duplicates_oversize_leaf_global_hash(den, oracle):
+    xyz, _ = synth.uniform_cube(6, 3000)
+    dup = np.repeat(xyz[:1], 3000, axis=0)  # > 2048 points in one depth-21 leaf
+    check(den, oracle, np.concatenate([xyz, dup]), k=8, leaf_cap=64, min_vox_count=2)
+
+
+def test_all_points_identical(den, oracle):
+    xyz = np.tile(np.array([[0.25, -1.0, 3.0]], np.float32), (500, 1))
+    check(den, oracle, xyz, k=4, leaf_cap=16, min_vox_count=2, eps=1e-6)
+
+
+def test_flat_plane_single_voxel_leaves(den, oracle):
+    xyz, _ = synth.uniform_cube(7, 4000)
+    xyz[:, 2] = 0.5
+    check(den, oracle, xyz, k=6, leaf_cap=128, min_vox_count=3)
+
+
+def test_cap_one_and_depth_limit(den, oracle):
+    xyz, _ = synth.uniform_cube(8, 600)
+    check(den, oracle, xyz, k=4, leaf_cap=1, min_vox_count=1)
+    S = float((xyz.max(0).astype(np.float64) - xyz.min(0)).max())
+    check(den, oracle, xyz, k=4, leaf_cap=4, min_vox_count=1, min_leaf_side=S / 16.0)
+
+
+def test_parameter_variety(den, oracle):
+    xyz, _ = synth.sphere_plane(seed=9, n_sphere=6000, n_plane=2000, n_out=2000)
+    check(den, oracle, xyz, k=10, leaf_cap=300, beta=2.0, min_vox_count=3, rho_percentile=20.0,
+          alpha=2.0, sigma=0.5, eps=1e-9, keep_ratio=0.5)
+    check(den, oracle, xyz, k=10, leaf_cap=300, rho_percentile=100.0, alpha=0.0, keep_ratio=1.0)
+
+
+def test_big_leaves_chunked_candidates(den, oracle):
+    xyz, _ = synth.uniform_cube(10, 60000)
+    g, ref = check(den, oracle, xyz, k=16, leaf_cap=2048, min_vox_count=1)
+    assert ref["leaf_ncand"].max() > 4096  # forces the chunked path + merge
+
+
+def test_deterministic_rerun(den, oracle):
+    xyz, _, p = synth.make("sphere_plane_20k")
+    den.set_params(**p)
+    a = run_gpu(den, xyz)
+    b = run_gpu(den, xyz)
+    for f in ["keep", "score", "stage", "kept_idx", "nbr_idx", "score64"]:
+        assert np.array_equal(a[f], b[f]), f
+
+
+def test_nonfinite_input_sets_status(den):
+    xyz, _ = synth.uniform_cube(11, 1000)
+    xyz[10, 1] = np.nan
+    xyz[20, 0] = np.inf
+    den.set_params(k=4, leaf_cap=64)
+    g = run_gpu(den, xyz)
+    assert g["status"] & 1
+
+
+def test_errors_are_reported(den):
+    import torch
+    from paper_2512_10386_amd.binding import GdnError, gdn_denoise, make_params, GDN_EINVAL, GDN_ENOMEM
+    x = torch.zeros((100, 3), device="cuda")
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    out = torch.empty(100, dtype=torch.uint8, device="cuda")
+    with pytest.raises(GdnError) as e:
+        gdn_denoise(den.ctx, make_params(k=4), x.data_ptr(), 100, ws.data_ptr(), 1024, out.data_ptr(),
+                    out.data_ptr(), 0, out.data_ptr(), out.data_ptr(), 0)
+    assert e.value.status == GDN_ENOMEM
+    with pytest.raises(GdnError) as e:
+        gdn_denoise(den.ctx, make_params(keep_ratio=2.0), x.data_ptr(), 100, ws.data_ptr(), 1024,
+                    out.data_ptr(), out.data_ptr(), 0, out.data_ptr(), out.data_ptr(), 0)
+    assert e.value.status == GDN_EINVAL
