@@ -1,0 +1,191 @@
+#!/usr/bin/env python
+"""Throughput of the denoiser's hot path on one MI355X.
+
+One step = one whole pass of the pipeline (Morton sort, octree, voxel filter,
+kNN, density, percentile/median, score, top-lambda, compaction) over one
+synthetic 120k-point LiDAR frame at k=32, leaf cap 1024, with the input already
+resident in HBM. Prints ONE JSON line on stdout; progress goes to stderr.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3      # MI355X: 256 CU x 2.4 GHz x 256 flop/clk (packed FMA)
+FP32_EXACT_CEILING_TOPS = 39.3       # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, one op per lane-cycle
+FLOPS_PER_PAIR = 8                   # 3 sub + 3 mul + 2 add per (query, candidate) pair
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def knn_traffic(knn_ms_launch):
+    """HBM bytes per kNN launch from the committed PMC summary, if it was taken
+    on the current kernel source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "knn_lidar_120k_traffic.json")
+    src = os.path.join(ROOT, "paper_2512_10386_amd", "csrc", "knn.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("knn_source_sha256") != sha:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(xyz, params, budget_s=12.0):
+    """The CPU oracle, as it stands, on the host cores: whole frames until the
+    time budget is used (at least one)."""
+    from oracle import oracle as O
+    O.build()
+    reps, t0 = 0, time.perf_counter()
+    threads = 1
+    while True:
+        r = O.denoise(xyz, **params)
+        threads = r["threads"]
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or reps >= 30:
+            break
+    return {"value": round(xyz.shape[0] * reps / el / 1e6, 4), "unit": "Mpoints/s",
+            "cores": int(threads), "kind": "oracle",
+            "sample": f"{reps} full frames of the same workload ({xyz.shape[0]} points each), "
+                      f"{el:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="lidar_120k")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(frames are independent; see the design notes on sharding).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2512_10386_amd import synth
+    from paper_2512_10386_amd.binding import Denoiser, gdn_set_timing, gdn_timing
+
+    xyz, label, params = synth.make(args.workload)
+    n = xyz.shape[0]
+    dev = torch.device("cuda", 0)
+    x = torch.from_numpy(xyz).to(dev)
+    den = Denoiser(0, **params)
+    out = den(x)
+    torch.cuda.synchronize()
+    counts = den.dump("COUNTS", n).cpu().numpy()
+    status = int(den.dump("STATUS", n).cpu().numpy()[0])
+    n_leaves, n_p1, pairs, n_kept = (int(c) for c in counts)
+    log(f"[bench] {args.workload}: n={n} leaves={n_leaves} |P1|={n_p1} pairs={pairs} kept={n_kept} status={status}")
+    if status != 0:
+        log("[bench] device status word is non-zero")
+
+    if args.copy_calib_mib:
+        a = torch.empty(args.copy_calib_mib << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        den(x, out)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup {args.warmup} done")
+
+    # timed region: K back-to-back frames
+    gdn_set_timing(den.ctx, True)
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    t_start.record()
+    for _ in range(args.steps):
+        den(x, out)
+    t_end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_total = t_start.elapsed_time(t_end)
+    ms_per_step = ms_total / args.steps
+    per_call = [gdn_timing(den.ctx, b) for b in range(min(args.steps, 256))]
+    knn_ms = statistics.fmean(k for _, k in per_call)
+    call_ms = statistics.fmean(t for t, _ in per_call)
+    log(f"[bench] timed {args.steps} steps: {ms_per_step:.4f} ms/step (host wall {wall:.3f} s), "
+        f"kNN kernel {knn_ms:.4f} ms, call {call_ms:.4f} ms")
+    gdn_set_timing(den.ctx, False)
+
+    # frame latency: each frame submitted alone and waited for
+    lat = []
+    for _ in range(args.steps):
+        s = time.perf_counter()
+        den(x, out)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - s) * 1e3)
+    lat.sort()
+    p50 = lat[len(lat) // 2]
+    p99 = lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]
+    log(f"[bench] latency p50 {p50:.4f} ms p99 {p99:.4f} ms")
+
+    flops = pairs * FLOPS_PER_PAIR
+    achieved = flops / (knn_ms * 1e-3) / 1e12
+    roofline = {
+        "kernel": "knn_kernel<32>",
+        "bound": "alu",
+        "achieved": round(achieved, 3),
+        "peak": FP32_VECTOR_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+        "traffic": knn_traffic(knn_ms),
+        "pairs_per_launch": pairs,
+        "flops_per_pair": FLOPS_PER_PAIR,
+        "kernel_ms": round(knn_ms, 5),
+        "exact_fp32_ceiling": FP32_EXACT_CEILING_TOPS,
+        "frac_of_exact_ceiling": round(achieved / FP32_EXACT_CEILING_TOPS, 4),
+    }
+
+    value = n / (ms_per_step * 1e-3) / 1e6
+    rec = {
+        "metric": "Mpoints/s denoised at k=32 (kNN+score) + p99 frame latency; batched vs plain",
+        "value": round(value, 4),
+        "unit": "Mpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "points": n, "k": params["k"],
+                   "leaf_cap": params["leaf_cap"], "frames_per_step": 1, "path": "plain single-frame",
+                   "score_dtype": "f64", "leaves": n_leaves, "p1_points": n_p1, "kept": n_kept},
+        "latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4)},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        rec["cpu_baseline"] = cpu_baseline(xyz, params)
+        log(f"[bench] cpu baseline {rec['cpu_baseline']}")
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

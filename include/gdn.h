@@ -116,6 +116,15 @@ enum {
  * rows not defined for a point are filled with the padding values). */
 gdn_status gdn_debug_dump(gdn_ctx *ctx, int what, void *dst, size_t dst_bytes, void *stream);
 
+/* Profiling aid. With timing enabled, each gdn_denoise records HIP events on
+ * its stream (call start, kNN kernel start, kNN kernel end, call end) into a
+ * ring of the last 256 calls. gdn_timing reads call `back` (0 = the latest),
+ * waiting for its events; it returns the whole call's and the brute-force kNN
+ * kernel's elapsed milliseconds. Enabling creates the events (no device
+ * memory); disabling destroys them. */
+gdn_status gdn_set_timing(gdn_ctx *ctx, int enable);
+gdn_status gdn_timing(gdn_ctx *ctx, int64_t back, float *total_ms, float *knn_ms);
+
 const char *gdn_status_string(gdn_status s);
 /* Message of the last failed call on ctx ("" if none). */
 const char *gdn_last_error(gdn_ctx *ctx);

@@ -57,12 +57,14 @@ def lib():
         L.gdn_workspace_size.argtypes = [vp, C.POINTER(gdn_params), i64, C.POINTER(sz)]
         L.gdn_denoise.argtypes = [vp, C.POINTER(gdn_params), vp, i64, vp, sz, vp, vp, vp, vp, vp, vp]
         L.gdn_debug_dump.argtypes = [vp, C.c_int, vp, sz, vp]
+        L.gdn_set_timing.argtypes = [vp, C.c_int]
+        L.gdn_timing.argtypes = [vp, i64, C.POINTER(C.c_float), C.POINTER(C.c_float)]
         L.gdn_status_string.argtypes = [C.c_int]
         L.gdn_status_string.restype = C.c_char_p
         L.gdn_last_error.argtypes = [vp]
         L.gdn_last_error.restype = C.c_char_p
         for f in ("gdn_default_params", "gdn_create", "gdn_workspace_size", "gdn_denoise",
-                  "gdn_debug_dump"):
+                  "gdn_debug_dump", "gdn_set_timing", "gdn_timing"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -109,6 +111,17 @@ def gdn_denoise(ctx, p, xyz, n, workspace, workspace_bytes, keep, score, stage,
 
 def gdn_debug_dump(ctx, what, dst, dst_bytes, stream) -> None:
     _check(ctx, lib().gdn_debug_dump(ctx, what, dst, dst_bytes, stream))
+
+
+def gdn_set_timing(ctx, enable: bool) -> None:
+    _check(ctx, lib().gdn_set_timing(ctx, 1 if enable else 0))
+
+
+def gdn_timing(ctx, back: int = 0):
+    """(whole-call ms, kNN-kernel ms) of a recent timed call."""
+    t, k = C.c_float(), C.c_float()
+    _check(ctx, lib().gdn_timing(ctx, back, C.byref(t), C.byref(k)))
+    return t.value, k.value
 
 
 def make_params(**kw) -> gdn_params:

@@ -3,9 +3,16 @@
 #include <cmath>
 #include <new>
 #include <string>
+#include <vector>
 
-#include "../../include/gdn.h"
+#include "gdn.h"
 #include "kernels.hpp"
+
+// Events of one timed call: start, kNN start, kNN end, end.
+constexpr int TIMING_RING = 256;
+struct CallEvents {
+    hipEvent_t ev[4];
+};
 
 struct gdn_ctx {
     int device = 0;
@@ -13,6 +20,9 @@ struct gdn_ctx {
     std::string err;
     gdn::Plan last{};
     bool has_last = false;
+    bool timing = false;
+    std::vector<CallEvents> ring;
+    int64_t timed_calls = 0;
 };
 
 namespace gdn {
@@ -84,6 +94,7 @@ gdn::Plan make_plan(uint32_t n, int k, char* base) {
     P.nbr = (uint32_t*)take(4 * N * k);
     P.nbr_d2 = (float*)take(4 * N * k);
     P.r2k = (float*)take(4 * N);
+    P.tau_c = (float*)take(4 * N);
     P.rho_c = (double*)take(8 * N);
     P.r64_c = (double*)take(8 * N);
     P.afac_c = (double*)take(8 * N);
@@ -93,6 +104,7 @@ gdn::Plan make_plan(uint32_t n, int k, char* base) {
     P.rho_o = (double*)take(8 * N);
     P.gpow_o = (double*)take(8 * N);
     P.items = (KnnItem*)take(sizeof(KnnItem) * (size_t)P.items_max);
+    P.tile_done = (uint32_t*)take(4 * (size_t)P.items_max);
     P.plist = (uint64_t*)take(8 * (size_t)P.plist_max * k);
     P.bytes = off;
     return P;
@@ -180,7 +192,55 @@ gdn_status gdn_create(gdn_ctx** out, int device) {
     return GDN_OK;
 }
 
-void gdn_destroy(gdn_ctx* ctx) { delete ctx; }
+static void free_events(gdn_ctx* c) {
+    for (auto& ce : c->ring)
+        for (auto& e : ce.ev)
+            if (e) (void)hipEventDestroy(e);
+    c->ring.clear();
+}
+
+void gdn_destroy(gdn_ctx* ctx) {
+    if (!ctx) return;
+    DeviceGuard guard(ctx->device);
+    free_events(ctx);
+    delete ctx;
+}
+
+gdn_status gdn_set_timing(gdn_ctx* ctx, int enable) {
+    if (!ctx) return GDN_EINVAL;
+    DeviceGuard guard(ctx->device);
+    if (!enable) {
+        free_events(ctx);
+        ctx->timing = false;
+        return GDN_OK;
+    }
+    if (ctx->ring.empty()) {
+        ctx->ring.resize(TIMING_RING);
+        for (auto& ce : ctx->ring)
+            for (auto& e : ce.ev)
+                if (hipEventCreate(&e) != hipSuccess) {
+                    free_events(ctx);
+                    return fail(ctx, GDN_EHIP, "hipEventCreate failed");
+                }
+    }
+    ctx->timing = true;
+    ctx->timed_calls = 0;
+    return GDN_OK;
+}
+
+gdn_status gdn_timing(gdn_ctx* ctx, int64_t back, float* total_ms, float* knn_ms) {
+    if (!ctx || !total_ms || !knn_ms) return GDN_EINVAL;
+    if (!ctx->timing) return fail(ctx, GDN_EINVAL, "timing is not enabled");
+    if (back < 0 || back >= ctx->timed_calls || back >= TIMING_RING)
+        return fail(ctx, GDN_EINVAL, "no such timed call");
+    DeviceGuard guard(ctx->device);
+    const CallEvents& ce = ctx->ring[(size_t)((ctx->timed_calls - 1 - back) % TIMING_RING)];
+    if (hipEventSynchronize(ce.ev[3]) != hipSuccess) return fail(ctx, GDN_EHIP, "hipEventSynchronize failed");
+    if (hipEventElapsedTime(total_ms, ce.ev[0], ce.ev[3]) != hipSuccess ||
+        hipEventElapsedTime(knn_ms, ce.ev[1], ce.ev[2]) != hipSuccess)
+        return fail(ctx, GDN_EHIP, "hipEventElapsedTime failed");
+    return GDN_OK;
+}
 
 gdn_status gdn_workspace_size(gdn_ctx* ctx, const gdn_params* p, int64_t n, size_t* bytes) {
     std::string why;
@@ -217,6 +277,12 @@ gdn_status gdn_denoise(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int6
     const gdn::Plan P = make_plan((uint32_t)n, p->k, (char*)workspace);
     if (workspace_bytes < P.bytes) return fail(ctx, GDN_ENOMEM, "workspace too small");
     const gdn::Params prm = to_params(p);
+    CallEvents* ce = nullptr;
+    if (ctx->timing) {
+        ce = &ctx->ring[(size_t)(ctx->timed_calls % TIMING_RING)];
+        ++ctx->timed_calls;
+        (void)hipEventRecord(ce->ev[0], st);
+    }
 
     gdn::launch_zero(P, st);
     gdn::launch_bbox(P, xyz, st);
@@ -228,12 +294,16 @@ gdn_status gdn_denoise(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int6
     gdn::launch_p1_compact(P, st);
     gdn::launch_halo(P, st);
     gdn::launch_knn_plan(P, st);
+    gdn::launch_knn_bound(P, prm.k, ctx->num_cus, st);
+    if (ce) (void)hipEventRecord(ce->ev[1], st);
     gdn::launch_knn(P, prm.k, ctx->num_cus, st);
+    if (ce) (void)hipEventRecord(ce->ev[2], st);
     gdn::launch_density(P, prm, xyz, st);
     gdn::launch_leaf_select(P, prm, st);
     gdn::launch_score(P, prm, xyz, st);
     gdn::launch_topl(P, prm, st);
     gdn::launch_outputs(P, keep, score, stage, kept_idx, n_kept, st);
+    if (ce) (void)hipEventRecord(ce->ev[3], st);
 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(ctx, GDN_EHIP, hipGetErrorString(e));

@@ -17,9 +17,8 @@ constexpr int SORT_PASSES = 8;                // 8-bit digits over the 63-bit ke
 constexpr int SCAN_BLOCK = 256;
 constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
-constexpr int KNN_TQ = 256;                   // queries per kNN work item
-constexpr int KNN_CT = 1024;                  // candidates per LDS tile
-constexpr int KNN_CC0 = 4096;                 // initial candidate chunk
+constexpr int KNN_TQ = 64;                    // queries per kNN work item (one wave)
+constexpr int KNN_CC0 = 2048;                 // initial candidate chunk
 constexpr int KNN_NCH_MAX = 32;               // max candidate chunks per leaf
 constexpr int HALO = 27;
 constexpr int VOX_BLOCK = 256;
@@ -60,8 +59,10 @@ struct FrameConst {
     double scale;
 };
 
+// One kNN work item: queries [q0, q1) of leaf `leaf` against candidate chunk
+// `chunk`; `grp` indexes the arrival counter shared by the chunks of a tile.
 struct KnnItem {
-    uint32_t leaf, q0, q1, chunk;
+    uint32_t leaf, q0, q1, chunk, grp, pad;
 };
 
 // Method parameters as the kernels use them.
@@ -125,6 +126,7 @@ struct Plan {
     uint32_t* nbr;            // [n][k] original indices
     float* nbr_d2;            // [n][k]
     float* r2k;               // [n]
+    float* tau_c;             // [n] per-query upper bound of r^2_K (-1: none)
     double* rho_c;            // [n]
     double* r64_c;            // [n]
     double* afac_c;           // [n] (rho_i / (rho_med^2 + eps))^(alpha/2)
@@ -135,6 +137,7 @@ struct Plan {
     double* gpow_o;           // [n] original order rho^(alpha/2)
     // kNN work
     KnnItem* items;           // [items_max]
+    uint32_t* tile_done;      // [items_max] chunk arrivals per query tile
     uint32_t items_max;
     uint64_t* plist;          // [plist_max][k] partial top-k keys
     uint32_t plist_max;

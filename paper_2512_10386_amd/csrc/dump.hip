@@ -1,6 +1,6 @@
 // Copies of the last frame's intermediates, mapped back to original point
 // order, for the per-stage parity checks.
-#include "../../include/gdn.h"
+#include "gdn.h"
 #include "kernels.hpp"
 
 namespace gdn {

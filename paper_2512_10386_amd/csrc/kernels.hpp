@@ -19,7 +19,8 @@ void launch_p1_compact(const Plan& P, hipStream_t st);
 void launch_halo(const Plan& P, hipStream_t st);
 void launch_knn_plan(const Plan& P, hipStream_t st);
 
-// knn.hip: brute-force kNN over leaf + halo candidates, partial-list merge
+// knn.hip: brute-force kNN over leaf + halo candidates (chunk merge included)
+void launch_knn_bound(const Plan& P, int k, int num_cus, hipStream_t st);
 void launch_knn(const Plan& P, int k, int num_cus, hipStream_t st);
 
 // score.hip: density, percentile/median, score, top-lambda, outputs

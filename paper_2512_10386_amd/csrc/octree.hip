@@ -332,15 +332,16 @@ void launch_halo(const Plan& P, hipStream_t st) {
 //
 // One workgroup. Work items are (leaf, tile of up to KNN_TQ queries,
 // candidate chunk). Leaves whose candidate set exceeds the chunk length are
-// split into chunks whose partial top-k lists are merged afterwards; the chunk
-// length doubles until the partial lists and items fit their workspace.
+// split into chunks whose partial top-k lists are merged by the last chunk of
+// each tile to finish; the chunk length doubles until the partial lists and
+// items fit their workspace.
 
 constexpr int PLAN_BLOCK = 1024;
 
 __global__ __launch_bounds__(PLAN_BLOCK) void knn_plan_kernel(Plan P) {
     __shared__ unsigned long long s_red[PLAN_BLOCK / 64][3];
     __shared__ uint32_t s_scan[PLAN_BLOCK / 64 + 1];
-    __shared__ uint32_t s_cc, s_done, s_carry_l, s_carry_i;
+    __shared__ uint32_t s_cc, s_done, s_carry_l, s_carry_c, s_carry_u, s_chunked_items;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t nl = P.ctr->n_leaves;
     if (tid == 0) { s_cc = KNN_CC0; s_done = 0; }
@@ -380,12 +381,34 @@ __global__ __launch_bounds__(PLAN_BLOCK) void knn_plan_kernel(Plan P) {
         if (s_done) break;
     }
     const uint32_t cc = s_cc;
-    // exclusive offsets of partial lists and items, leaf by leaf
-    if (tid == 0) { s_carry_l = 0; s_carry_i = 0; }
-    __syncthreads();
+    // Items of chunked leaves (the heaviest) come first in the queue, then the
+    // rest; both classes keep leaf order. Pass A counts the chunked items.
+    {
+        unsigned long long ic = 0;
+        for (uint32_t t = tid; t < nl; t += PLAN_BLOCK) {
+            const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
+            const uint32_t n1 = qe - qb, nc = P.leaf_ncand[t];
+            uint32_t nch = (nc + cc - 1) / cc;
+            if (nch > KNN_NCH_MAX) nch = KNN_NCH_MAX;
+            if (n1 > 0 && nch > 1) ic += (unsigned long long)((n1 + KNN_TQ - 1) / KNN_TQ) * nch;
+        }
+        for (int o = 32; o > 0; o >>= 1) ic += __shfl_xor(ic, o, 64);
+        if (lane == 0) s_red[wave][0] = ic;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long T = 0;
+            for (int w = 0; w < PLAN_BLOCK / 64; ++w) T += s_red[w][0];
+            s_chunked_items = (uint32_t)T;
+            s_carry_l = 0;
+            s_carry_c = 0;
+            s_carry_u = 0;
+        }
+        __syncthreads();
+    }
+    const uint32_t n_chunked_items = s_chunked_items;
     for (uint32_t t0 = 0; t0 < nl; t0 += PLAN_BLOCK) {
         const uint32_t t = t0 + tid;
-        uint32_t nl1 = 0, ni = 0, nch = 1, qb = 0, qe = 0, nc = 0;
+        uint32_t nl1 = 0, nic = 0, niu = 0, nch = 1, qb = 0, qe = 0, nc = 0;
         if (t < nl) {
             qb = P.p1pos[P.leaf_begin[t]];
             qe = P.p1pos[P.leaf_begin[t + 1]];
@@ -395,28 +418,31 @@ __global__ __launch_bounds__(PLAN_BLOCK) void knn_plan_kernel(Plan P) {
             if (nch < 1) nch = 1;
             if (nch > KNN_NCH_MAX) nch = KNN_NCH_MAX;
             if (n1 == 0) nch = 1;
+            const uint32_t ni = n1 ? ((n1 + KNN_TQ - 1) / KNN_TQ) * nch : 0u;
             nl1 = (nch > 1) ? n1 * nch : 0u;
-            ni = n1 ? ((n1 + KNN_TQ - 1) / KNN_TQ) * nch : 0u;
+            if (nch > 1) nic = ni; else niu = ni;
         }
-        uint32_t totl, toti;
+        uint32_t totl, totc, totu;
         const uint32_t exl = block_excl_scan(nl1, s_scan, &totl);
-        const uint32_t exi = block_excl_scan(ni, s_scan, &toti);
-        const uint32_t offl = s_carry_l + exl, offi = s_carry_i + exi;
+        const uint32_t exc = block_excl_scan(nic, s_scan, &totc);
+        const uint32_t exu = block_excl_scan(niu, s_scan, &totu);
         if (t < nl) {
             P.leaf_nch[t] = nch;
             P.leaf_cc[t] = (nc + nch - 1) / nch;
-            P.leaf_plist[t] = offl;
-            uint32_t w = offi;
+            P.leaf_plist[t] = s_carry_l + exl;
+            uint32_t w = (nch > 1) ? s_carry_c + exc : n_chunked_items + s_carry_u + exu;
             for (uint32_t q0 = qb; q0 < qe; q0 += KNN_TQ) {
                 const uint32_t q1 = min(qe, q0 + KNN_TQ);
-                for (uint32_t c = 0; c < nch; ++c) P.items[w++] = KnnItem{t, q0, q1, c};
+                const uint32_t grp = w;
+                P.tile_done[grp] = 0u;
+                for (uint32_t c = 0; c < nch; ++c) P.items[w++] = KnnItem{t, q0, q1, c, grp, 0u};
             }
         }
         __syncthreads();
-        if (tid == 0) { s_carry_l += totl; s_carry_i += toti; }
+        if (tid == 0) { s_carry_l += totl; s_carry_c += totc; s_carry_u += totu; }
         __syncthreads();
     }
-    if (tid == 0) P.ctr->n_items = s_carry_i;
+    if (tid == 0) P.ctr->n_items = s_carry_c + s_carry_u;
 }
 
 void launch_knn_plan(const Plan& P, hipStream_t st) {
