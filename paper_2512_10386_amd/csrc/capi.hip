@@ -84,6 +84,7 @@ gdn::Plan make_plan(uint32_t n, int k, char* base) {
     P.leaf_nch = (uint32_t*)take(4 * N);
     P.leaf_cc = (uint32_t*)take(4 * N);
     P.leaf_plist = (uint32_t*)take(4 * N);
+    P.leaf_item = (uint32_t*)take(4 * N);
     P.leaf_rho_med = (double*)take(8 * N);
     P.leaf_r2cut = (float*)take(4 * N);
     P.leaf_m = (uint32_t*)take(4 * N);

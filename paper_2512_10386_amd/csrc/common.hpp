@@ -17,7 +17,7 @@ constexpr int SORT_PASSES = 8;                // 8-bit digits over the 63-bit ke
 constexpr int SCAN_BLOCK = 256;
 constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
-constexpr int KNN_TQ = 64;                    // queries per kNN work item (one wave)
+constexpr int KNN_TQ = 16;                    // queries per kNN work item (one wave)
 constexpr int KNN_CC0 = 2048;                 // initial candidate chunk
 constexpr int KNN_NCH_MAX = 32;               // max candidate chunks per leaf
 constexpr int HALO = 27;
@@ -115,6 +115,7 @@ struct Plan {
     uint32_t* leaf_nch;       // [n] candidate chunks
     uint32_t* leaf_cc;        // [n] chunk length
     uint32_t* leaf_plist;     // [n] first partial list of the leaf
+    uint32_t* leaf_item;      // [n] queue index of the leaf's first kNN item
     double* leaf_rho_med;     // [n]
     float* leaf_r2cut;        // [n]
     uint32_t* leaf_m;         // [n]

@@ -1,26 +1,32 @@
 // Leaf-local brute-force kNN with halo candidates (Sec. 3: N_K(i), d_ij and
 // r_K,i on the voxel-filtered set P1).
 //
-// One wave per work item (64 queries, one per lane); the candidate stream
-// has wave-uniform addresses and comes through the scalar cache. Squared distances are fp32 (dx*dx + dy*dy) + dz*dz without
-// contraction, so the neighbour sets are exact. Each lane keeps its k best
-// (d2, original index) pairs as sorted 64-bit keys (d2 bits << 32 | index) in
-// registers, updated by a fully unrolled insertion network; a list of KMAX
-// slots serves any k <= KMAX by parking KMAX - k sentinel keys (-1) in front.
+// Work item = (leaf, up to 16 queries, candidate chunk), one wave each.
+// Lane-per-candidate: each lane holds 4 candidates of a 256-candidate block
+// (coalesced loads, the next block prefetched), reused for the item's 16
+// queries, whose coordinates are wave-uniform (scalar loads). Squared
+// distances are fp32 (dx*dx + dy*dy) + dz*dz without contraction, so the
+// neighbour sets are exact.
 //
-// Bound (knn_bound_kernel, once per query tile): tau = the largest d2 to k
-// points next to the query in Morton order inside its own leaf; then, over a
-// window of the leaf's points around the tile, count the candidates under
-// tau * 2^(-m/2) and keep the smallest such threshold still holding k of them.
-// Those are candidates, so the k-th nearest distance is <= tau: the scan's
-// list starts as k placeholder keys (tau, 0xFFFFFFFF) and only candidates with
-// d2 <= tau can ever enter it. The result is unchanged; the insertion path
-// runs far less.
+// Each query keeps, in LDS, its k best (d2, original index) keys (d2 bits <<
+// 32 | index), sorted, one per lane when loaded, and a pending buffer of up
+// to 64 keys. A candidate block is tested against the query's current k-th
+// distance with one compare per lane; the candidates that pass are appended
+// to the pending buffer (ballot + lane rank). A full buffer, and the buffer
+// at the end of the chunk, is merged into the list: the 64 pending keys are
+// sorted descending by a wave-wide bitonic network, the elementwise minimum
+// with the ascending list holds the 64 smallest keys of both as a bitonic
+// sequence, and six more exchange steps sort it. The list keeps the first k.
 //
-// Leaves with many candidates are split into chunks processed by different
-// workgroups; each writes its partial list and the last chunk of a query tile
-// to finish (arrival counter, device-scope fences, no waiting) inserts the
-// other chunks' entries into its own list.
+// Bound: knn_bound_kernel gives each query tau >= its k-th squared distance
+// (from k of its own candidates), so its list starts as k placeholder keys
+// (tau, 0xFFFFFFFF) and only candidates with d2 <= tau can ever enter. The
+// result is unchanged.
+//
+// Leaves with many candidates are split into chunks processed as separate
+// items; each writes its partial lists, and the last chunk of a query group
+// to finish (arrival counter with device-scope fences, no waiting) merges
+// the other chunks' lists into its own with the same exchange steps.
 #include <climits>
 
 #include "kernels.hpp"
@@ -28,51 +34,80 @@
 namespace gdn {
 
 constexpr uint32_t NONE32 = 0xFFFFFFFFu;
+constexpr unsigned long long KEY_EMPTY = (unsigned long long)LLONG_MAX;
+constexpr int QPW = KNN_TQ;  // queries per wave item
+constexpr int CPL = 4;       // candidates per lane per block
+constexpr int CBLK = 64 * CPL;
+constexpr int PEND = 64;     // pending keys per query
 
 __device__ __forceinline__ float dist2(const float4 q, const float4 c) {
     const float dx = c.x - q.x, dy = c.y - q.y, dz = c.z - q.z;
     return (dx * dx + dy * dy) + dz * dz;
 }
 
-template <int KMAX>
-__device__ __forceinline__ void topk_insert(long long (&a)[KMAX], const long long key) {
-#pragma unroll
-    for (int i = KMAX - 1; i >= 1; --i) {
-        const long long lo = key < a[i] ? key : a[i];
-        a[i] = a[i - 1] > lo ? a[i - 1] : lo;
-    }
-    a[0] = key < a[0] ? key : a[0];
-}
-
-template <int KMAX>
-__device__ __forceinline__ void try_insert(long long (&a)[KMAX], float& worst, const float d,
-                                           const float cw, const uint32_t self) {
-    const uint32_t ci = __float_as_uint(cw);
-    // sign bit cleared: keys stay >= 0 even for a NaN distance (non-finite input)
-    const long long key = ((long long)(__float_as_uint(d) & 0x7FFFFFFFu) << 32) | (long long)ci;
-    if (key < a[KMAX - 1] && ci != self) {
-        topk_insert<KMAX>(a, key);
-        worst = __uint_as_float((uint32_t)((unsigned long long)a[KMAX - 1] >> 32));
-    }
-}
-
 // A list entry is real unless it is the empty key or a tau placeholder.
-__device__ __forceinline__ bool real_entry(long long v) {
-    return v != LLONG_MAX && (uint32_t)v != NONE32;
+__device__ __forceinline__ bool real_entry(unsigned long long v) {
+    return v != KEY_EMPTY && (uint32_t)v != NONE32;
 }
 
-__device__ __forceinline__ void write_final(const Plan& P, uint32_t qi, int k, int r, long long v) {
-    const bool ok = real_entry(v);
-    const float d = ok ? __uint_as_float((uint32_t)((unsigned long long)v >> 32)) : INFINITY;
-    P.nbr[(size_t)qi * k + r] = ok ? (uint32_t)v : NONE32;
-    P.nbr_d2[(size_t)qi * k + r] = d;
-    if (r == k - 1) P.r2k[qi] = d;
+__device__ __forceinline__ unsigned long long make_key(float d, uint32_t idx) {
+    // sign bit cleared: keys stay >= 0 even for a NaN distance (non-finite input)
+    return ((unsigned long long)(__float_as_uint(d) & 0x7FFFFFFFu) << 32) | idx;
 }
+
+__device__ __forceinline__ unsigned long long read_lane64(unsigned long long v, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long shfl64(unsigned long long v, int src_lane) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src_lane, 64);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src_lane, 64);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long xor64(unsigned long long v, int m) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Compare-exchange with lane ^ stride: this lane keeps the smaller key iff
+// keep_min.
+__device__ __forceinline__ unsigned long long cx(unsigned long long v, int stride, bool keep_min) {
+    const unsigned long long o = xor64(v, stride);
+    return ((o < v) == keep_min) ? o : v;
+}
+
+// Bitonic sort of one key per lane, descending over lanes 0..63.
+__device__ __forceinline__ unsigned long long sort64_desc(unsigned long long v, uint32_t lane) {
+#pragma unroll
+    for (int size = 2; size <= 64; size <<= 1) {
+        const bool asc = (lane & (uint32_t)size) != 0u;
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1)
+            v = cx(v, stride, ((lane & (uint32_t)stride) == 0u) == asc);
+    }
+    return v;
+}
+
+// Sort a bitonic sequence (one key per lane) ascending.
+__device__ __forceinline__ unsigned long long merge64_asc(unsigned long long v, uint32_t lane) {
+#pragma unroll
+    for (int stride = 32; stride > 0; stride >>= 1) v = cx(v, stride, (lane & (uint32_t)stride) == 0u);
+    return v;
+}
+
+// ---------------------------------------------------------------- bound
 
 constexpr int BOUND_MARGIN = 64;   // window reaches this far on each side of a query
 constexpr int BOUND_LEVELS = 10;   // thresholds tau * 2^(-m/2), m = 1..10
 
-// tau for query qi (one lane): -1 when the leaf has <= k P1 points.
+// tau: the largest d2 to the k points next to the query in Morton order inside
+// its own leaf (all of them candidates); then, over the leaf's points within
+// BOUND_MARGIN positions, count the candidates under tau * 2^(-m/2) and keep
+// the smallest threshold still holding k. -1 when the leaf has <= k P1 points.
 __device__ float query_bound(const float4* __restrict__ cand4, uint32_t qb, uint32_t qe, uint32_t qi, int k) {
     if (qe - qb <= (uint32_t)k) return -1.0f;
     const float4 q = cand4[qi];
@@ -105,55 +140,68 @@ __device__ float query_bound(const float4* __restrict__ cand4, uint32_t qb, uint
     return best;
 }
 
-// One wave per query tile (the chunk-0 item of each tile).
+// One thread per P1 point: its bound, and, for the first query of each tile,
+// the tile's work items (one per candidate chunk) at the queue position the
+// plan gave the leaf; the tile's arrival counter is cleared here.
 __global__ __launch_bounds__(256) void knn_bound_kernel(Plan P, const float4* __restrict__ cand4, int k) {
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    const uint32_t n_items = P.ctr->n_items;
-    for (uint32_t it = wave; it < n_items; it += nwaves) {
-        const KnnItem w = P.items[it];
-        if (w.chunk != 0) continue;
-        const uint32_t t = w.leaf;
+    const uint32_t np1 = P.ctr->n_p1;
+    for (uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x; qi < np1; qi += gridDim.x * blockDim.x) {
+        const uint32_t t = P.cand_leaf[qi];
         const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
-        const uint32_t qi = w.q0 + lane;
-        if (qi < w.q1) P.tau_c[qi] = query_bound(cand4, qb, qe, qi, k);
+        P.tau_c[qi] = query_bound(cand4, qb, qe, qi, k);
+        if ((qi - qb) % (uint32_t)KNN_TQ == 0u) {
+            const uint32_t nch = P.leaf_nch[t];
+            const uint32_t grp = P.leaf_item[t] + ((qi - qb) / (uint32_t)KNN_TQ) * nch;
+            const uint32_t q1 = min(qe, qi + (uint32_t)KNN_TQ);
+            P.tile_done[grp] = 0u;
+            for (uint32_t c = 0; c < nch; ++c) P.items[grp + c] = KnnItem{t, qi, q1, c, grp, 0u};
+        }
     }
 }
 
-template <int KMAX>
-__device__ __forceinline__ void test4(long long (&a)[KMAX], float& worst, const uint32_t self, const bool vq,
-                                      const float d0, const float d1, const float d2, const float d3,
-                                      const float w0, const float w1, const float w2, const float w3) {
-    const float dm = fminf(fminf(d0, d1), fminf(d2, d3));
-    if (vq && !(dm > worst)) {
-        try_insert<KMAX>(a, worst, d0, w0, self);
-        try_insert<KMAX>(a, worst, d1, w1, self);
-        try_insert<KMAX>(a, worst, d2, w2, self);
-        try_insert<KMAX>(a, worst, d3, w3, self);
+// ---------------------------------------------------------------- kNN
+
+__device__ __forceinline__ void write_final(const Plan& P, uint32_t qi, uint32_t k, uint32_t lane,
+                                            unsigned long long v) {
+    if (lane < k) {
+        const bool ok = real_entry(v);
+        const float d = ok ? __uint_as_float((uint32_t)(v >> 32)) : INFINITY;
+        P.nbr[(size_t)qi * k + lane] = ok ? (uint32_t)v : NONE32;
+        P.nbr_d2[(size_t)qi * k + lane] = d;
+        if (lane == k - 1) P.r2k[qi] = d;
     }
 }
 
-template <int KMAX>
-__device__ __forceinline__ void scan4(long long (&a)[KMAX], float& worst, const float4 q, const uint32_t self,
-                                      const bool vq, const float4 c0, const float4 c1, const float4 c2,
-                                      const float4 c3) {
-    const float d0 = dist2(q, c0), d1 = dist2(q, c1), d2 = dist2(q, c2), d3 = dist2(q, c3);
-    const float dm = fminf(fminf(d0, d1), fminf(d2, d3));
-    if (vq && !(dm > worst)) {
-        try_insert<KMAX>(a, worst, d0, c0.w, self);
-        try_insert<KMAX>(a, worst, d1, c1.w, self);
-        try_insert<KMAX>(a, worst, d2, c2.w, self);
-        try_insert<KMAX>(a, worst, d3, c3.w, self);
-    }
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One wave per work item; waves of a block are independent. Item scalars and
-// the candidate stream have wave-uniform addresses, so they come through the
-// scalar cache into SGPRs and feed the VALU directly.
-template <int KMAX>
-__global__ __launch_bounds__(256) void knn_kernel(Plan P, const float4* __restrict__ cand4, int k) {
-    const uint32_t lane = threadIdx.x & 63u;
+// Merge query j's pending keys into its list; returns the new k-th distance
+// (NaN while the list holds fewer than k keys).
+__device__ __forceinline__ float flush(unsigned long long* __restrict__ lst, unsigned long long* __restrict__ pend,
+                                       uint32_t cnt, uint32_t lane, uint32_t k) {
+    wave_lds_sync();
+    unsigned long long v = lane < cnt ? pend[lane] : KEY_EMPTY;
+    const unsigned long long L = lane < k ? lst[lane] : KEY_EMPTY;
+    v = sort64_desc(v, lane);
+    v = merge64_asc(L < v ? L : v, lane);
+    if (lane < k) lst[lane] = v;
+    wave_lds_sync();
+    return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)k - 1));
+}
+
+// One wave per block. Dynamic LDS: per query, the list (k keys) and the
+// pending buffer (PEND keys).
+__global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restrict__ cand4, int kk) {
+    extern __shared__ unsigned long long s_dyn[];
+    __shared__ uint32_t pre[HALO + 1];
+    __shared__ uint32_t rx[HALO];
+    const uint32_t lane = threadIdx.x;
+    const uint32_t k = (uint32_t)kk;
+    unsigned long long* const s_list = s_dyn;                    // [QPW][k]
+    unsigned long long* const s_pend = s_dyn + (size_t)QPW * k;  // [QPW][PEND]
     const uint32_t n_items = P.ctr->n_items;
     for (;;) {
         uint32_t got = 0;
@@ -165,118 +213,161 @@ __global__ __launch_bounds__(256) void knn_kernel(Plan P, const float4* __restri
         const uint32_t nr = P.leaf_nr[t];
         const uint32_t ncand = P.leaf_ncand[t], nch = P.leaf_nch[t], cc = P.leaf_cc[t];
         const uint32_t qb = P.p1pos[P.leaf_begin[t]];
-        const uint32_t qi = w.q0 + lane;
-        const bool vq = qi < w.q1;
-        const float4 q = vq ? cand4[qi] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const uint32_t self = __float_as_uint(q.w);
-        const float tb = vq ? P.tau_c[qi] : -1.0f;
-        const bool has_tau = tb >= 0.0f;
-        const long long init =
-            has_tau ? (((long long)(__float_as_uint(tb) & 0x7FFFFFFFu) << 32) | (long long)NONE32) : LLONG_MAX;
-        long long a[KMAX];
-#pragma unroll
-        for (int r = 0; r < KMAX; ++r) a[r] = (r < KMAX - k) ? -1ll : init;
-        float worst = has_tau ? tb : __uint_as_float(0x7FFFFFFFu);  // NaN: no bound yet
+        const uint32_t qn = w.q1 - w.q0;
 
-        // walk the chunk [c_lo, c_hi) of the leaf's concatenated candidate ranges
+        // the leaf's candidate ranges and their prefix lengths
+        uint32_t len = 0;
+        if (lane < nr) {
+            const uint2 R = P.leaf_ranges[(size_t)t * HALO + lane];
+            rx[lane] = R.x;
+            len = R.y - R.x;
+        }
+        const uint32_t incl = wave_incl_scan(len);
+        if (lane < nr) pre[lane + 1] = incl;
+        if (lane == 0) pre[0] = 0;
+
+        // lists start as k tau placeholders (or empty); lane j of `worst`
+        // holds query j's current k-th distance, of `pcnt` its pending count
+        float worst = __uint_as_float(0x7FC00000u);
+        uint32_t pcnt = 0;
+        if (lane < qn) {
+            const float tb = P.tau_c[w.q0 + lane];
+            if (tb >= 0.0f) worst = tb;
+        }
+        for (uint32_t j = 0; j < qn; ++j) {
+            const float tb = P.tau_c[w.q0 + j];
+            if (lane < k) s_list[j * k + lane] = tb >= 0.0f ? make_key(tb, NONE32) : KEY_EMPTY;
+        }
+        wave_lds_sync();
+
         const uint32_t c_lo = w.chunk * cc;
         const uint32_t c_hi = min(ncand, c_lo + cc);
-        uint32_t pre = 0;
-        for (uint32_t r = 0; r < nr && pre < c_hi; ++r) {
-            const uint2 R = P.leaf_ranges[(size_t)t * HALO + r];
-            const uint32_t len = R.y - R.x;
-            const uint32_t s = max(c_lo, pre), e = min(c_hi, pre + len);
-            if (s < e) {
-                const float4* cp = cand4 + (R.x + (s - pre));
-                const float4* const cend = cand4 + (R.x + (e - pre));
-                if (cp + 8 <= cend) {
-                    // software pipeline: the next 8 candidates are requested
-                    // after this group's distances, so their scalar loads are
-                    // in flight while this group is tested
-                    float4 n0 = cp[0], n1 = cp[1], n2 = cp[2], n3 = cp[3];
-                    float4 n4 = cp[4], n5 = cp[5], n6 = cp[6], n7 = cp[7];
-                    for (;;) {
-                        const float d0 = dist2(q, n0), d1 = dist2(q, n1), d2 = dist2(q, n2), d3 = dist2(q, n3);
-                        const float d4 = dist2(q, n4), d5 = dist2(q, n5), d6 = dist2(q, n6), d7 = dist2(q, n7);
-                        const float w0 = n0.w, w1 = n1.w, w2 = n2.w, w3 = n3.w;
-                        const float w4 = n4.w, w5 = n5.w, w6 = n6.w, w7 = n7.w;
-                        cp += 8;
-                        const bool more = cp + 8 <= cend;
-                        __builtin_amdgcn_sched_barrier(0);
-                        if (more) {
-                            n0 = cp[0]; n1 = cp[1]; n2 = cp[2]; n3 = cp[3];
-                            n4 = cp[4]; n5 = cp[5]; n6 = cp[6]; n7 = cp[7];
-                        }
-                        __builtin_amdgcn_sched_barrier(0);
-                        test4<KMAX>(a, worst, self, vq, d0, d1, d2, d3, w0, w1, w2, w3);
-                        test4<KMAX>(a, worst, self, vq, d4, d5, d6, d7, w4, w5, w6, w7);
-                        if (!more) break;
-                    }
-                }
-                for (; cp < cend; ++cp) {
-                    const float4 c0 = cp[0];
-                    const float d0 = dist2(q, c0);
-                    if (vq && !(d0 > worst)) try_insert<KMAX>(a, worst, d0, c0.w, self);
+        uint32_t rr[CPL];
+#pragma unroll
+        for (int g = 0; g < CPL; ++g) rr[g] = 0;
+        float4 cn[CPL];
+        auto load_block = [&](uint32_t pos) {
+#pragma unroll
+            for (int g = 0; g < CPL; ++g) {
+                const uint32_t Lg = pos + (uint32_t)g * 64u + lane;
+                if (Lg < c_hi) {
+                    while (rr[g] + 1u < nr && pre[rr[g] + 1u] <= Lg) ++rr[g];
+                    cn[g] = cand4[rx[rr[g]] + (Lg - pre[rr[g]])];
+                } else {
+                    cn[g] = make_float4(0.f, 0.f, 0.f, __uint_as_float(NONE32));
                 }
             }
-            pre += len;
+        };
+        if (c_lo < c_hi) load_block(c_lo);
+        for (uint32_t pos = c_lo; pos < c_hi; pos += CBLK) {
+            float4 c[CPL];
+            bool valid[CPL];
+#pragma unroll
+            for (int g = 0; g < CPL; ++g) {
+                c[g] = cn[g];
+                valid[g] = pos + (uint32_t)g * 64u + lane < c_hi;
+            }
+            if (pos + CBLK < c_hi) load_block(pos + CBLK);
+            for (uint32_t j = 0; j < qn; ++j) {
+                const float4 q = cand4[w.q0 + j];
+                const uint32_t self = __float_as_uint(q.w);
+                float wj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(worst), (int)j));
+                float d[CPL];
+                unsigned long long m[CPL];
+                unsigned long long any = 0ull;
+#pragma unroll
+                for (int g = 0; g < CPL; ++g) {
+                    d[g] = dist2(q, c[g]);
+                    m[g] = __ballot(valid[g] && !(d[g] > wj) && __float_as_uint(c[g].w) != self);
+                    any |= m[g];
+                }
+                if (any == 0ull) continue;
+                uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)pcnt, (int)j);
+                unsigned long long* const pend = s_pend + (size_t)j * PEND;
+                unsigned long long* const lst = s_list + (size_t)j * k;
+#pragma unroll
+                for (int g = 0; g < CPL; ++g) {
+                    if (m[g] == 0ull) continue;
+                    uint32_t pc = (uint32_t)__popcll(m[g]);
+                    if (cnt + pc > (uint32_t)PEND) {
+                        wj = flush(lst, pend, cnt, lane, k);
+                        cnt = 0;
+#pragma unroll
+                        for (int h = g; h < CPL; ++h)
+                            m[h] = __ballot(valid[h] && !(d[h] > wj) && __float_as_uint(c[h].w) != self);
+                        pc = (uint32_t)__popcll(m[g]);
+                        if (pc == 0u) continue;
+                    }
+                    const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(m[g] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[g], 0u));
+                    if ((m[g] >> lane) & 1ull) pend[cnt + rank] = make_key(d[g], __float_as_uint(c[g].w));
+                    cnt += pc;
+                }
+                if (lane == j) {
+                    pcnt = cnt;
+                    worst = wj;
+                }
+            }
+        }
+        // drain the pending buffers
+        for (uint32_t j = 0; j < qn; ++j) {
+            const uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)pcnt, (int)j);
+            if (cnt) (void)flush(s_list + (size_t)j * k, s_pend + (size_t)j * PEND, cnt, lane, k);
         }
 
         bool write_out = nch == 1;
         if (nch > 1) {
-            // partial lists of a tile, laid out [chunk][r][query]: coalesced
-            const uint32_t m = w.q1 - w.q0;
-            long long* tb_ = (long long*)P.plist + ((size_t)P.leaf_plist[t] + (size_t)(w.q0 - qb) * nch) * (size_t)k;
-            if (vq) {
-#pragma unroll
-                for (int r = 0; r < KMAX; ++r)
-                    if (r >= KMAX - k) tb_[((size_t)w.chunk * k + (r - (KMAX - k))) * m + lane] = a[r];
-            }
+            // partial lists [query][chunk][r]: one coalesced row per list
+            unsigned long long* base = (unsigned long long*)P.plist + (size_t)P.leaf_plist[t] * k;
+            for (uint32_t j = 0; j < qn; ++j)
+                if (lane < k) base[((size_t)(w.q0 + j - qb) * nch + w.chunk) * k + lane] = s_list[j * k + lane];
             __threadfence();
             uint32_t last = 0;
             if (lane == 0) last = (atomicAdd(&P.tile_done[w.grp], 1u) == nch - 1u) ? 1u : 0u;
             last = __builtin_amdgcn_readfirstlane(__shfl(last, 0, 64));
             if (last) {
-                // last chunk of this tile to finish: insert the other chunks'
-                // entries (sorted; stop at the first that cannot enter)
+                // last chunk of this query group to finish: merge the other
+                // chunks' sorted lists into its own
                 __threadfence();
                 write_out = true;
-                if (vq) {
+                for (uint32_t j = 0; j < qn; ++j) {
+                    unsigned long long L = lane < k ? s_list[j * k + lane] : KEY_EMPTY;
+                    const unsigned long long* row = base + (size_t)(w.q0 + j - qb) * nch * k;
                     for (uint32_t c = 0; c < nch; ++c) {
                         if (c == w.chunk) continue;
-                        for (int r = 0; r < k; ++r) {
-                            const long long v = tb_[((size_t)c * k + r) * m + lane];
-                            if (!real_entry(v) || !(v < a[KMAX - 1])) break;
-                            topk_insert<KMAX>(a, v);
-                        }
+                        const unsigned long long pv = lane < k ? row[(size_t)c * k + lane] : KEY_EMPTY;
+                        if (!(read_lane64(pv, 0) < read_lane64(L, (int)k - 1))) continue;
+                        const unsigned long long rv = shfl64(pv, 63 - (int)lane);  // descending
+                        L = merge64_asc(L < rv ? L : rv, lane);
+                        if (lane >= k) L = KEY_EMPTY;
                     }
+                    if (lane < k) s_list[j * k + lane] = L;
                 }
+                wave_lds_sync();
             }
         }
-        if (write_out && vq) {
-#pragma unroll
-            for (int r = 0; r < KMAX; ++r)
-                if (r >= KMAX - k) write_final(P, qi, k, r - (KMAX - k), a[r]);
+        if (write_out) {
+            for (uint32_t j = 0; j < qn; ++j) {
+                const unsigned long long v = lane < k ? s_list[j * k + lane] : KEY_EMPTY;
+                write_final(P, w.q0 + j, k, lane, v);
+            }
         }
+        wave_lds_sync();
     }
 }
 
-template <int KMAX>
-static void launch_knn_t(const Plan& P, int k, int num_cus, hipStream_t st) {
-    const unsigned blocks = (unsigned)(num_cus > 0 ? num_cus : 256) * 4u;
-    hipLaunchKernelGGL(knn_kernel<KMAX>, dim3(blocks), dim3(256), 0, st, P, (const float4*)P.cand4, k);
-}
-
 void launch_knn_bound(const Plan& P, int k, int num_cus, hipStream_t st) {
-    const unsigned blocks = (unsigned)(num_cus > 0 ? num_cus : 256) * 4u;
+    (void)num_cus;
+    unsigned blocks = (P.n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(knn_bound_kernel, dim3(blocks), dim3(256), 0, st, P, (const float4*)P.cand4, k);
 }
 
+size_t knn_lds_bytes(int k) { return (size_t)QPW * ((size_t)k + PEND) * sizeof(unsigned long long); }
+
 void launch_knn(const Plan& P, int k, int num_cus, hipStream_t st) {
-    if (k <= 8) launch_knn_t<8>(P, k, num_cus, st);
-    else if (k <= 16) launch_knn_t<16>(P, k, num_cus, st);
-    else if (k <= 32) launch_knn_t<32>(P, k, num_cus, st);
-    else launch_knn_t<64>(P, k, num_cus, st);
+    const unsigned blocks = (unsigned)(num_cus > 0 ? num_cus : 256) * 16u;
+    hipLaunchKernelGGL(knn_kernel, dim3(blocks), dim3(64), knn_lds_bytes(k), st, P, (const float4*)P.cand4, k);
 }
 
 }  // namespace gdn

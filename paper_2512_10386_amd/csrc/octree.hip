@@ -334,7 +334,10 @@ void launch_halo(const Plan& P, hipStream_t st) {
 // candidate chunk). Leaves whose candidate set exceeds the chunk length are
 // split into chunks whose partial top-k lists are merged by the last chunk of
 // each tile to finish; the chunk length doubles until the partial lists and
-// items fit their workspace.
+// items fit their workspace. This kernel fixes, per leaf, the chunking and
+// the index of its first item; items of chunked leaves (the heaviest) come
+// first in the queue, then the rest, both in leaf order. The items themselves
+// are written by the bound kernel, one tile per thread.
 
 constexpr int PLAN_BLOCK = 1024;
 
@@ -381,8 +384,6 @@ __global__ __launch_bounds__(PLAN_BLOCK) void knn_plan_kernel(Plan P) {
         if (s_done) break;
     }
     const uint32_t cc = s_cc;
-    // Items of chunked leaves (the heaviest) come first in the queue, then the
-    // rest; both classes keep leaf order. Pass A counts the chunked items.
     {
         unsigned long long ic = 0;
         for (uint32_t t = tid; t < nl; t += PLAN_BLOCK) {
@@ -408,10 +409,9 @@ __global__ __launch_bounds__(PLAN_BLOCK) void knn_plan_kernel(Plan P) {
     const uint32_t n_chunked_items = s_chunked_items;
     for (uint32_t t0 = 0; t0 < nl; t0 += PLAN_BLOCK) {
         const uint32_t t = t0 + tid;
-        uint32_t nl1 = 0, nic = 0, niu = 0, nch = 1, qb = 0, qe = 0, nc = 0;
+        uint32_t nl1 = 0, nic = 0, niu = 0, nch = 1, nc = 0;
         if (t < nl) {
-            qb = P.p1pos[P.leaf_begin[t]];
-            qe = P.p1pos[P.leaf_begin[t + 1]];
+            const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
             nc = P.leaf_ncand[t];
             const uint32_t n1 = qe - qb;
             nch = (nc + cc - 1) / cc;
@@ -430,13 +430,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void knn_plan_kernel(Plan P) {
             P.leaf_nch[t] = nch;
             P.leaf_cc[t] = (nc + nch - 1) / nch;
             P.leaf_plist[t] = s_carry_l + exl;
-            uint32_t w = (nch > 1) ? s_carry_c + exc : n_chunked_items + s_carry_u + exu;
-            for (uint32_t q0 = qb; q0 < qe; q0 += KNN_TQ) {
-                const uint32_t q1 = min(qe, q0 + KNN_TQ);
-                const uint32_t grp = w;
-                P.tile_done[grp] = 0u;
-                for (uint32_t c = 0; c < nch; ++c) P.items[w++] = KnnItem{t, q0, q1, c, grp, 0u};
-            }
+            P.leaf_item[t] = (nch > 1) ? s_carry_c + exc : n_chunked_items + s_carry_u + exu;
         }
         __syncthreads();
         if (tid == 0) { s_carry_l += totl; s_carry_c += totc; s_carry_u += totu; }
