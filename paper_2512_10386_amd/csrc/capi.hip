@@ -105,7 +105,6 @@ gdn::Plan make_plan(uint32_t n, int k, char* base) {
     P.rho_o = (double*)take(8 * N);
     P.gpow_o = (double*)take(8 * N);
     P.items = (KnnItem*)take(sizeof(KnnItem) * (size_t)P.items_max);
-    P.tile_done = (uint32_t*)take(4 * (size_t)P.items_max);
     P.plist = (uint64_t*)take(8 * (size_t)P.plist_max * k);
     P.bytes = off;
     return P;
@@ -299,6 +298,7 @@ gdn_status gdn_denoise(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int6
     if (ce) (void)hipEventRecord(ce->ev[1], st);
     gdn::launch_knn(P, prm.k, ctx->num_cus, st);
     if (ce) (void)hipEventRecord(ce->ev[2], st);
+    gdn::launch_knn_merge(P, prm.k, ctx->num_cus, st);
     gdn::launch_density(P, prm, xyz, st);
     gdn::launch_leaf_select(P, prm, st);
     gdn::launch_score(P, prm, xyz, st);

@@ -48,7 +48,8 @@ struct Counters {
     uint32_t scan_tile_ctr[4];
     unsigned long long pairs;
     uint32_t knn_next;        // dynamic work-queue cursor of the kNN kernel
-    uint32_t pad[5];
+    uint32_t n_chunked_items; // kNN items of chunked leaves (they come first)
+    uint32_t pad[4];
 };
 
 // Frame constants derived on the device from the bounding box.
@@ -138,7 +139,6 @@ struct Plan {
     double* gpow_o;           // [n] original order rho^(alpha/2)
     // kNN work
     KnnItem* items;           // [items_max]
-    uint32_t* tile_done;      // [items_max] chunk arrivals per query tile
     uint32_t items_max;
     uint64_t* plist;          // [plist_max][k] partial top-k keys
     uint32_t plist_max;

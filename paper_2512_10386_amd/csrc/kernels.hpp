@@ -22,6 +22,7 @@ void launch_knn_plan(const Plan& P, hipStream_t st);
 // knn.hip: brute-force kNN over leaf + halo candidates (chunk merge included)
 void launch_knn_bound(const Plan& P, int k, int num_cus, hipStream_t st);
 void launch_knn(const Plan& P, int k, int num_cus, hipStream_t st);
+void launch_knn_merge(const Plan& P, int k, int num_cus, hipStream_t st);
 
 // score.hip: density, percentile/median, score, top-lambda, outputs
 void launch_density(const Plan& P, const Params& prm, const float* xyz, hipStream_t st);

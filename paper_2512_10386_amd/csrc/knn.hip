@@ -24,9 +24,10 @@
 // result is unchanged.
 //
 // Leaves with many candidates are split into chunks processed as separate
-// items; each writes its partial lists, and the last chunk of a query group
-// to finish (arrival counter with device-scope fences, no waiting) merges
-// the other chunks' lists into its own with the same exchange steps.
+// items; each writes its partial lists, which knn_merge_kernel combines after
+// this kernel. (Combining them here would need device-scope release/acquire
+// between waves, which on this chip writes back the L2 of the releasing XCD
+// on every chunk.)
 #include <climits>
 
 #include "kernels.hpp"
@@ -67,35 +68,81 @@ __device__ __forceinline__ unsigned long long shfl64(unsigned long long v, int s
     return ((unsigned long long)hi << 32) | lo;
 }
 
-__device__ __forceinline__ unsigned long long xor64(unsigned long long v, int m) {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
-    return ((unsigned long long)hi << 32) | lo;
+// Value of lane ^ M, without LDS: DPP quad permutes (1, 2), row rotations
+// (4, 8) and the gfx950 permlane swaps (16, 32).
+template <int M>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t x, uint32_t lane) {
+    if constexpr (M == 1) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0u, x, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    } else if constexpr (M == 2) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0u, x, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    } else if constexpr (M == 4) {
+        const uint32_t a = (uint32_t)__builtin_amdgcn_update_dpp(0u, x, 0x124, 0xF, 0xF, false);  // row_ror:4
+        const uint32_t b = (uint32_t)__builtin_amdgcn_update_dpp(0u, x, 0x12C, 0xF, 0xF, false);  // row_ror:12
+        return (lane & 4u) ? a : b;
+    } else if constexpr (M == 8) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0u, x, 0x128, 0xF, 0xF, false);  // row_ror:8
+    } else if constexpr (M == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        return (lane & 16u) ? (uint32_t)r[0] : (uint32_t)r[1];
+    } else {
+        static_assert(M == 32, "xor distance");
+        const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        return (lane & 32u) ? (uint32_t)r[0] : (uint32_t)r[1];
+    }
 }
 
-// Compare-exchange with lane ^ stride: this lane keeps the smaller key iff
+// Compare-exchange with lane ^ M: this lane keeps the smaller key iff
 // keep_min.
-__device__ __forceinline__ unsigned long long cx(unsigned long long v, int stride, bool keep_min) {
-    const unsigned long long o = xor64(v, stride);
+template <int M>
+__device__ __forceinline__ unsigned long long cx(unsigned long long v, uint32_t lane, bool keep_min) {
+    const uint32_t lo = xor_lane<M>((uint32_t)v, lane);
+    const uint32_t hi = xor_lane<M>((uint32_t)(v >> 32), lane);
+    const unsigned long long o = ((unsigned long long)hi << 32) | lo;
     return ((o < v) == keep_min) ? o : v;
+}
+
+// One exchange step of the descending sort: blocks of SIZE lanes alternate
+// direction so that each stage leaves bitonic blocks of twice the size.
+template <int SIZE, int M>
+__device__ __forceinline__ unsigned long long sort_step(unsigned long long v, uint32_t lane) {
+    return cx<M>(v, lane, ((lane & (uint32_t)M) == 0u) == ((lane & (uint32_t)SIZE) != 0u));
 }
 
 // Bitonic sort of one key per lane, descending over lanes 0..63.
 __device__ __forceinline__ unsigned long long sort64_desc(unsigned long long v, uint32_t lane) {
-#pragma unroll
-    for (int size = 2; size <= 64; size <<= 1) {
-        const bool asc = (lane & (uint32_t)size) != 0u;
-#pragma unroll
-        for (int stride = size >> 1; stride > 0; stride >>= 1)
-            v = cx(v, stride, ((lane & (uint32_t)stride) == 0u) == asc);
-    }
+    v = sort_step<2, 1>(v, lane);
+    v = sort_step<4, 2>(v, lane);
+    v = sort_step<4, 1>(v, lane);
+    v = sort_step<8, 4>(v, lane);
+    v = sort_step<8, 2>(v, lane);
+    v = sort_step<8, 1>(v, lane);
+    v = sort_step<16, 8>(v, lane);
+    v = sort_step<16, 4>(v, lane);
+    v = sort_step<16, 2>(v, lane);
+    v = sort_step<16, 1>(v, lane);
+    v = sort_step<32, 16>(v, lane);
+    v = sort_step<32, 8>(v, lane);
+    v = sort_step<32, 4>(v, lane);
+    v = sort_step<32, 2>(v, lane);
+    v = sort_step<32, 1>(v, lane);
+    v = sort_step<64, 32>(v, lane);
+    v = sort_step<64, 16>(v, lane);
+    v = sort_step<64, 8>(v, lane);
+    v = sort_step<64, 4>(v, lane);
+    v = sort_step<64, 2>(v, lane);
+    v = sort_step<64, 1>(v, lane);
     return v;
 }
 
 // Sort a bitonic sequence (one key per lane) ascending.
 __device__ __forceinline__ unsigned long long merge64_asc(unsigned long long v, uint32_t lane) {
-#pragma unroll
-    for (int stride = 32; stride > 0; stride >>= 1) v = cx(v, stride, (lane & (uint32_t)stride) == 0u);
+    v = cx<32>(v, lane, (lane & 32u) == 0u);
+    v = cx<16>(v, lane, (lane & 16u) == 0u);
+    v = cx<8>(v, lane, (lane & 8u) == 0u);
+    v = cx<4>(v, lane, (lane & 4u) == 0u);
+    v = cx<2>(v, lane, (lane & 2u) == 0u);
+    v = cx<1>(v, lane, (lane & 1u) == 0u);
     return v;
 }
 
@@ -142,7 +189,7 @@ __device__ float query_bound(const float4* __restrict__ cand4, uint32_t qb, uint
 
 // One thread per P1 point: its bound, and, for the first query of each tile,
 // the tile's work items (one per candidate chunk) at the queue position the
-// plan gave the leaf; the tile's arrival counter is cleared here.
+// plan gave the leaf.
 __global__ __launch_bounds__(256) void knn_bound_kernel(Plan P, const float4* __restrict__ cand4, int k) {
     const uint32_t np1 = P.ctr->n_p1;
     for (uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x; qi < np1; qi += gridDim.x * blockDim.x) {
@@ -153,7 +200,6 @@ __global__ __launch_bounds__(256) void knn_bound_kernel(Plan P, const float4* __
             const uint32_t nch = P.leaf_nch[t];
             const uint32_t grp = P.leaf_item[t] + ((qi - qb) / (uint32_t)KNN_TQ) * nch;
             const uint32_t q1 = min(qe, qi + (uint32_t)KNN_TQ);
-            P.tile_done[grp] = 0u;
             for (uint32_t c = 0; c < nch; ++c) P.items[grp + c] = KnnItem{t, qi, q1, c, grp, 0u};
         }
     }
@@ -178,18 +224,25 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Merge query j's pending keys into its list; returns the new k-th distance
-// (NaN while the list holds fewer than k keys).
+// Distance bound of a list whose k-th key is v: +inf while the list holds
+// fewer than k keys.
+__device__ __forceinline__ float bound_of(uint32_t hi) {
+    return hi == 0x7FFFFFFFu ? INFINITY : __uint_as_float(hi);
+}
+
+// Merge query j's pending keys into its list, dropping the query's own key
+// (the hot loop does not test for it); returns the new distance bound.
 __device__ __forceinline__ float flush(unsigned long long* __restrict__ lst, unsigned long long* __restrict__ pend,
-                                       uint32_t cnt, uint32_t lane, uint32_t k) {
+                                       uint32_t cnt, uint32_t lane, uint32_t k, unsigned long long selfkey) {
     wave_lds_sync();
     unsigned long long v = lane < cnt ? pend[lane] : KEY_EMPTY;
+    if (v == selfkey) v = KEY_EMPTY;
     const unsigned long long L = lane < k ? lst[lane] : KEY_EMPTY;
     v = sort64_desc(v, lane);
     v = merge64_asc(L < v ? L : v, lane);
     if (lane < k) lst[lane] = v;
     wave_lds_sync();
-    return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)k - 1));
+    return bound_of((uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)k - 1));
 }
 
 // One wave per block. Dynamic LDS: per query, the list (k keys) and the
@@ -226,13 +279,16 @@ __global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restric
         if (lane < nr) pre[lane + 1] = incl;
         if (lane == 0) pre[0] = 0;
 
-        // lists start as k tau placeholders (or empty); lane j of `worst`
-        // holds query j's current k-th distance, of `pcnt` its pending count
-        float worst = __uint_as_float(0x7FC00000u);
+        // lists start as k tau placeholders (or empty); lane j holds query
+        // j's coordinates, its distance bound (`worst`: candidates with d2 <=
+        // worst may enter) and its pending count
+        float worst = lane < qn ? INFINITY : -1.0f;
         uint32_t pcnt = 0;
+        float4 qv = make_float4(0.f, 0.f, 0.f, 0.f);
         if (lane < qn) {
             const float tb = P.tau_c[w.q0 + lane];
             if (tb >= 0.0f) worst = tb;
+            qv = cand4[w.q0 + lane];
         }
         for (uint32_t j = 0; j < qn; ++j) {
             const float tb = P.tau_c[w.q0 + j];
@@ -254,35 +310,24 @@ __global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restric
                     while (rr[g] + 1u < nr && pre[rr[g] + 1u] <= Lg) ++rr[g];
                     cn[g] = cand4[rx[rr[g]] + (Lg - pre[rr[g]])];
                 } else {
-                    cn[g] = make_float4(0.f, 0.f, 0.f, __uint_as_float(NONE32));
+                    // NaN coordinates: d2 <= bound never holds
+                    const float nan = __uint_as_float(0x7FC00000u);
+                    cn[g] = make_float4(nan, nan, nan, __uint_as_float(NONE32));
                 }
             }
         };
         if (c_lo < c_hi) load_block(c_lo);
         for (uint32_t pos = c_lo; pos < c_hi; pos += CBLK) {
             float4 c[CPL];
-            bool valid[CPL];
 #pragma unroll
-            for (int g = 0; g < CPL; ++g) {
-                c[g] = cn[g];
-                valid[g] = pos + (uint32_t)g * 64u + lane < c_hi;
-            }
+            for (int g = 0; g < CPL; ++g) c[g] = cn[g];
             if (pos + CBLK < c_hi) load_block(pos + CBLK);
-            for (uint32_t j = 0; j < qn; ++j) {
-                const float4 q = cand4[w.q0 + j];
-                const uint32_t self = __float_as_uint(q.w);
-                float wj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(worst), (int)j));
-                float d[CPL];
-                unsigned long long m[CPL];
-                unsigned long long any = 0ull;
-#pragma unroll
-                for (int g = 0; g < CPL; ++g) {
-                    d[g] = dist2(q, c[g]);
-                    m[g] = __ballot(valid[g] && !(d[g] > wj) && __float_as_uint(c[g].w) != self);
-                    any |= m[g];
-                }
-                if (any == 0ull) continue;
+            // append query j's passing candidates (masks m) to its pending
+            // buffer, merging the buffer into the list when it would overflow
+            auto append = [&](uint32_t j, float wj, unsigned long long (&m)[CPL], const float (&d)[CPL]) {
                 uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)pcnt, (int)j);
+                const unsigned long long selfkey =
+                    (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j);
                 unsigned long long* const pend = s_pend + (size_t)j * PEND;
                 unsigned long long* const lst = s_list + (size_t)j * k;
 #pragma unroll
@@ -290,11 +335,10 @@ __global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restric
                     if (m[g] == 0ull) continue;
                     uint32_t pc = (uint32_t)__popcll(m[g]);
                     if (cnt + pc > (uint32_t)PEND) {
-                        wj = flush(lst, pend, cnt, lane, k);
+                        wj = flush(lst, pend, cnt, lane, k, selfkey);
                         cnt = 0;
 #pragma unroll
-                        for (int h = g; h < CPL; ++h)
-                            m[h] = __ballot(valid[h] && !(d[h] > wj) && __float_as_uint(c[h].w) != self);
+                        for (int h = g; h < CPL; ++h) m[h] = __builtin_amdgcn_ballot_w64(d[h] <= wj);
                         pc = (uint32_t)__popcll(m[g]);
                         if (pc == 0u) continue;
                     }
@@ -307,50 +351,163 @@ __global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restric
                     pcnt = cnt;
                     worst = wj;
                 }
+            };
+            // Phase A: every query against the block, unrolled and without
+            // branches; bit j of `hit` marks a query with passing candidates
+            // (queries past qn have bound -1, which no distance passes).
+            uint32_t hit = 0;
+#pragma unroll
+            for (int j = 0; j < QPW; ++j) {
+                const float4 q = make_float4(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(qv.x), j)),
+                                             __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qv.y), j)),
+                                             __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qv.z), j)), 0.f);
+                const float wj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(worst), j));
+                unsigned long long any = 0ull;
+#pragma unroll
+                for (int g = 0; g < CPL; ++g) any |= __builtin_amdgcn_ballot_w64(dist2(q, c[g]) <= wj);
+                hit |= any != 0ull ? 1u << j : 0u;
+            }
+            // Phase B: the queries that hit, with their distances recomputed
+            while (hit != 0u) {
+                const uint32_t j = (uint32_t)__ffs((int)hit) - 1u;
+                hit &= hit - 1u;
+                const float4 q = make_float4(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(qv.x), (int)j)),
+                                             __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qv.y), (int)j)),
+                                             __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qv.z), (int)j)), 0.f);
+                const float wj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(worst), (int)j));
+                float d[CPL];
+                unsigned long long m[CPL];
+#pragma unroll
+                for (int g = 0; g < CPL; ++g) {
+                    d[g] = dist2(q, c[g]);
+                    m[g] = __builtin_amdgcn_ballot_w64(d[g] <= wj);
+                }
+                append(j, wj, m, d);
             }
         }
         // drain the pending buffers
         for (uint32_t j = 0; j < qn; ++j) {
             const uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)pcnt, (int)j);
-            if (cnt) (void)flush(s_list + (size_t)j * k, s_pend + (size_t)j * PEND, cnt, lane, k);
+            const unsigned long long selfkey =
+                (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j);
+            if (cnt) (void)flush(s_list + (size_t)j * k, s_pend + (size_t)j * PEND, cnt, lane, k, selfkey);
         }
 
-        bool write_out = nch == 1;
         if (nch > 1) {
-            // partial lists [query][chunk][r]: one coalesced row per list
+            // partial lists [query][chunk][r]: one coalesced row per list,
+            // merged by knn_merge_kernel
             unsigned long long* base = (unsigned long long*)P.plist + (size_t)P.leaf_plist[t] * k;
             for (uint32_t j = 0; j < qn; ++j)
                 if (lane < k) base[((size_t)(w.q0 + j - qb) * nch + w.chunk) * k + lane] = s_list[j * k + lane];
-            __threadfence();
-            uint32_t last = 0;
-            if (lane == 0) last = (atomicAdd(&P.tile_done[w.grp], 1u) == nch - 1u) ? 1u : 0u;
-            last = __builtin_amdgcn_readfirstlane(__shfl(last, 0, 64));
-            if (last) {
-                // last chunk of this query group to finish: merge the other
-                // chunks' sorted lists into its own
-                __threadfence();
-                write_out = true;
-                for (uint32_t j = 0; j < qn; ++j) {
-                    unsigned long long L = lane < k ? s_list[j * k + lane] : KEY_EMPTY;
-                    const unsigned long long* row = base + (size_t)(w.q0 + j - qb) * nch * k;
-                    for (uint32_t c = 0; c < nch; ++c) {
-                        if (c == w.chunk) continue;
-                        const unsigned long long pv = lane < k ? row[(size_t)c * k + lane] : KEY_EMPTY;
-                        if (!(read_lane64(pv, 0) < read_lane64(L, (int)k - 1))) continue;
-                        const unsigned long long rv = shfl64(pv, 63 - (int)lane);  // descending
-                        L = merge64_asc(L < rv ? L : rv, lane);
-                        if (lane >= k) L = KEY_EMPTY;
-                    }
-                    if (lane < k) s_list[j * k + lane] = L;
-                }
-                wave_lds_sync();
-            }
-        }
-        if (write_out) {
+        } else {
             for (uint32_t j = 0; j < qn; ++j) {
                 const unsigned long long v = lane < k ? s_list[j * k + lane] : KEY_EMPTY;
                 write_final(P, w.q0 + j, k, lane, v);
             }
+        }
+        wave_lds_sync();
+    }
+}
+
+// ---------------------------------------------------------------- chunk merge
+//
+// One wave per query tile of a chunked leaf, after the kNN kernel (the kernel
+// boundary makes every partial list visible). B_j, the smallest k-th key over
+// the chunks of query j, bounds its merged k-th key, so a list whose first key
+// exceeds B_j contributes nothing. The first and k-th keys of all lists of the
+// tile are fetched together and staged in LDS; the contributing lists are then
+// fetched eight at a time, over all queries of the tile, and merged into the
+// query's list with the exchange steps of the kNN kernel.
+__global__ __launch_bounds__(64) void knn_merge_kernel(Plan P, int kk) {
+    __shared__ unsigned long long s_fk[QPW * KNN_NCH_MAX * 2];
+    __shared__ unsigned long long s_lst[QPW * 64];
+    const uint32_t lane = threadIdx.x;
+    const uint32_t k = (uint32_t)kk;
+    const uint32_t nci = P.ctr->n_chunked_items;
+    for (uint32_t it = blockIdx.x; it < nci; it += gridDim.x) {
+        const KnnItem w = P.items[it];
+        if (w.chunk != 0u) continue;
+        const uint32_t t = w.leaf;
+        const uint32_t nch = P.leaf_nch[t];
+        const uint32_t qb = P.p1pos[P.leaf_begin[t]];
+        const uint32_t qn = w.q1 - w.q0;
+        const unsigned long long* base = (const unsigned long long*)P.plist + (size_t)P.leaf_plist[t] * k;
+        const uint32_t tot = qn * nch;
+        for (uint32_t e0 = 0; e0 < tot; e0 += 256u) {
+            unsigned long long f[4], kt[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const uint32_t e = e0 + (uint32_t)b * 64u + lane;
+                if (e < tot) {
+                    const uint32_t j = e / nch, c = e - j * nch;
+                    const unsigned long long* l = base + ((size_t)(w.q0 + j - qb) * nch + c) * k;
+                    f[b] = l[0];
+                    kt[b] = l[k - 1];
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const uint32_t e = e0 + (uint32_t)b * 64u + lane;
+                if (e < tot) {
+                    const uint32_t j = e / nch, c = e - j * nch;
+                    s_fk[(j * KNN_NCH_MAX + c) * 2u] = f[b];
+                    s_fk[(j * KNN_NCH_MAX + c) * 2u + 1u] = kt[b];
+                }
+            }
+        }
+        for (uint32_t j = 0; j < qn; ++j) s_lst[j * 64u + lane] = KEY_EMPTY;
+        wave_lds_sync();
+        uint32_t cm = 0;  // lane j: contributing chunks of query j
+        if (lane < qn) {
+            unsigned long long B = KEY_EMPTY;
+            for (uint32_t c = 0; c < nch; ++c) {
+                const unsigned long long v = s_fk[(lane * KNN_NCH_MAX + c) * 2u + 1u];
+                B = v < B ? v : B;
+            }
+            for (uint32_t c = 0; c < nch; ++c) {
+                const unsigned long long v = s_fk[(lane * KNN_NCH_MAX + c) * 2u];
+                if (real_entry(v) && v <= B) cm |= 1u << c;
+            }
+        }
+        // flattened (query, chunk) pairs: pair p belongs to the last query j
+        // with excl_j <= p among the queries that have pairs
+        const uint32_t pc = (uint32_t)__popc(cm);
+        const uint32_t incl = wave_incl_scan(pc);
+        const uint32_t excl = incl - pc;
+        const uint32_t T = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+        for (uint32_t p0 = 0; p0 < T; p0 += 8u) {
+            unsigned long long pv[8];
+            uint32_t pj[8];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const uint32_t p = p0 + (uint32_t)b;
+                pv[b] = KEY_EMPTY;
+                pj[b] = NONE32;
+                if (p < T) {
+                    const unsigned long long mk = __builtin_amdgcn_ballot_w64(pc > 0u && excl <= p);
+                    const uint32_t j = 63u - (uint32_t)__clzll((long long)mk);
+                    uint32_t bits = (uint32_t)__builtin_amdgcn_readlane((int)cm, (int)j);
+                    for (uint32_t r = p - (uint32_t)__builtin_amdgcn_readlane((int)excl, (int)j); r > 0u; --r)
+                        bits &= bits - 1u;
+                    const uint32_t c = (uint32_t)__ffs((int)bits) - 1u;
+                    if (lane < k) pv[b] = base[((size_t)(w.q0 + j - qb) * nch + c) * k + lane];
+                    pj[b] = j;
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                if (pj[b] == NONE32) continue;
+                unsigned long long* const lst = s_lst + pj[b] * 64u;
+                const unsigned long long L = lane < k ? lst[lane] : KEY_EMPTY;
+                const unsigned long long rv = shfl64(pv[b], 63 - (int)lane);  // descending
+                const unsigned long long v = merge64_asc(L < rv ? L : rv, lane);
+                if (lane < k) lst[lane] = v;
+                wave_lds_sync();
+            }
+        }
+        for (uint32_t j = 0; j < qn; ++j) {
+            const unsigned long long v = lane < k ? s_lst[j * 64u + lane] : KEY_EMPTY;
+            write_final(P, w.q0 + j, k, lane, v);
         }
         wave_lds_sync();
     }
@@ -368,6 +525,11 @@ size_t knn_lds_bytes(int k) { return (size_t)QPW * ((size_t)k + PEND) * sizeof(u
 void launch_knn(const Plan& P, int k, int num_cus, hipStream_t st) {
     const unsigned blocks = (unsigned)(num_cus > 0 ? num_cus : 256) * 16u;
     hipLaunchKernelGGL(knn_kernel, dim3(blocks), dim3(64), knn_lds_bytes(k), st, P, (const float4*)P.cand4, k);
+}
+
+void launch_knn_merge(const Plan& P, int k, int num_cus, hipStream_t st) {
+    const unsigned blocks = (unsigned)(num_cus > 0 ? num_cus : 256) * 8u;
+    hipLaunchKernelGGL(knn_merge_kernel, dim3(blocks), dim3(64), 0, st, P, k);
 }
 
 }  // namespace gdn

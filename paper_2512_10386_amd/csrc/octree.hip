@@ -436,7 +436,10 @@ __global__ __launch_bounds__(PLAN_BLOCK) void knn_plan_kernel(Plan P) {
         if (tid == 0) { s_carry_l += totl; s_carry_c += totc; s_carry_u += totu; }
         __syncthreads();
     }
-    if (tid == 0) P.ctr->n_items = s_carry_c + s_carry_u;
+    if (tid == 0) {
+        P.ctr->n_items = s_carry_c + s_carry_u;
+        P.ctr->n_chunked_items = s_carry_c;
+    }
 }
 
 void launch_knn_plan(const Plan& P, hipStream_t st) {
