@@ -18,7 +18,7 @@ constexpr int SCAN_BLOCK = 256;
 constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
 constexpr int KNN_TQ = 16;                    // queries per kNN work item (one wave)
-constexpr int KNN_CC0 = 2048;                 // initial candidate chunk
+constexpr int KNN_CC0 = 16384;                // initial candidate chunk
 constexpr int KNN_NCH_MAX = 32;               // max candidate chunks per leaf
 constexpr int HALO = 27;
 constexpr int VOX_BLOCK = 256;

@@ -135,6 +135,30 @@ __device__ __forceinline__ unsigned long long sort64_desc(unsigned long long v, 
     return v;
 }
 
+template <int M>
+__device__ __forceinline__ float xor_f32(float x, uint32_t lane) {
+    return __uint_as_float(xor_lane<M>(__float_as_uint(x), lane));
+}
+
+// Wave-wide min / max, result in every lane (fminf/fmaxf skip NaN).
+__device__ __forceinline__ float wave_min(float v, uint32_t lane) {
+    v = fminf(v, xor_f32<1>(v, lane));
+    v = fminf(v, xor_f32<2>(v, lane));
+    v = fminf(v, xor_f32<4>(v, lane));
+    v = fminf(v, xor_f32<8>(v, lane));
+    v = fminf(v, xor_f32<16>(v, lane));
+    return fminf(v, xor_f32<32>(v, lane));
+}
+
+__device__ __forceinline__ float wave_max(float v, uint32_t lane) {
+    v = fmaxf(v, xor_f32<1>(v, lane));
+    v = fmaxf(v, xor_f32<2>(v, lane));
+    v = fmaxf(v, xor_f32<4>(v, lane));
+    v = fmaxf(v, xor_f32<8>(v, lane));
+    v = fmaxf(v, xor_f32<16>(v, lane));
+    return fmaxf(v, xor_f32<32>(v, lane));
+}
+
 // Sort a bitonic sequence (one key per lane) ascending.
 __device__ __forceinline__ unsigned long long merge64_asc(unsigned long long v, uint32_t lane) {
     v = cx<32>(v, lane, (lane & 32u) == 0u);
@@ -152,9 +176,9 @@ constexpr int BOUND_MARGIN = 64;   // window reaches this far on each side of a 
 constexpr int BOUND_LEVELS = 10;   // thresholds tau * 2^(-m/2), m = 1..10
 
 // tau: the largest d2 to the k points next to the query in Morton order inside
-// its own leaf (all of them candidates); then, over the leaf's points within
-// BOUND_MARGIN positions, count the candidates under tau * 2^(-m/2) and keep
-// the smallest threshold still holding k. -1 when the leaf has <= k P1 points.
+// [qb, qe), a run of candidates holding the query; then, over the run's points
+// within BOUND_MARGIN positions, count those under tau * 2^(-m/2) and keep the
+// smallest threshold still holding k. -1 when the run has <= k points.
 __device__ float query_bound(const float4* __restrict__ cand4, uint32_t qb, uint32_t qe, uint32_t qi, int k) {
     if (qe - qb <= (uint32_t)k) return -1.0f;
     const float4 q = cand4[qi];
@@ -195,7 +219,19 @@ __global__ __launch_bounds__(256) void knn_bound_kernel(Plan P, const float4* __
     for (uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x; qi < np1; qi += gridDim.x * blockDim.x) {
         const uint32_t t = P.cand_leaf[qi];
         const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
-        P.tau_c[qi] = query_bound(cand4, qb, qe, qi, k);
+        // the window lives in the merged candidate range holding the query,
+        // which may reach past a small leaf (every point of it is a candidate)
+        uint32_t rb = qb, re = qe;
+        const uint32_t nr = P.leaf_nr[t];
+        for (uint32_t r = 0; r < nr; ++r) {
+            const uint2 R = P.leaf_ranges[(size_t)t * HALO + r];
+            if (R.x <= qi && qi < R.y) {
+                rb = R.x;
+                re = R.y;
+                break;
+            }
+        }
+        P.tau_c[qi] = query_bound(cand4, rb, re, qi, k);
         if ((qi - qb) % (uint32_t)KNN_TQ == 0u) {
             const uint32_t nch = P.leaf_nch[t];
             const uint32_t grp = P.leaf_item[t] + ((qi - qb) / (uint32_t)KNN_TQ) * nch;
@@ -249,8 +285,6 @@ __device__ __forceinline__ float flush(unsigned long long* __restrict__ lst, uns
 // pending buffer (PEND keys).
 __global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restrict__ cand4, int kk) {
     extern __shared__ unsigned long long s_dyn[];
-    __shared__ uint32_t pre[HALO + 1];
-    __shared__ uint32_t rx[HALO];
     const uint32_t lane = threadIdx.x;
     const uint32_t k = (uint32_t)kk;
     unsigned long long* const s_list = s_dyn;                    // [QPW][k]
@@ -268,16 +302,21 @@ __global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restric
         const uint32_t qb = P.p1pos[P.leaf_begin[t]];
         const uint32_t qn = w.q1 - w.q0;
 
-        // the leaf's candidate ranges and their prefix lengths
-        uint32_t len = 0;
+        // The leaf's candidate ranges, concatenated: lane r holds where range
+        // r starts in that order (cpre; past the end for lanes >= nr) and the
+        // offset from there to its P1 index (coff). The range of a position L
+        // is the number of lanes 1..nr-1 with cpre <= L.
+        uint32_t len = 0, rbeg = 0;
         if (lane < nr) {
             const uint2 R = P.leaf_ranges[(size_t)t * HALO + lane];
-            rx[lane] = R.x;
+            rbeg = R.x;
             len = R.y - R.x;
         }
-        const uint32_t incl = wave_incl_scan(len);
-        if (lane < nr) pre[lane + 1] = incl;
-        if (lane == 0) pre[0] = 0;
+        const uint32_t cpre = wave_incl_scan(len) - len + (lane < nr ? 0u : ncand);
+        const uint32_t coff = rbeg - cpre;
+        auto range_of = [&](uint32_t L) -> uint32_t {
+            return (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(lane >= 1u && lane < nr && cpre <= L));
+        };
 
         // lists start as k tau placeholders (or empty); lane j holds query
         // j's coordinates, its distance bound (`worst`: candidates with d2 <=
@@ -298,17 +337,21 @@ __global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restric
 
         const uint32_t c_lo = w.chunk * cc;
         const uint32_t c_hi = min(ncand, c_lo + cc);
-        uint32_t rr[CPL];
-#pragma unroll
-        for (int g = 0; g < CPL; ++g) rr[g] = 0;
         float4 cn[CPL];
+        // candidates [pos, pos + CBLK) of the concatenated order into cn
         auto load_block = [&](uint32_t pos) {
+            const uint32_t last = min(c_hi, pos + (uint32_t)CBLK) - 1u;
+            const uint32_t ra = range_of(pos), rb = range_of(last);
+            const uint32_t off0 = (uint32_t)__builtin_amdgcn_readlane((int)coff, (int)ra);
 #pragma unroll
             for (int g = 0; g < CPL; ++g) {
                 const uint32_t Lg = pos + (uint32_t)g * 64u + lane;
+                uint32_t off = off0;
+                for (uint32_t r = ra + 1u; r <= rb; ++r)
+                    if ((uint32_t)__builtin_amdgcn_readlane((int)cpre, (int)r) <= Lg)
+                        off = (uint32_t)__builtin_amdgcn_readlane((int)coff, (int)r);
                 if (Lg < c_hi) {
-                    while (rr[g] + 1u < nr && pre[rr[g] + 1u] <= Lg) ++rr[g];
-                    cn[g] = cand4[rx[rr[g]] + (Lg - pre[rr[g]])];
+                    cn[g] = cand4[off + Lg];
                 } else {
                     // NaN coordinates: d2 <= bound never holds
                     const float nan = __uint_as_float(0x7FC00000u);
@@ -316,12 +359,37 @@ __global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restric
                 }
             }
         };
-        if (c_lo < c_hi) load_block(c_lo);
-        for (uint32_t pos = c_lo; pos < c_hi; pos += CBLK) {
+        // Blocks nearest to the tile in Morton order first, so that the bounds
+        // tighten early: start at the block holding the tile's position in the
+        // concatenated order (or the chunk end nearest to it), then alternate
+        // outwards.
+        const uint32_t ro = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(lane >= 1u && lane < nr && rbeg <= w.q0));
+        const uint32_t p_t = (uint32_t)__builtin_amdgcn_readlane((int)cpre, (int)ro) +
+                             (w.q0 - (uint32_t)__builtin_amdgcn_readlane((int)rbeg, (int)ro));
+        const int nblk = c_lo < c_hi ? (int)((c_hi - c_lo + CBLK - 1) / CBLK) : 0;
+        const int b_start = p_t < c_lo ? 0 : min((int)((p_t - c_lo) / CBLK), nblk - 1);
+        int nx_hi = b_start + 1, nx_lo = b_start - 1;
+        bool up = true;
+        auto next_block = [&]() -> int {
+            if (up && nx_hi < nblk) {
+                up = false;
+                return nx_hi++;
+            }
+            if (nx_lo >= 0) {
+                up = true;
+                return nx_lo--;
+            }
+            if (nx_hi < nblk) return nx_hi++;
+            return -1;
+        };
+        if (nblk > 0) load_block(c_lo + (uint32_t)b_start * CBLK);
+        for (int b = nblk > 0 ? b_start : -1; b >= 0;) {
             float4 c[CPL];
 #pragma unroll
             for (int g = 0; g < CPL; ++g) c[g] = cn[g];
-            if (pos + CBLK < c_hi) load_block(pos + CBLK);
+            const int b_next = next_block();
+            if (b_next >= 0) load_block(c_lo + (uint32_t)b_next * CBLK);
+            b = b_next;
             // append query j's passing candidates (masks m) to its pending
             // buffer, merging the buffer into the list when it would overflow
             auto append = [&](uint32_t j, float wj, unsigned long long (&m)[CPL], const float (&d)[CPL]) {
@@ -352,37 +420,43 @@ __global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restric
                     worst = wj;
                 }
             };
-            // Phase A: every query against the block, unrolled and without
-            // branches; bit j of `hit` marks a query with passing candidates
-            // (queries past qn have bound -1, which no distance passes).
-            uint32_t hit = 0;
+            // Cull by the block's bounding box: with lo <= c <= hi per axis,
+            // fl(lo - q) <= fl(c - q) (and likewise above hi), and rounded
+            // squares and sums are monotone, so the box distance computed in
+            // the same order as dist2 is <= the d2 of every candidate in the
+            // block. A query whose box distance exceeds its bound skips the
+            // block; the result is unchanged. (fminf/fmaxf skip the NaN
+            // padding of a ragged block.)
+            float lx = c[0].x, ly = c[0].y, lz = c[0].z, hx = c[0].x, hy = c[0].y, hz = c[0].z;
 #pragma unroll
-            for (int j = 0; j < QPW; ++j) {
-                const float4 q = make_float4(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(qv.x), j)),
-                                             __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qv.y), j)),
-                                             __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qv.z), j)), 0.f);
-                const float wj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(worst), j));
-                unsigned long long any = 0ull;
-#pragma unroll
-                for (int g = 0; g < CPL; ++g) any |= __builtin_amdgcn_ballot_w64(dist2(q, c[g]) <= wj);
-                hit |= any != 0ull ? 1u << j : 0u;
+            for (int g = 1; g < CPL; ++g) {
+                lx = fminf(lx, c[g].x); ly = fminf(ly, c[g].y); lz = fminf(lz, c[g].z);
+                hx = fmaxf(hx, c[g].x); hy = fmaxf(hy, c[g].y); hz = fmaxf(hz, c[g].z);
             }
-            // Phase B: the queries that hit, with their distances recomputed
-            while (hit != 0u) {
-                const uint32_t j = (uint32_t)__ffs((int)hit) - 1u;
-                hit &= hit - 1u;
+            lx = wave_min(lx, lane); ly = wave_min(ly, lane); lz = wave_min(lz, lane);
+            hx = wave_max(hx, lane); hy = wave_max(hy, lane); hz = wave_max(hz, lane);
+            const float gx = fmaxf(fmaxf(lx - qv.x, qv.x - hx), 0.0f);
+            const float gy = fmaxf(fmaxf(ly - qv.y, qv.y - hy), 0.0f);
+            const float gz = fmaxf(fmaxf(lz - qv.z, qv.z - hz), 0.0f);
+            const float bd = (gx * gx + gy * gy) + gz * gz;
+            unsigned long long qm = __builtin_amdgcn_ballot_w64(lane < qn && !(bd > worst));
+            while (qm != 0ull) {
+                const uint32_t j = (uint32_t)__ffsll((long long)qm) - 1u;
+                qm &= qm - 1ull;
                 const float4 q = make_float4(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(qv.x), (int)j)),
                                              __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qv.y), (int)j)),
                                              __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qv.z), (int)j)), 0.f);
                 const float wj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(worst), (int)j));
                 float d[CPL];
                 unsigned long long m[CPL];
+                unsigned long long any = 0ull;
 #pragma unroll
                 for (int g = 0; g < CPL; ++g) {
                     d[g] = dist2(q, c[g]);
                     m[g] = __builtin_amdgcn_ballot_w64(d[g] <= wj);
+                    any |= m[g];
                 }
-                append(j, wj, m, d);
+                if (any != 0ull) append(j, wj, m, d);
             }
         }
         // drain the pending buffers
