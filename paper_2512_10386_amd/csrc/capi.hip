@@ -73,6 +73,7 @@ gdn::Plan make_plan(uint32_t n, int k, char* base) {
     P.leaf_of = (uint32_t*)take(4 * N);
     P.occ = (uint32_t*)take(4 * N);
     P.p1 = (uint8_t*)take(N);
+    P.bflag = (uint8_t*)take(N);
     P.p1pos = (uint32_t*)take(4 * (N + 1));
     P.leaf_begin = (uint32_t*)take(4 * (N + 1));
     P.leaf_level = (uint32_t*)take(4 * N);
@@ -102,7 +103,6 @@ gdn::Plan make_plan(uint32_t n, int k, char* base) {
     P.p2 = (uint8_t*)take(N);
     P.stage_c = (uint8_t*)take(N);
     P.score_c = (double*)take(8 * N);
-    P.rho_o = (double*)take(8 * N);
     P.gpow_o = (double*)take(8 * N);
     P.items = (KnnItem*)take(sizeof(KnnItem) * (size_t)P.items_max);
     P.plist = (uint64_t*)take(8 * (size_t)P.plist_max * k);

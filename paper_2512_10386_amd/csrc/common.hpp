@@ -11,7 +11,7 @@ constexpr uint32_t QMAX = (1u << MORTON_BITS) - 1u;
 
 // Tile sizes.
 constexpr int SORT_BLOCK = 256;               // radix-sort workgroup
-constexpr int SORT_ITEMS = 16;                // keys per thread
+constexpr int SORT_ITEMS = 4;                 // keys per thread
 constexpr int SORT_TILE = SORT_BLOCK * SORT_ITEMS;
 constexpr int SORT_PASSES = 8;                // 8-bit digits over the 63-bit key
 constexpr int SCAN_BLOCK = 256;
@@ -104,6 +104,7 @@ struct Plan {
     uint32_t* leaf_of;        // [n] sorted
     uint32_t* occ;            // [n] sorted
     uint8_t* p1;              // [n] sorted
+    uint8_t* bflag;           // [n] sorted: a leaf starts here
     uint32_t* p1pos;          // [n+1] exclusive scan of p1
     // leaves (at most n)
     uint32_t* leaf_begin;     // [n+1]
@@ -135,7 +136,6 @@ struct Plan {
     uint8_t* p2;              // [n]
     uint8_t* stage_c;         // [n] 1 density-removed, 2 score-removed, 3 kept
     double* score_c;          // [n]
-    double* rho_o;            // [n] original order
     double* gpow_o;           // [n] original order rho^(alpha/2)
     // kNN work
     KnnItem* items;           // [items_max]
@@ -155,10 +155,14 @@ __device__ __forceinline__ float f32_from_ordered(uint32_t o) {
     return __uint_as_float(u);
 }
 
-__device__ __forceinline__ uint32_t ld_acquire_agent(const uint32_t* p) {
+// Look-back status words carry their whole payload (flag + count), so relaxed
+// device-scope atomics suffice: no other data is published through them.
+constexpr int LB_WINDOW = 8;                  // predecessors fetched per look-back round trip
+
+__device__ __forceinline__ uint32_t ld_relaxed_agent(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_release_agent(uint32_t* p, uint32_t v) {
+__device__ __forceinline__ void st_relaxed_agent(uint32_t* p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 

@@ -216,26 +216,43 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
     uint32_t* st = status + (size_t)tile * 256 + tid;
     uint32_t excl = 0;
     if (tile == 0) {
-        st_release_agent(st, LB_FLAG_PRE | tcnt);
+        st_relaxed_agent(st, LB_FLAG_PRE | tcnt);
     } else {
-        st_release_agent(st, LB_FLAG_AGG | tcnt);
+        st_relaxed_agent(st, LB_FLAG_AGG | tcnt);
+        // LB_WINDOW predecessors per round trip; consume ready words nearest
+        // first until an inclusive prefix, stop at the first one not ready
         int j = (int)tile - 1;
         uint32_t spins = 0;
         while (j >= 0) {
-            uint32_t w = ld_acquire_agent(status + (size_t)j * 256 + tid);
-            if ((w & ~LB_VALUE) == 0u) {
+            uint32_t w[LB_WINDOW];
+#pragma unroll
+            for (int b = 0; b < LB_WINDOW; ++b)
+                w[b] = j - b >= 0 ? ld_relaxed_agent(status + (size_t)(j - b) * 256 + tid) : 0u;
+            int used = 0;
+            bool stop = false, pre = false;
+#pragma unroll
+            for (int b = 0; b < LB_WINDOW; ++b) {
+                if (!stop) {
+                    if (j - b < 0 || (w[b] & ~LB_VALUE) == 0u) {
+                        stop = true;
+                    } else {
+                        excl += w[b] & LB_VALUE;
+                        ++used;
+                        if (w[b] & LB_FLAG_PRE) pre = stop = true;
+                    }
+                }
+            }
+            if (pre) break;
+            j -= used;
+            if (used == 0) {
                 if (++spins > SPIN_LIMIT) {
                     atomicOr(dev_status, DEV_WAIT_LIMIT);
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
-                continue;
             }
-            excl += w & LB_VALUE;
-            if (w & LB_FLAG_PRE) break;
-            --j;
         }
-        st_release_agent(st, LB_FLAG_PRE | ((excl + tcnt) & LB_VALUE));
+        st_relaxed_agent(st, LB_FLAG_PRE | ((excl + tcnt) & LB_VALUE));
     }
     // global base of each digit
     uint32_t total;

@@ -81,12 +81,26 @@ __global__ __launch_bounds__(256) void leaf_table_kernel(Plan P, uint32_t cap) {
     }
 }
 
+// The boundary tests run one thread per position (each is a chain of
+// dependent loads); the scan then only reads the flags.
+__global__ __launch_bounds__(256) void boundary_flag_kernel(Plan P, uint32_t cap) {
+    const BoundaryGet g{P.keys_a, P.fc, P.n, cap};
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < P.n; j += gridDim.x * blockDim.x)
+        P.bflag[j] = (uint8_t)g(j);
+}
+
+struct FlagGet {
+    const uint8_t* f;
+    __device__ uint32_t operator()(uint32_t j) const { return f[j]; }
+};
+
 void launch_leaves(const Plan& P, const Params& prm, hipStream_t st) {
-    BoundaryGet g{P.keys_a, P.fc, P.n, (uint32_t)prm.leaf_cap};
+    unsigned blocks = (P.n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(boundary_flag_kernel, dim3(blocks), dim3(256), 0, st, P, (uint32_t)prm.leaf_cap);
     BoundaryEmit e{P.leaf_of, P.leaf_begin};
     BoundaryFin f{P.ctr, P.leaf_begin, P.n};
-    launch_scan(g, e, f, nullptr, P.n, P.scan_status, &P.ctr->scan_tile_ctr[0], &P.ctr->status, st);
-    unsigned blocks = (P.n + 255) / 256;
+    launch_scan(FlagGet{P.bflag}, e, f, nullptr, P.n, P.scan_status, &P.ctr->scan_tile_ctr[0], &P.ctr->status, st);
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(leaf_table_kernel, dim3(blocks), dim3(256), 0, st, P, (uint32_t)prm.leaf_cap);
 }

@@ -41,31 +41,46 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(Get get, Emit emit, Fi
     }
     uint32_t agg;
     const uint32_t ex = block_excl_scan(sum, s_scan, &agg);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {
+        // first wave: look back over up to 64 predecessors per round trip
+        // (lane l reads tile j - l); add the ready aggregates nearest first
+        // up to and including an inclusive prefix, stop at one not ready
+        const uint32_t lane = threadIdx.x;
         uint32_t* st = status + tile;
         if (tile == 0) {
-            st_release_agent(st, LB_FLAG_PRE | agg);
-            s_excl = 0;
+            if (lane == 0) {
+                st_relaxed_agent(st, LB_FLAG_PRE | agg);
+                s_excl = 0;
+            }
         } else {
-            st_release_agent(st, LB_FLAG_AGG | agg);
+            if (lane == 0) st_relaxed_agent(st, LB_FLAG_AGG | agg);
             uint32_t excl = 0, spins = 0;
             int j = (int)tile - 1;
             while (j >= 0) {
-                uint32_t w = ld_acquire_agent(status + j);
-                if ((w & ~LB_VALUE) == 0u) {
+                const int jj = j - (int)lane;
+                const uint32_t w = jj >= 0 ? ld_relaxed_agent(status + jj) : 0u;
+                const unsigned long long nready = __builtin_amdgcn_ballot_w64(jj >= 0 && (w & ~LB_VALUE) == 0u);
+                const unsigned long long pre = __builtin_amdgcn_ballot_w64(jj >= 0 && (w & LB_FLAG_PRE) != 0u);
+                const unsigned long long stop = nready | pre;
+                const uint32_t s = stop ? (uint32_t)__ffsll((long long)stop) - 1u : 64u;
+                const bool done = s < 64u && ((pre >> s) & 1ull);
+                const uint32_t take = (jj >= 0 && (lane < s || (done && lane == s))) ? (w & LB_VALUE) : 0u;
+                excl += wave_sum(take);
+                if (done) break;
+                const uint32_t used = min(s, (uint32_t)(j + 1));
+                j -= (int)used;
+                if (used == 0u) {
                     if (++spins > SPIN_LIMIT) {
-                        atomicOr(dev_status, DEV_WAIT_LIMIT);
+                        if (lane == 0) atomicOr(dev_status, DEV_WAIT_LIMIT);
                         break;
                     }
                     __builtin_amdgcn_s_sleep(1);
-                    continue;
                 }
-                excl += w & LB_VALUE;
-                if (w & LB_FLAG_PRE) break;
-                --j;
             }
-            st_release_agent(st, LB_FLAG_PRE | ((excl + agg) & LB_VALUE));
-            s_excl = excl;
+            if (lane == 0) {
+                st_relaxed_agent(st, LB_FLAG_PRE | ((excl + agg) & LB_VALUE));
+                s_excl = excl;
+            }
         }
     }
     __syncthreads();

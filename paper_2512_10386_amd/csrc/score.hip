@@ -15,43 +15,76 @@ constexpr double PI_D = 3.14159265358979323846;
 //
 // r_K,i = the largest FP64 distance to the k neighbours; rho_i = K / (4/3 pi r^3).
 // A point with fewer than k candidates has rho = 0 (r = inf).
+//
+// Density and score gather their neighbours one lane each: a wave holds
+// 64 / kp queries, kp = k rounded up to a power of two, lane r of a segment
+// takes neighbour r, and segment reductions combine them.
 
-__global__ __launch_bounds__(256) void density_kernel(Plan P, const float* __restrict__ xyz, int k,
-                                                      double half_alpha) {
+__device__ __forceinline__ uint32_t pow2_at_least(uint32_t k) {
+    uint32_t p = 1;
+    while (p < k) p <<= 1;
+    return p;
+}
+
+__device__ __forceinline__ double seg_max(double v, uint32_t kp) {
+    for (uint32_t o = kp >> 1; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, (int)o, 64));
+    return v;
+}
+
+__device__ __forceinline__ double seg_sum(double v, uint32_t kp) {
+    for (uint32_t o = kp >> 1; o > 0; o >>= 1) v += __shfl_xor(v, (int)o, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void density_kernel(Plan P, const float* __restrict__ xyz, int kk) {
     const uint32_t np1 = P.ctr->n_p1;
-    for (uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x; qi < np1; qi += gridDim.x * blockDim.x) {
-        const uint32_t i = __float_as_uint(P.cand4[qi].w);
-        const double xi = xyz[3 * (size_t)i], yi = xyz[3 * (size_t)i + 1], zi = xyz[3 * (size_t)i + 2];
-        const uint32_t* nb = P.nbr + (size_t)qi * k;
-        double rho, r64;
-        if (nb[k - 1] == NO_NBR) {
-            rho = 0.0;
-            r64 = INFINITY;
-        } else {
-            double m2 = 0.0;
-            for (int r = 0; r < k; ++r) {
+    const uint32_t k = (uint32_t)kk, kp = pow2_at_least(k), qpw = 64u / kp;
+    const uint32_t lane = threadIdx.x & 63u, seg = lane / kp, r = lane % kp;
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t q0 = wid * qpw; q0 < np1; q0 += nw * qpw) {
+        const uint32_t qi = q0 + seg;
+        const bool live = qi < np1;
+        double m2 = 0.0;
+        bool insufficient = true;
+        uint32_t i = 0;
+        if (live) {
+            i = __float_as_uint(P.cand4[qi].w);
+            const uint32_t* nb = P.nbr + (size_t)qi * k;
+            insufficient = nb[k - 1] == NO_NBR;
+            if (!insufficient && r < k) {
                 const uint32_t j = nb[r];
-                if (j >= P.n) continue;
-                const double dx = (double)xyz[3 * (size_t)j] - xi;
-                const double dy = (double)xyz[3 * (size_t)j + 1] - yi;
-                const double dz = (double)xyz[3 * (size_t)j + 2] - zi;
-                const double d2 = dx * dx + dy * dy + dz * dz;
-                if (d2 > m2) m2 = d2;
+                if (j < P.n) {
+                    const double dx = (double)xyz[3 * (size_t)j] - (double)xyz[3 * (size_t)i];
+                    const double dy = (double)xyz[3 * (size_t)j + 1] - (double)xyz[3 * (size_t)i + 1];
+                    const double dz = (double)xyz[3 * (size_t)j + 2] - (double)xyz[3 * (size_t)i + 2];
+                    m2 = dx * dx + dy * dy + dz * dz;
+                }
             }
-            r64 = sqrt(m2);
-            rho = (double)k / ((4.0 / 3.0) * PI_D * (r64 * r64 * r64));
         }
-        P.rho_c[qi] = rho;
-        P.r64_c[qi] = r64;
-        P.rho_o[i] = rho;
-        P.gpow_o[i] = pow(rho, half_alpha);
+        m2 = seg_max(m2, kp);
+        if (live && r == 0) {
+            double rho, r64;
+            if (insufficient) {
+                rho = 0.0;
+                r64 = INFINITY;
+            } else {
+                r64 = sqrt(m2);
+                rho = (double)k / ((4.0 / 3.0) * PI_D * (r64 * r64 * r64));
+            }
+            P.rho_c[qi] = rho;
+            P.r64_c[qi] = r64;
+        }
     }
 }
 
 void launch_density(const Plan& P, const Params& prm, const float* xyz, hipStream_t st) {
-    unsigned blocks = (P.n + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(density_kernel, dim3(blocks), dim3(256), 0, st, P, xyz, prm.k, prm.alpha / 2.0);
+    uint32_t kp = 1;
+    while (kp < (uint32_t)prm.k) kp <<= 1;
+    const uint64_t waves = ((uint64_t)P.n * kp + 63) / 64;
+    unsigned blocks = (unsigned)((waves + 3) / 4);
+    if (blocks > 8192) blocks = 8192;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(density_kernel, dim3(blocks), dim3(256), 0, st, P, xyz, prm.k);
 }
 
 // ---------------------------------------------------------------- block radix select
@@ -104,6 +137,14 @@ __device__ T block_select(Get get, uint32_t cnt, uint32_t r, uint32_t* s_hist, u
     return prefix;
 }
 
+template <typename T>
+struct LdsBits {
+    const T* v;
+    __device__ T operator()(uint32_t i) const { return v[i]; }
+};
+
+constexpr uint32_t SEL_LDS_MAX = 2048;  // leaves up to this size are selected from LDS
+
 struct R2Bits {
     const float* r2k;
     uint32_t qb;
@@ -125,9 +166,28 @@ struct RhoBits {
 // drops points with fewer than k candidates). The median of the densities is
 // the middle value, or the mean of the two middle values for even n1.
 
+template <class RG, class HG>
+__device__ void leaf_cut_and_median(RG r2, HG rho, uint32_t n1, double q, float* cut, double* med,
+                                    uint32_t* s_hist, uint32_t* s_sel) {
+    double cd = ceil((double)n1 * q / 100.0 + 0.5);
+    if (cd < 1.0) cd = 1.0;
+    if (cd > (double)n1) cd = (double)n1;
+    const uint32_t c = (uint32_t)cd;
+    *cut = __uint_as_float(block_select<uint32_t>(r2, n1, n1 - c, s_hist, s_sel));
+    if (n1 & 1u) {
+        *med = __longlong_as_double((long long)block_select<unsigned long long>(rho, n1, (n1 - 1) / 2, s_hist, s_sel));
+    } else {
+        const double a = __longlong_as_double((long long)block_select<unsigned long long>(rho, n1, n1 / 2 - 1, s_hist, s_sel));
+        const double b = __longlong_as_double((long long)block_select<unsigned long long>(rho, n1, n1 / 2, s_hist, s_sel));
+        *med = (a + b) / 2.0;
+    }
+}
+
 __global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params prm) {
     __shared__ uint32_t s_hist[256];
     __shared__ uint32_t s_sel[2];
+    __shared__ uint32_t s_r2[SEL_LDS_MAX];
+    __shared__ unsigned long long s_rho[SEL_LDS_MAX];
     const uint32_t nl = P.ctr->n_leaves;
     const int k = prm.k;
     for (uint32_t t = blockIdx.x; t < nl; t += gridDim.x) {
@@ -137,18 +197,19 @@ __global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params p
             if (threadIdx.x == 0) { P.leaf_rho_med[t] = 0.0; P.leaf_r2cut[t] = 0.0f; }
             continue;
         }
-        double cd = ceil((double)n1 * prm.rho_percentile / 100.0 + 0.5);
-        if (cd < 1.0) cd = 1.0;
-        if (cd > (double)n1) cd = (double)n1;
-        const uint32_t c = (uint32_t)cd;
-        const float cut = __uint_as_float(block_select<uint32_t>(R2Bits{P.r2k, qb}, n1, n1 - c, s_hist, s_sel));
+        float cut;
         double med;
-        if (n1 & 1u) {
-            med = __longlong_as_double((long long)block_select<unsigned long long>(RhoBits{P.rho_c, qb}, n1, (n1 - 1) / 2, s_hist, s_sel));
+        if (n1 <= SEL_LDS_MAX) {
+            for (uint32_t i = threadIdx.x; i < n1; i += blockDim.x) {
+                s_r2[i] = __float_as_uint(P.r2k[qb + i]);
+                s_rho[i] = (unsigned long long)__double_as_longlong(P.rho_c[qb + i]);
+            }
+            __syncthreads();
+            leaf_cut_and_median(LdsBits<uint32_t>{s_r2}, LdsBits<unsigned long long>{s_rho}, n1, prm.rho_percentile,
+                                &cut, &med, s_hist, s_sel);
         } else {
-            const double a = __longlong_as_double((long long)block_select<unsigned long long>(RhoBits{P.rho_c, qb}, n1, n1 / 2 - 1, s_hist, s_sel));
-            const double b = __longlong_as_double((long long)block_select<unsigned long long>(RhoBits{P.rho_c, qb}, n1, n1 / 2, s_hist, s_sel));
-            med = (a + b) / 2.0;
+            leaf_cut_and_median(R2Bits{P.r2k, qb}, RhoBits{P.rho_c, qb}, n1, prm.rho_percentile, &cut, &med, s_hist,
+                                s_sel);
         }
         const double den = med * med + prm.eps;
         const double ha = prm.alpha / 2.0;
@@ -157,6 +218,8 @@ __global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params p
             const bool insufficient = P.nbr[(size_t)qi * k + (k - 1)] == NO_NBR;
             P.p2[qi] = (!insufficient && P.r2k[qi] <= cut) ? 1 : 0;
             P.afac_c[qi] = pow(P.rho_c[qi] / den, ha);
+            // rho_j^(alpha/2) of Eq. 17's factored density weight, by original index
+            P.gpow_o[__float_as_uint(P.cand4[qi].w)] = pow(P.rho_c[qi], ha);
         }
         if (threadIdx.x == 0) { P.leaf_rho_med[t] = med; P.leaf_r2cut[t] = cut; }
         __syncthreads();
@@ -174,38 +237,46 @@ void launch_leaf_select(const Plan& P, const Params& prm, hipStream_t st) {
 // F_i = sum over N_K(i) of (rho_i rho_j / (rho_med^2 + eps))^(alpha/2)
 //       * exp(-d_ij^2 / (2 (sigma r_K,i)^2)) / (d_ij^2 + eps), in FP64, with the
 // density weight factored as afac_i * rho_j^(alpha/2). A neighbour at d = 0
-// gets the Gaussian factor 1 (also when r_K,i = 0).
+// gets the Gaussian factor 1 (also when r_K,i = 0). The k terms are summed by
+// a fixed pairwise tree (lane r holds term r), not left to right.
 
-__global__ __launch_bounds__(256) void score_kernel(Plan P, const float* __restrict__ xyz, int k, double sigma,
+__global__ __launch_bounds__(256) void score_kernel(Plan P, const float* __restrict__ xyz, int kk, double sigma,
                                                     double eps) {
     const uint32_t np1 = P.ctr->n_p1;
-    for (uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x; qi < np1; qi += gridDim.x * blockDim.x) {
-        if (!P.p2[qi]) continue;
-        const uint32_t i = __float_as_uint(P.cand4[qi].w);
-        const double xi = xyz[3 * (size_t)i], yi = xyz[3 * (size_t)i + 1], zi = xyz[3 * (size_t)i + 2];
-        const double sr = sigma * P.r64_c[qi];
-        const double a = P.afac_c[qi];
-        const uint32_t* nb = P.nbr + (size_t)qi * k;
-        double F = 0.0;
-        for (int r = 0; r < k; ++r) {
-            const uint32_t j = nb[r];
-            if (j >= P.n) continue;
-            const double dx = (double)xyz[3 * (size_t)j] - xi;
-            const double dy = (double)xyz[3 * (size_t)j + 1] - yi;
-            const double dz = (double)xyz[3 * (size_t)j + 2] - zi;
-            const double d2 = dx * dx + dy * dy + dz * dz;
-            const double w_den = a * P.gpow_o[j];
-            const double w_dis = (d2 == 0.0) ? 1.0 : exp(-d2 / (2.0 * sr * sr));
-            const double kern = 1.0 / (d2 + eps);
-            F += w_den * w_dis * kern;
+    const uint32_t k = (uint32_t)kk, kp = pow2_at_least(k), qpw = 64u / kp;
+    const uint32_t lane = threadIdx.x & 63u, seg = lane / kp, r = lane % kp;
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t q0 = wid * qpw; q0 < np1; q0 += nw * qpw) {
+        const uint32_t qi = q0 + seg;
+        const bool live = qi < np1 && P.p2[qi];
+        double term = 0.0;
+        if (live && r < k) {
+            const uint32_t j = P.nbr[(size_t)qi * k + r];
+            if (j < P.n) {
+                const uint32_t i = __float_as_uint(P.cand4[qi].w);
+                const double sr = sigma * P.r64_c[qi];
+                const double dx = (double)xyz[3 * (size_t)j] - (double)xyz[3 * (size_t)i];
+                const double dy = (double)xyz[3 * (size_t)j + 1] - (double)xyz[3 * (size_t)i + 1];
+                const double dz = (double)xyz[3 * (size_t)j + 2] - (double)xyz[3 * (size_t)i + 2];
+                const double d2 = dx * dx + dy * dy + dz * dz;
+                const double w_den = P.afac_c[qi] * P.gpow_o[j];
+                const double w_dis = (d2 == 0.0) ? 1.0 : exp(-d2 / (2.0 * sr * sr));
+                const double kern = 1.0 / (d2 + eps);
+                term = w_den * w_dis * kern;
+            }
         }
-        P.score_c[qi] = F;
+        const double F = seg_sum(term, kp);
+        if (live && r == 0) P.score_c[qi] = F;
     }
 }
 
 void launch_score(const Plan& P, const Params& prm, const float* xyz, hipStream_t st) {
-    unsigned blocks = (P.n + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
+    uint32_t kp = 1;
+    while (kp < (uint32_t)prm.k) kp <<= 1;
+    const uint64_t waves = ((uint64_t)P.n * kp + 63) / 64;
+    unsigned blocks = (unsigned)((waves + 3) / 4);
+    if (blocks > 8192) blocks = 8192;
+    if (blocks == 0) blocks = 1;
     hipLaunchKernelGGL(score_kernel, dim3(blocks), dim3(256), 0, st, P, xyz, prm.k, prm.sigma, prm.eps);
 }
 
@@ -227,19 +298,38 @@ struct ScoreKey {
         return (unsigned long long)__double_as_longlong(f) + 2ull;
     }
 };
-struct TieIdx {
-    ScoreKey key;
+
+// theta = the m-th largest key, idx_cut = the largest original index kept
+// among the keys equal to theta.
+template <class KG, class IG>
+__device__ void topl_cut(KG key, IG tie_idx_of, uint32_t n1, uint32_t m, unsigned long long* theta,
+                         uint32_t* idx_cut, uint32_t* s_hist, uint32_t* s_sel, uint32_t* s_cnt) {
+    const unsigned long long th = block_select<unsigned long long>(key, n1, n1 - m, s_hist, s_sel);
+    if (threadIdx.x == 0) *s_cnt = 0;
+    __syncthreads();
+    uint32_t g = 0;
+    for (uint32_t i = threadIdx.x; i < n1; i += blockDim.x) g += key(i) > th ? 1u : 0u;
+    g = wave_sum(g);
+    if ((threadIdx.x & 63) == 0 && g) atomicAdd(s_cnt, g);
+    __syncthreads();
+    const uint32_t need = m - *s_cnt;
+    auto tie = [&](uint32_t i) -> uint32_t { return key(i) == th ? tie_idx_of(i) : 0xFFFFFFFFu; };
+    *idx_cut = block_select<uint32_t>(tie, n1, need - 1, s_hist, s_sel);
+    *theta = th;
+}
+
+struct CandIdx {
     const float4* cand4;
-    unsigned long long theta;
-    __device__ uint32_t operator()(uint32_t i) const {
-        return key(i) == theta ? __float_as_uint(cand4[key.qb + i].w) : 0xFFFFFFFFu;
-    }
+    uint32_t qb;
+    __device__ uint32_t operator()(uint32_t i) const { return __float_as_uint(cand4[qb + i].w); }
 };
 
 __global__ __launch_bounds__(SEL_BLOCK) void topl_kernel(Plan P, double lambda) {
     __shared__ uint32_t s_hist[256];
     __shared__ uint32_t s_sel[2];
     __shared__ uint32_t s_cnt;
+    __shared__ unsigned long long s_key[SEL_LDS_MAX];
+    __shared__ uint32_t s_idx[SEL_LDS_MAX];
     const uint32_t nl = P.ctr->n_leaves;
     for (uint32_t t = blockIdx.x; t < nl; t += gridDim.x) {
         const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
@@ -261,16 +351,17 @@ __global__ __launch_bounds__(SEL_BLOCK) void topl_kernel(Plan P, double lambda) 
         unsigned long long theta = ~0ull;
         uint32_t idx_cut = 0;
         if (m > 0) {
-            theta = block_select<unsigned long long>(key, n1, n1 - m, s_hist, s_sel);
-            if (threadIdx.x == 0) s_cnt = 0;
-            __syncthreads();
-            uint32_t g = 0;
-            for (uint32_t i = threadIdx.x; i < n1; i += blockDim.x) g += key(i) > theta ? 1u : 0u;
-            g = wave_sum(g);
-            if ((threadIdx.x & 63) == 0 && g) atomicAdd(&s_cnt, g);
-            __syncthreads();
-            const uint32_t need = m - s_cnt;
-            idx_cut = block_select<uint32_t>(TieIdx{key, P.cand4, theta}, n1, need - 1, s_hist, s_sel);
+            if (n1 <= SEL_LDS_MAX) {
+                for (uint32_t i = threadIdx.x; i < n1; i += blockDim.x) {
+                    s_key[i] = key(i);
+                    s_idx[i] = __float_as_uint(P.cand4[qb + i].w);
+                }
+                __syncthreads();
+                topl_cut(LdsBits<unsigned long long>{s_key}, LdsBits<uint32_t>{s_idx}, n1, m, &theta, &idx_cut,
+                         s_hist, s_sel, &s_cnt);
+            } else {
+                topl_cut(key, CandIdx{P.cand4, qb}, n1, m, &theta, &idx_cut, s_hist, s_sel, &s_cnt);
+            }
         }
         for (uint32_t i = threadIdx.x; i < n1; i += blockDim.x) {
             const uint32_t qi = qb + i;
