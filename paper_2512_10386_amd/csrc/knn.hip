@@ -179,7 +179,8 @@ constexpr int BOUND_LEVELS = 10;   // thresholds tau * 2^(-m/2), m = 1..10
 // [qb, qe), a run of candidates holding the query; then, over the run's points
 // within BOUND_MARGIN positions, count those under tau * 2^(-m/2) and keep the
 // smallest threshold still holding k. -1 when the run has <= k points.
-__device__ float query_bound(const float4* __restrict__ cand4, uint32_t qb, uint32_t qe, uint32_t qi, int k) {
+template <class Pts>
+__device__ float query_bound(Pts cand4, uint32_t qb, uint32_t qe, uint32_t qi, int k) {
     if (qe - qb <= (uint32_t)k) return -1.0f;
     const float4 q = cand4[qi];
     uint32_t s0 = (qi - qb > (uint32_t)(k / 2)) ? qi - (uint32_t)(k / 2) : qb;
@@ -211,33 +212,50 @@ __device__ float query_bound(const float4* __restrict__ cand4, uint32_t qb, uint
     return best;
 }
 
+// Points [lo, lo + count) of the P1 order, staged in LDS.
+struct StagedPts {
+    const float4* s;
+    uint32_t lo;
+    __device__ float4 operator[](uint32_t j) const { return s[j - lo]; }
+};
+
 // One thread per P1 point: its bound, and, for the first query of each tile,
 // the tile's work items (one per candidate chunk) at the queue position the
-// plan gave the leaf.
+// plan gave the leaf. A block takes 256 consecutive queries; every window
+// lies within BOUND_MARGIN of its query, so the block stages those points.
 __global__ __launch_bounds__(256) void knn_bound_kernel(Plan P, const float4* __restrict__ cand4, int k) {
+    __shared__ float4 s_pts[256 + 2 * BOUND_MARGIN + 1];
     const uint32_t np1 = P.ctr->n_p1;
-    for (uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x; qi < np1; qi += gridDim.x * blockDim.x) {
-        const uint32_t t = P.cand_leaf[qi];
-        const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
-        // the window lives in the merged candidate range holding the query,
-        // which may reach past a small leaf (every point of it is a candidate)
-        uint32_t rb = qb, re = qe;
-        const uint32_t nr = P.leaf_nr[t];
-        for (uint32_t r = 0; r < nr; ++r) {
-            const uint2 R = P.leaf_ranges[(size_t)t * HALO + r];
-            if (R.x <= qi && qi < R.y) {
-                rb = R.x;
-                re = R.y;
-                break;
+    for (uint32_t q_first = blockIdx.x * 256u; q_first < np1; q_first += gridDim.x * 256u) {
+        const uint32_t lo = q_first > (uint32_t)BOUND_MARGIN ? q_first - (uint32_t)BOUND_MARGIN : 0u;
+        const uint32_t hi = min(np1, q_first + 256u + (uint32_t)BOUND_MARGIN + 1u);
+        for (uint32_t j = lo + threadIdx.x; j < hi; j += 256u) s_pts[j - lo] = cand4[j];
+        __syncthreads();
+        const uint32_t qi = q_first + threadIdx.x;
+        if (qi < np1) {
+            const uint32_t t = P.cand_leaf[qi];
+            const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
+            // the window lives in the merged candidate range holding the query,
+            // which may reach past a small leaf (every point of it is a candidate)
+            uint32_t rb = qb, re = qe;
+            const uint32_t nr = P.leaf_nr[t];
+            for (uint32_t r = 0; r < nr; ++r) {
+                const uint2 R = P.leaf_ranges[(size_t)t * HALO + r];
+                if (R.x <= qi && qi < R.y) {
+                    rb = R.x;
+                    re = R.y;
+                    break;
+                }
+            }
+            P.tau_c[qi] = query_bound(StagedPts{s_pts, lo}, rb, re, qi, k);
+            if ((qi - qb) % (uint32_t)KNN_TQ == 0u) {
+                const uint32_t nch = P.leaf_nch[t];
+                const uint32_t grp = P.leaf_item[t] + ((qi - qb) / (uint32_t)KNN_TQ) * nch;
+                const uint32_t q1 = min(qe, qi + (uint32_t)KNN_TQ);
+                for (uint32_t c = 0; c < nch; ++c) P.items[grp + c] = KnnItem{t, qi, q1, c, grp, 0u};
             }
         }
-        P.tau_c[qi] = query_bound(cand4, rb, re, qi, k);
-        if ((qi - qb) % (uint32_t)KNN_TQ == 0u) {
-            const uint32_t nch = P.leaf_nch[t];
-            const uint32_t grp = P.leaf_item[t] + ((qi - qb) / (uint32_t)KNN_TQ) * nch;
-            const uint32_t q1 = min(qe, qi + (uint32_t)KNN_TQ);
-            for (uint32_t c = 0; c < nch; ++c) P.items[grp + c] = KnnItem{t, qi, q1, c, grp, 0u};
-        }
+        __syncthreads();
     }
 }
 
