@@ -11,7 +11,9 @@
  *     owned by the caller. The library allocates no device memory on the
  *     denoise path: all scratch lives in the caller's workspace.
  *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
- *     No call synchronises the host except gdn_create/gdn_destroy.
+ *     No call synchronises the host except gdn_create/gdn_destroy, the
+ *     profiling/tuning calls gdn_timing and gdn_autotune, and graph creation
+ *     and destruction.
  *   - Parameter and size errors are reported synchronously by the return
  *     value, with nothing enqueued. Conditions only the GPU can see
  *     (non-finite coordinates, an exhausted internal wait) are recorded in a
@@ -41,6 +43,10 @@ typedef enum {
 /* Device status word bits (GDN_DUMP_STATUS). */
 #define GDN_DEV_NONFINITE   1u  /* some coordinate was NaN/inf: outputs unspecified */
 #define GDN_DEV_WAIT_LIMIT  2u  /* an inter-workgroup wait hit its spin limit */
+#define GDN_DEV_BAD_FRAMES  4u  /* a batch's frame table was not 0 = off[0] <= ... <= off[nf] = n;
+                                   it was clamped/repaired: outputs unspecified */
+
+#define GDN_MAX_FRAMES 4096     /* frames per gdn_denoise_batch call */
 
 typedef struct {
     int32_t k;              /* K of Eq. 13 and Eq. 15: neighbours per point, 1..64 */
@@ -53,13 +59,15 @@ typedef struct {
     double  sigma;          /* bandwidth scale of Eq. 18, > 0 */
     double  eps;            /* epsilon of Eq. 17 and Eq. 20, >= 0 */
     double  keep_ratio;     /* lambda: top fraction of P2 kept per leaf, (0, 1] */
+    int32_t knn_chunk;      /* initial candidate chunk length of the kNN work split;
+                               changes speed only, never results; 0 = default (16384) */
 } gdn_params;
 
 typedef struct gdn_ctx gdn_ctx;
 
 /* Defaults: k=12, rho_percentile=0.2, min_vox_count=4 (the paper's defaults,
  * Sec. 4.3.1); beta=1, alpha=1, sigma=1, eps=1e-12, keep_ratio=0.98,
- * leaf_cap=512, min_leaf_side=0 (not valued in the paper). */
+ * leaf_cap=512, min_leaf_side=0 (not valued in the paper); knn_chunk=0. */
 gdn_status gdn_default_params(gdn_params *out);
 
 /* Create a context bound to HIP device `device`. */
@@ -91,8 +99,69 @@ gdn_status gdn_denoise(gdn_ctx *ctx, const gdn_params *p, const float *xyz, int6
                        uint8_t *keep, float *score, uint8_t *stage,
                        uint32_t *kept_idx, int64_t *n_kept, void *stream);
 
-/* Intermediates of the last gdn_denoise on this context (its workspace must
- * be untouched since). Per-point arrays are in ORIGINAL point order. */
+/* Workspace bytes gdn_denoise_batch needs for nf frames of n points in all
+ * (1 <= nf <= GDN_MAX_FRAMES). */
+gdn_status gdn_workspace_size_batch(gdn_ctx *ctx, const gdn_params *p, int64_t n, int64_t nf, size_t *bytes);
+
+/*
+ * Denoise a batch of nf independent frames in one pass of the pipeline: the
+ * method of Sec. 3 runs on every frame on its own (own bounding box and
+ * octree, own percentiles), with results equal to nf gdn_denoise calls.
+ *   xyz       [n][3] float32: the frames' points back to back
+ *   frame_off DEVICE int64[nf+1]: frame f is points [frame_off[f],
+ *             frame_off[f+1]); frame_off[0] = 0, non-decreasing,
+ *             frame_off[nf] = n (empty frames allowed). A table breaking this
+ *             is repaired on the device and GDN_DEV_BAD_FRAMES is set.
+ *   keep, score, stage  [n], as gdn_denoise, at the points' batch positions
+ *   kept_idx  [n] uint32: frame f's kept points, as FRAME-LOCAL indices in
+ *             ascending order, start at kept_idx[frame_off[f]]
+ *   n_kept    DEVICE int64[nf]: kept points per frame
+ * Errors as gdn_denoise; GDN_ECAPACITY also for nf > GDN_MAX_FRAMES.
+ */
+gdn_status gdn_denoise_batch(gdn_ctx *ctx, const gdn_params *p, const float *xyz, int64_t n,
+                             const int64_t *frame_off, int64_t nf,
+                             void *workspace, size_t workspace_bytes,
+                             uint8_t *keep, float *score, uint8_t *stage,
+                             uint32_t *kept_idx, int64_t *n_kept, void *stream);
+
+/*
+ * A gdn_denoise_batch call recorded once as a HIP graph and replayed with
+ * one launch. Every pointer and the sizes n, nf are fixed at creation; the
+ * CONTENTS of xyz and frame_off may change between launches (same n and nf).
+ * Creation captures on a private stream and runs nothing; each launch
+ * enqueues the whole pipeline on `stream`. Launches of one graph must not
+ * overlap (they share the workspace). gdn_debug_dump reads the workspace of
+ * the latest launch. Destroy before the context.
+ */
+typedef struct gdn_graph gdn_graph;
+gdn_status gdn_graph_create(gdn_ctx *ctx, const gdn_params *p, const float *xyz, int64_t n,
+                            const int64_t *frame_off, int64_t nf,
+                            void *workspace, size_t workspace_bytes,
+                            uint8_t *keep, float *score, uint8_t *stage,
+                            uint32_t *kept_idx, int64_t *n_kept, gdn_graph **out);
+gdn_status gdn_graph_launch(gdn_graph *g, void *stream);
+void gdn_graph_destroy(gdn_graph *g);
+
+/*
+ * Autotuner: runs the batch with every (leaf_cap, knn_chunk) pair from
+ * caps[ncaps] x chunks[nchunks] (chunks may be NULL: default only), one
+ * warm-up and `reps` timed runs each (HIP events on `stream`; this call waits
+ * for them), and writes the fastest pair into *p. The leaf capacity changes
+ * the octree and therefore the results (Sec. 3); knn_chunk does not. The
+ * outputs and workspace hold the last run's results afterwards, not the
+ * chosen pair's; gdn_debug_dump is unavailable until the next denoise.
+ *   ms_out  float[ncaps * nchunks] or NULL: median ms per pair (row = cap)
+ */
+gdn_status gdn_autotune(gdn_ctx *ctx, gdn_params *p, const int32_t *caps, int ncaps,
+                        const int32_t *chunks, int nchunks, int reps,
+                        const float *xyz, int64_t n, const int64_t *frame_off, int64_t nf,
+                        void *workspace, size_t workspace_bytes,
+                        uint8_t *keep, float *score, uint8_t *stage,
+                        uint32_t *kept_idx, int64_t *n_kept, float *ms_out, void *stream);
+
+/* Intermediates of the last gdn_denoise / gdn_denoise_batch / graph launch
+ * on this context (its workspace must be untouched since). Per-point arrays
+ * are in ORIGINAL (batch) point order; leaf arrays cover the whole batch. */
 enum {
     GDN_DUMP_STATUS = 0,     /* uint32 device status word (GDN_DEV_*) */
     GDN_DUMP_COUNTS = 1,     /* int64[4]: n_leaves, |P1|, kNN pair count W, n_kept */

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(HERE, "libgdn.so")
 GDN_OK, GDN_EINVAL, GDN_ENOMEM, GDN_ECAPACITY, GDN_EHIP, GDN_EINTERNAL = range(6)
 GDN_DEV_NONFINITE = 1
 GDN_DEV_WAIT_LIMIT = 2
+GDN_DEV_BAD_FRAMES = 4
+GDN_MAX_FRAMES = 4096
 
 DUMP = dict(STATUS=0, COUNTS=1, KEYS=2, ORDER=3, LEAF_OF=4, LEAF_TABLE=5, OCC=6, P1=7,
             NBR_IDX=8, NBR_D2=9, R2K=10, RHO=11, P2=12, LEAF_RHO_MED=13, SCORE64=14,
@@ -29,7 +31,8 @@ class gdn_params(C.Structure):
                 ("min_leaf_side", C.c_double), ("beta", C.c_double),
                 ("min_vox_count", C.c_int32), ("rho_percentile", C.c_double),
                 ("alpha", C.c_double), ("sigma", C.c_double),
-                ("eps", C.c_double), ("keep_ratio", C.c_double)]
+                ("eps", C.c_double), ("keep_ratio", C.c_double),
+                ("knn_chunk", C.c_int32)]
 
 
 class GdnError(RuntimeError):
@@ -56,6 +59,17 @@ def lib():
         L.gdn_destroy.restype = None
         L.gdn_workspace_size.argtypes = [vp, C.POINTER(gdn_params), i64, C.POINTER(sz)]
         L.gdn_denoise.argtypes = [vp, C.POINTER(gdn_params), vp, i64, vp, sz, vp, vp, vp, vp, vp, vp]
+        L.gdn_workspace_size_batch.argtypes = [vp, C.POINTER(gdn_params), i64, i64, C.POINTER(sz)]
+        L.gdn_denoise_batch.argtypes = [vp, C.POINTER(gdn_params), vp, i64, vp, i64, vp, sz,
+                                        vp, vp, vp, vp, vp, vp]
+        L.gdn_graph_create.argtypes = [vp, C.POINTER(gdn_params), vp, i64, vp, i64, vp, sz,
+                                       vp, vp, vp, vp, vp, C.POINTER(vp)]
+        L.gdn_graph_launch.argtypes = [vp, vp]
+        L.gdn_graph_destroy.argtypes = [vp]
+        L.gdn_graph_destroy.restype = None
+        L.gdn_autotune.argtypes = [vp, C.POINTER(gdn_params), C.POINTER(C.c_int32), C.c_int,
+                                   C.POINTER(C.c_int32), C.c_int, C.c_int, vp, i64, vp, i64, vp, sz,
+                                   vp, vp, vp, vp, vp, C.POINTER(C.c_float), vp]
         L.gdn_debug_dump.argtypes = [vp, C.c_int, vp, sz, vp]
         L.gdn_set_timing.argtypes = [vp, C.c_int]
         L.gdn_timing.argtypes = [vp, i64, C.POINTER(C.c_float), C.POINTER(C.c_float)]
@@ -64,7 +78,8 @@ def lib():
         L.gdn_last_error.argtypes = [vp]
         L.gdn_last_error.restype = C.c_char_p
         for f in ("gdn_default_params", "gdn_create", "gdn_workspace_size", "gdn_denoise",
-                  "gdn_debug_dump", "gdn_set_timing", "gdn_timing"):
+                  "gdn_debug_dump", "gdn_set_timing", "gdn_timing", "gdn_workspace_size_batch",
+                  "gdn_denoise_batch", "gdn_graph_create", "gdn_graph_launch", "gdn_autotune"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -107,6 +122,47 @@ def gdn_denoise(ctx, p, xyz, n, workspace, workspace_bytes, keep, score, stage,
                 kept_idx, n_kept, stream) -> None:
     _check(ctx, lib().gdn_denoise(ctx, C.byref(p), xyz, n, workspace, workspace_bytes,
                                   keep, score, stage, kept_idx, n_kept, stream))
+
+
+def gdn_workspace_size_batch(ctx: int, p: gdn_params, n: int, nf: int) -> int:
+    b = C.c_size_t()
+    _check(ctx, lib().gdn_workspace_size_batch(ctx, C.byref(p), n, nf, C.byref(b)))
+    return b.value
+
+
+def gdn_denoise_batch(ctx, p, xyz, n, frame_off, nf, workspace, workspace_bytes, keep, score, stage,
+                      kept_idx, n_kept, stream) -> None:
+    _check(ctx, lib().gdn_denoise_batch(ctx, C.byref(p), xyz, n, frame_off, nf, workspace, workspace_bytes,
+                                        keep, score, stage, kept_idx, n_kept, stream))
+
+
+def gdn_graph_create(ctx, p, xyz, n, frame_off, nf, workspace, workspace_bytes, keep, score, stage,
+                     kept_idx, n_kept) -> int:
+    g = C.c_void_p()
+    _check(ctx, lib().gdn_graph_create(ctx, C.byref(p), xyz, n, frame_off, nf, workspace, workspace_bytes,
+                                       keep, score, stage, kept_idx, n_kept, C.byref(g)))
+    return g.value
+
+
+def gdn_graph_launch(ctx, g, stream) -> None:
+    _check(ctx, lib().gdn_graph_launch(g, stream))
+
+
+def gdn_graph_destroy(g) -> None:
+    lib().gdn_graph_destroy(g)
+
+
+def gdn_autotune(ctx, p, caps, chunks, reps, xyz, n, frame_off, nf, workspace, workspace_bytes, keep, score,
+                 stage, kept_idx, n_kept, stream):
+    """Tune (leaf_cap, knn_chunk) in place in p; returns the median ms per pair."""
+    ca = (C.c_int32 * len(caps))(*caps)
+    ch = (C.c_int32 * len(chunks))(*chunks) if chunks else None
+    nch = len(chunks) if chunks else 1
+    ms = (C.c_float * (len(caps) * nch))()
+    _check(ctx, lib().gdn_autotune(ctx, C.byref(p), ca, len(caps), ch, len(chunks) if chunks else 0, reps,
+                                   xyz, n, frame_off, nf, workspace, workspace_bytes, keep, score, stage,
+                                   kept_idx, n_kept, ms, stream))
+    return list(ms)
 
 
 def gdn_debug_dump(ctx, what, dst, dst_bytes, stream) -> None:
@@ -215,3 +271,91 @@ class Denoiser:
         stream = torch.cuda.current_stream(self.device).cuda_stream
         gdn_debug_dump(self.ctx, DUMP[what], t.data_ptr(), t.numel() * t.element_size(), stream)
         return t
+
+
+class BatchDenoiser(Denoiser):
+    """Batches of frames through gdn_denoise_batch, optionally replayed from a
+    captured HIP graph (same batch shape, new contents)."""
+
+    def __init__(self, device: int = 0, **params):
+        super().__init__(device, **params)
+        self._graph = None
+        self._graph_key = None
+
+    def close(self):
+        self.drop_graph()
+        super().close()
+
+    def drop_graph(self):
+        if self._graph:
+            gdn_graph_destroy(self._graph)
+        self._graph = None
+        self._graph_key = None
+
+    def workspace_batch(self, n: int, nf: int):
+        need = gdn_workspace_size_batch(self.ctx, self.params, n, nf)
+        if self._ws is None or self._ws.numel() < need:
+            self.drop_graph()  # a graph holds the old workspace's address
+            self._ws = self.torch.empty(max(need, 256), dtype=self.torch.uint8, device=self.device)
+        return self._ws, need
+
+    def alloc(self, n: int, nf: int) -> Result:
+        torch = self.torch
+        return Result(keep=torch.empty(max(n, 1), dtype=torch.uint8, device=self.device),
+                      score=torch.empty(max(n, 1), dtype=torch.float32, device=self.device),
+                      stage=torch.empty(max(n, 1), dtype=torch.uint8, device=self.device),
+                      kept_idx=torch.empty(max(n, 1), dtype=torch.int32, device=self.device),
+                      n_kept=torch.empty(max(nf, 1), dtype=torch.int64, device=self.device))
+
+    def _check_inputs(self, xyz, frame_off):
+        torch = self.torch
+        if xyz.device != self.device or xyz.dtype != torch.float32 or xyz.dim() != 2 or xyz.shape[1] != 3:
+            raise ValueError("xyz must be a float32 [n, 3] tensor on the context's device")
+        if frame_off.device != self.device or frame_off.dtype != torch.int64 or frame_off.dim() != 1:
+            raise ValueError("frame_off must be an int64 [nf + 1] tensor on the context's device")
+        if not xyz.is_contiguous() or not frame_off.is_contiguous():
+            raise ValueError("xyz and frame_off must be contiguous")
+
+    def __call__(self, xyz, frame_off, out: Result | None = None) -> Result:
+        self._check_inputs(xyz, frame_off)
+        n, nf = xyz.shape[0], frame_off.shape[0] - 1
+        ws, _ = self.workspace_batch(n, nf)
+        if out is None:
+            out = self.alloc(n, nf)
+        stream = self.torch.cuda.current_stream(self.device).cuda_stream
+        gdn_denoise_batch(self.ctx, self.params, xyz.data_ptr(), n, frame_off.data_ptr(), nf, ws.data_ptr(),
+                          ws.numel(), out.keep.data_ptr(), out.score.data_ptr(), out.stage.data_ptr(),
+                          out.kept_idx.data_ptr(), out.n_kept.data_ptr(), stream)
+        return out
+
+    def graph(self, xyz, frame_off, out: Result):
+        """Capture (once per batch shape and buffers) and launch the batch."""
+        self._check_inputs(xyz, frame_off)
+        n, nf = xyz.shape[0], frame_off.shape[0] - 1
+        ws, _ = self.workspace_batch(n, nf)
+        key = (n, nf, xyz.data_ptr(), frame_off.data_ptr(), ws.data_ptr(), out.keep.data_ptr(),
+               out.score.data_ptr(), out.stage.data_ptr(), out.kept_idx.data_ptr(), out.n_kept.data_ptr(),
+               bytes(self.params))
+        if self._graph_key != key:
+            self.drop_graph()
+            self._graph = gdn_graph_create(self.ctx, self.params, xyz.data_ptr(), n, frame_off.data_ptr(), nf,
+                                           ws.data_ptr(), ws.numel(), out.keep.data_ptr(), out.score.data_ptr(),
+                                           out.stage.data_ptr(), out.kept_idx.data_ptr(), out.n_kept.data_ptr())
+            self._graph_key = key
+        gdn_graph_launch(self.ctx, self._graph, self.torch.cuda.current_stream(self.device).cuda_stream)
+        return out
+
+    def autotune(self, xyz, frame_off, caps, chunks=None, reps=3):
+        """Pick (leaf_cap, knn_chunk) for this batch; returns {(cap, chunk): ms}."""
+        self._check_inputs(xyz, frame_off)
+        n, nf = xyz.shape[0], frame_off.shape[0] - 1
+        ws, _ = self.workspace_batch(n, nf)
+        out = self.alloc(n, nf)
+        stream = self.torch.cuda.current_stream(self.device).cuda_stream
+        ms = gdn_autotune(self.ctx, self.params, list(caps), list(chunks or []), reps, xyz.data_ptr(), n,
+                          frame_off.data_ptr(), nf, ws.data_ptr(), ws.numel(), out.keep.data_ptr(),
+                          out.score.data_ptr(), out.stage.data_ptr(), out.kept_idx.data_ptr(),
+                          out.n_kept.data_ptr(), stream)
+        self.drop_graph()
+        chs = list(chunks) if chunks else [0]
+        return {(c, h): ms[a * len(chs) + b] for a, c in enumerate(caps) for b, h in enumerate(chs)}

@@ -1,5 +1,7 @@
-// C ABI of the denoiser (include/gdn.h): parameter checks, workspace layout
-// and the launch sequence of one frame.
+// C ABI of the denoiser (include/gdn.h): parameter checks, workspace layout,
+// the launch sequence of a frame or a batch of frames, graph capture of that
+// sequence and the leaf-capacity / chunk-length autotuner.
+#include <algorithm>
 #include <cmath>
 #include <new>
 #include <string>
@@ -32,12 +34,13 @@ size_t dump_bytes(uint32_t n, int k, int what);
 namespace {
 
 constexpr int64_t MAX_POINTS = (1ll << 30) - 1;
+static_assert(GDN_MAX_FRAMES == gdn::MAX_FRAMES, "frame limit of the ABI and the kernels");
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Carve the workspace into the frame's arrays. With base == nullptr only the
-// size is computed.
-gdn::Plan make_plan(uint32_t n, int k, char* base) {
+// Carve the workspace into the batch's arrays (a plain call is one frame).
+// With base == nullptr only the size is computed.
+gdn::Plan make_plan(uint32_t n, uint32_t nf, int k, char* base) {
     using namespace gdn;
     Plan P{};
     size_t off = 0;
@@ -49,6 +52,8 @@ gdn::Plan make_plan(uint32_t n, int k, char* base) {
     const size_t N = n;
     P.n = n;
     P.k = k;
+    P.nf = nf;
+    P.sort_passes = SORT_PASSES + (nf > 256u ? 2u : (nf > 1u ? 1u : 0u));
     P.sort_tiles = (uint32_t)((N + SORT_TILE - 1) / SORT_TILE);
     if (P.sort_tiles == 0) P.sort_tiles = 1;
     P.scan_tiles = (uint32_t)((N + SCAN_TILE - 1) / SCAN_TILE);
@@ -58,17 +63,26 @@ gdn::Plan make_plan(uint32_t n, int k, char* base) {
 
     const size_t z0 = off;
     P.ctr = (Counters*)take(sizeof(Counters));
-    P.sort_hist = (uint32_t*)take(sizeof(uint32_t) * SORT_PASSES * 256);
-    P.sort_status = (uint32_t*)take(sizeof(uint32_t) * (size_t)SORT_PASSES * P.sort_tiles * 256);
+    P.fstat = (FrameStat*)take(sizeof(FrameStat) * (size_t)nf);
+    P.sort_hist = (uint32_t*)take(sizeof(uint32_t) * SORT_PASSES_MAX * 256);
+    P.sort_status = (uint32_t*)take(sizeof(uint32_t) * (size_t)P.sort_passes * P.sort_tiles * 256);
     P.scan_status = (uint32_t*)take(sizeof(uint32_t) * 4 * (size_t)P.scan_tiles);
     P.zero_begin = base ? base + z0 : nullptr;
     P.zero_bytes = off - z0;
 
-    P.fc = (FrameConst*)take(sizeof(FrameConst));
+    P.foff = (uint32_t*)take(4 * ((size_t)nf + 1));
+    P.fc = (FrameConst*)take(sizeof(FrameConst) * (size_t)nf);
+    if (nf > 1) {
+        P.fid = (uint32_t*)take(4 * N);
+        P.keep_ex = (uint32_t*)take(4 * (N + 1));
+    }
     P.keys_a = (uint64_t*)take(8 * N);
     P.keys_b = (uint64_t*)take(8 * N);
     P.idx_a = (uint32_t*)take(4 * N);
     P.idx_b = (uint32_t*)take(4 * N);
+    const bool odd = (P.sort_passes & 1u) != 0u;
+    P.keys_src = odd ? P.keys_b : P.keys_a;
+    P.idx_src = odd ? P.idx_b : P.idx_a;
     P.pos4 = (float4*)take(16 * N);
     P.leaf_of = (uint32_t*)take(4 * N);
     P.occ = (uint32_t*)take(4 * N);
@@ -123,6 +137,7 @@ bool params_ok(const gdn_params* p, std::string* why) {
     if (!(p->sigma > 0.0) || !std::isfinite(p->sigma)) return bad("sigma must be finite and > 0");
     if (!(p->eps >= 0.0) || !std::isfinite(p->eps)) return bad("eps must be finite and >= 0");
     if (!(p->keep_ratio > 0.0 && p->keep_ratio <= 1.0)) return bad("keep_ratio must be in (0, 1]");
+    if (p->knn_chunk < 0 || p->knn_chunk > (1 << 28)) return bad("knn_chunk must be in [0, 2^28]");
     return true;
 }
 
@@ -138,6 +153,7 @@ gdn::Params to_params(const gdn_params* p) {
     q.sigma = p->sigma;
     q.eps = p->eps;
     q.keep_ratio = p->keep_ratio;
+    q.knn_chunk = p->knn_chunk;
     return q;
 }
 
@@ -174,6 +190,7 @@ gdn_status gdn_default_params(gdn_params* out) {
     out->sigma = 1.0;
     out->eps = 1e-12;
     out->keep_ratio = 0.98;
+    out->knn_chunk = 0;
     return GDN_OK;
 }
 
@@ -242,30 +259,39 @@ gdn_status gdn_timing(gdn_ctx* ctx, int64_t back, float* total_ms, float* knn_ms
     return GDN_OK;
 }
 
-gdn_status gdn_workspace_size(gdn_ctx* ctx, const gdn_params* p, int64_t n, size_t* bytes) {
+static gdn_status size_checks(gdn_ctx* ctx, const gdn_params* p, int64_t n, int64_t nf) {
     std::string why;
-    if (!bytes) return fail(ctx, GDN_EINVAL, "bytes is NULL");
     if (!params_ok(p, &why)) return fail(ctx, GDN_EINVAL, why);
     if (n < 0) return fail(ctx, GDN_EINVAL, "n < 0");
     if (n > MAX_POINTS) return fail(ctx, GDN_ECAPACITY, "n exceeds 2^30-1 points");
-    *bytes = n == 0 ? 0 : make_plan((uint32_t)n, p->k, nullptr).bytes;
+    if (nf < 1) return fail(ctx, GDN_EINVAL, "a batch needs at least one frame");
+    if (nf > (int64_t)gdn::MAX_FRAMES) return fail(ctx, GDN_ECAPACITY, "more than 4096 frames in one batch");
     return GDN_OK;
 }
 
-gdn_status gdn_denoise(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int64_t n, void* workspace,
-                       size_t workspace_bytes, uint8_t* keep, float* score, uint8_t* stage, uint32_t* kept_idx,
-                       int64_t* n_kept, void* stream) {
-    if (!ctx) return GDN_EINVAL;
-    std::string why;
-    if (!params_ok(p, &why)) return fail(ctx, GDN_EINVAL, why);
-    if (n < 0) return fail(ctx, GDN_EINVAL, "n < 0");
-    if (n > MAX_POINTS) return fail(ctx, GDN_ECAPACITY, "n exceeds 2^30-1 points");
+gdn_status gdn_workspace_size(gdn_ctx* ctx, const gdn_params* p, int64_t n, size_t* bytes) {
+    return gdn_workspace_size_batch(ctx, p, n, 1, bytes);
+}
+
+gdn_status gdn_workspace_size_batch(gdn_ctx* ctx, const gdn_params* p, int64_t n, int64_t nf, size_t* bytes) {
+    if (!bytes) return fail(ctx, GDN_EINVAL, "bytes is NULL");
+    const gdn_status e = size_checks(ctx, p, n, nf);
+    if (e != GDN_OK) return e;
+    *bytes = n == 0 ? 0 : make_plan((uint32_t)n, (uint32_t)nf, p->k, nullptr).bytes;
+    return GDN_OK;
+}
+
+// Enqueue the whole pipeline. frame_off == nullptr: one frame of n points.
+static gdn_status run(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int64_t n, const int64_t* frame_off,
+                      int64_t nf, void* workspace, size_t workspace_bytes, uint8_t* keep, float* score,
+                      uint8_t* stage, uint32_t* kept_idx, int64_t* n_kept, hipStream_t st, bool record) {
+    gdn_status es = size_checks(ctx, p, n, nf);
+    if (es != GDN_OK) return es;
     if (!n_kept) return fail(ctx, GDN_EINVAL, "n_kept is NULL");
-    hipStream_t st = (hipStream_t)stream;
-    DeviceGuard guard(ctx->device);
+    if (frame_off == nullptr && nf != 1) return fail(ctx, GDN_EINVAL, "frame_off is NULL");
     ctx->has_last = false;
     if (n == 0) {
-        gdn::launch_write_zero_count(n_kept, st);
+        gdn::launch_write_zero_count(n_kept, (uint32_t)nf, st);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail(ctx, GDN_EHIP, hipGetErrorString(e));
         ctx->err.clear();
@@ -274,17 +300,18 @@ gdn_status gdn_denoise(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int6
     if (!xyz || !keep || !score || !kept_idx) return fail(ctx, GDN_EINVAL, "NULL array argument");
     if (!workspace) return fail(ctx, GDN_EINVAL, "workspace is NULL");
     if (((uintptr_t)workspace & 255u) != 0) return fail(ctx, GDN_EINVAL, "workspace must be 256-byte aligned");
-    const gdn::Plan P = make_plan((uint32_t)n, p->k, (char*)workspace);
+    const gdn::Plan P = make_plan((uint32_t)n, (uint32_t)nf, p->k, (char*)workspace);
     if (workspace_bytes < P.bytes) return fail(ctx, GDN_ENOMEM, "workspace too small");
     const gdn::Params prm = to_params(p);
     CallEvents* ce = nullptr;
-    if (ctx->timing) {
+    if (record && ctx->timing) {
         ce = &ctx->ring[(size_t)(ctx->timed_calls % TIMING_RING)];
         ++ctx->timed_calls;
         (void)hipEventRecord(ce->ev[0], st);
     }
 
     gdn::launch_zero(P, st);
+    if (frame_off) gdn::launch_frames(P, frame_off, st);
     gdn::launch_bbox(P, xyz, st);
     gdn::launch_morton(P, prm, xyz, st);
     gdn::launch_sort(P, st);
@@ -293,7 +320,7 @@ gdn_status gdn_denoise(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int6
     gdn::launch_voxel(P, prm, st);
     gdn::launch_p1_compact(P, st);
     gdn::launch_halo(P, st);
-    gdn::launch_knn_plan(P, st);
+    gdn::launch_knn_plan(P, prm, st);
     gdn::launch_knn_bound(P, prm.k, ctx->num_cus, st);
     if (ce) (void)hipEventRecord(ce->ev[1], st);
     gdn::launch_knn(P, prm.k, ctx->num_cus, st);
@@ -311,6 +338,156 @@ gdn_status gdn_denoise(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int6
     ctx->last = P;
     ctx->has_last = true;
     ctx->err.clear();
+    return GDN_OK;
+}
+
+gdn_status gdn_denoise(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int64_t n, void* workspace,
+                       size_t workspace_bytes, uint8_t* keep, float* score, uint8_t* stage, uint32_t* kept_idx,
+                       int64_t* n_kept, void* stream) {
+    if (!ctx) return GDN_EINVAL;
+    DeviceGuard guard(ctx->device);
+    return run(ctx, p, xyz, n, nullptr, 1, workspace, workspace_bytes, keep, score, stage, kept_idx, n_kept,
+               (hipStream_t)stream, true);
+}
+
+gdn_status gdn_denoise_batch(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int64_t n,
+                             const int64_t* frame_off, int64_t nf, void* workspace, size_t workspace_bytes,
+                             uint8_t* keep, float* score, uint8_t* stage, uint32_t* kept_idx, int64_t* n_kept,
+                             void* stream) {
+    if (!ctx) return GDN_EINVAL;
+    if (!frame_off) return fail(ctx, GDN_EINVAL, "frame_off is NULL");
+    DeviceGuard guard(ctx->device);
+    return run(ctx, p, xyz, n, frame_off, nf, workspace, workspace_bytes, keep, score, stage, kept_idx, n_kept,
+               (hipStream_t)stream, true);
+}
+
+// ---------------------------------------------------------------- graphs
+
+struct gdn_graph {
+    gdn_ctx* ctx = nullptr;
+    hipGraphExec_t exec = nullptr;
+    gdn::Plan plan{};
+};
+
+gdn_status gdn_graph_create(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int64_t n,
+                            const int64_t* frame_off, int64_t nf, void* workspace, size_t workspace_bytes,
+                            uint8_t* keep, float* score, uint8_t* stage, uint32_t* kept_idx, int64_t* n_kept,
+                            gdn_graph** out) {
+    if (!ctx) return GDN_EINVAL;
+    if (!out) return fail(ctx, GDN_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!frame_off) return fail(ctx, GDN_EINVAL, "frame_off is NULL");
+    DeviceGuard guard(ctx->device);
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+        return fail(ctx, GDN_EHIP, "hipStreamCreateWithFlags failed");
+    gdn_status st = GDN_OK;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        st = fail(ctx, GDN_EHIP, "hipStreamBeginCapture failed");
+    } else {
+        st = run(ctx, p, xyz, n, frame_off, nf, workspace, workspace_bytes, keep, score, stage, kept_idx, n_kept,
+                 cs, false);
+        const hipError_t ec = hipStreamEndCapture(cs, &g);
+        if (st == GDN_OK && ec != hipSuccess) st = fail(ctx, GDN_EHIP, "hipStreamEndCapture failed");
+        if (st == GDN_OK && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) != hipSuccess)
+            st = fail(ctx, GDN_EHIP, "hipGraphInstantiate failed");
+    }
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    if (st != GDN_OK) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        ctx->has_last = false;
+        return st;
+    }
+    gdn_graph* G = new (std::nothrow) gdn_graph();
+    if (!G) {
+        (void)hipGraphExecDestroy(exec);
+        return fail(ctx, GDN_EINTERNAL, "out of host memory");
+    }
+    G->ctx = ctx;
+    G->exec = exec;
+    G->plan = ctx->last;
+    ctx->has_last = false;  // nothing has run yet
+    *out = G;
+    return GDN_OK;
+}
+
+gdn_status gdn_graph_launch(gdn_graph* g, void* stream) {
+    if (!g || !g->exec) return GDN_EINVAL;
+    DeviceGuard guard(g->ctx->device);
+    if (hipGraphLaunch(g->exec, (hipStream_t)stream) != hipSuccess)
+        return fail(g->ctx, GDN_EHIP, "hipGraphLaunch failed");
+    g->ctx->last = g->plan;
+    g->ctx->has_last = true;
+    return GDN_OK;
+}
+
+void gdn_graph_destroy(gdn_graph* g) {
+    if (!g) return;
+    DeviceGuard guard(g->ctx->device);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    delete g;
+}
+
+// ---------------------------------------------------------------- autotuner
+
+gdn_status gdn_autotune(gdn_ctx* ctx, gdn_params* p, const int32_t* caps, int ncaps, const int32_t* chunks,
+                        int nchunks, int reps, const float* xyz, int64_t n, const int64_t* frame_off, int64_t nf,
+                        void* workspace, size_t workspace_bytes, uint8_t* keep, float* score, uint8_t* stage,
+                        uint32_t* kept_idx, int64_t* n_kept, float* ms_out, void* stream) {
+    if (!ctx) return GDN_EINVAL;
+    if (!p || !caps || ncaps < 1 || reps < 1) return fail(ctx, GDN_EINVAL, "bad autotune arguments");
+    if (!frame_off) return fail(ctx, GDN_EINVAL, "frame_off is NULL");
+    const int32_t zero_chunk = 0;
+    if (!chunks || nchunks < 1) {
+        chunks = &zero_chunk;
+        nchunks = 1;
+    }
+    DeviceGuard guard(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(ctx, GDN_EHIP, "hipEventCreate failed");
+    }
+    gdn_params best = *p;
+    float best_ms = INFINITY;
+    gdn_status status = GDN_OK;
+    std::vector<float> t((size_t)reps);
+    for (int a = 0; a < ncaps && status == GDN_OK; ++a) {
+        for (int b = 0; b < nchunks && status == GDN_OK; ++b) {
+            gdn_params q = *p;
+            q.leaf_cap = caps[a];
+            q.knn_chunk = chunks[b];
+            status = run(ctx, &q, xyz, n, frame_off, nf, workspace, workspace_bytes, keep, score, stage, kept_idx,
+                         n_kept, st, false);  // warm-up
+            for (int r = 0; r < reps && status == GDN_OK; ++r) {
+                (void)hipEventRecord(e0, st);
+                status = run(ctx, &q, xyz, n, frame_off, nf, workspace, workspace_bytes, keep, score, stage,
+                             kept_idx, n_kept, st, false);
+                (void)hipEventRecord(e1, st);
+                if (status != GDN_OK) break;
+                if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t[(size_t)r], e0, e1) != hipSuccess)
+                    status = fail(ctx, GDN_EHIP, "event timing failed");
+            }
+            if (status != GDN_OK) break;
+            std::vector<float> srt = t;
+            std::sort(srt.begin(), srt.end());
+            const float med = srt[srt.size() / 2];
+            if (ms_out) ms_out[a * nchunks + b] = med;
+            if (med < best_ms) {
+                best_ms = med;
+                best = q;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status != GDN_OK) return status;
+    *p = best;
+    ctx->has_last = false;  // the workspace holds the last candidate's frame, not the chosen one
     return GDN_OK;
 }
 

@@ -14,11 +14,14 @@ constexpr int SORT_BLOCK = 256;               // radix-sort workgroup
 constexpr int SORT_ITEMS = 4;                 // keys per thread
 constexpr int SORT_TILE = SORT_BLOCK * SORT_ITEMS;
 constexpr int SORT_PASSES = 8;                // 8-bit digits over the 63-bit key
+constexpr int SORT_FRAME_PASSES_MAX = 2;      // 8-bit digits of the frame id (batches)
+constexpr int SORT_PASSES_MAX = SORT_PASSES + SORT_FRAME_PASSES_MAX;
+constexpr uint32_t MAX_FRAMES = 4096;         // frames per batched call (frame table staged in LDS)
 constexpr int SCAN_BLOCK = 256;
 constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
 constexpr int KNN_TQ = 16;                    // queries per kNN work item (one wave)
-constexpr int KNN_CC0 = 16384;                // initial candidate chunk
+constexpr int KNN_CC0 = 16384;                // default initial candidate chunk
 constexpr int KNN_NCH_MAX = 32;               // max candidate chunks per leaf
 constexpr int HALO = 27;
 constexpr int VOX_BLOCK = 256;
@@ -33,23 +36,29 @@ constexpr uint32_t SPIN_LIMIT = 1u << 22;
 
 constexpr uint32_t DEV_NONFINITE = 1u;
 constexpr uint32_t DEV_WAIT_LIMIT = 2u;
+constexpr uint32_t DEV_BAD_FRAMES = 4u;
 
-// Scalars the kernels share through device memory (inside the zeroed block).
-struct Counters {
+// Per-frame bounding-box accumulators (inside the zeroed block).
+struct FrameStat {
     uint32_t bbox_max[3];   // ordered-uint max of x, y, z
     uint32_t bbox_nmin[3];  // ordered-uint max of ~x (i.e. the min)
     uint32_t nonfinite;
+    uint32_t pad;
+};
+
+// Scalars the kernels share through device memory (inside the zeroed block).
+struct Counters {
     uint32_t status;
     uint32_t n_leaves;
     uint32_t n_p1;
     uint32_t n_items;
     uint32_t n_kept;
-    uint32_t sort_tile_ctr[SORT_PASSES];
+    uint32_t sort_tile_ctr[SORT_PASSES_MAX];
     uint32_t scan_tile_ctr[4];
     unsigned long long pairs;
     uint32_t knn_next;        // dynamic work-queue cursor of the kNN kernel
     uint32_t n_chunked_items; // kNN items of chunked leaves (they come first)
-    uint32_t pad[4];
+    uint32_t pad[3];
 };
 
 // Frame constants derived on the device from the bounding box.
@@ -78,28 +87,40 @@ struct Params {
     double sigma;
     double eps;
     double keep_ratio;
+    int32_t knn_chunk;        // initial kNN candidate chunk length (performance only)
 };
 
-// Pointers into the caller's workspace for one frame of n points.
+// Pointers into the caller's workspace for a batch of nf frames, n points in
+// all (a plain call is the batch of one frame). Frames are contiguous runs of
+// the input; after the sort (frame id most significant) frame f occupies the
+// same positions [foff[f], foff[f+1]) in sorted order.
 struct Plan {
     uint32_t n;
     int k;
+    uint32_t nf;
+    uint32_t sort_passes;     // SORT_PASSES + frame-id passes
     size_t bytes;
     // zero-initialised block
     char* zero_begin;
     size_t zero_bytes;
     Counters* ctr;
-    uint32_t* sort_hist;      // [SORT_PASSES][256]
-    uint32_t* sort_status;    // [SORT_PASSES][sort_tiles][256]
+    FrameStat* fstat;         // [nf]
+    uint32_t* sort_hist;      // [SORT_PASSES_MAX][256]
+    uint32_t* sort_status;    // [SORT_PASSES_MAX][sort_tiles][256]
     uint32_t* scan_status;    // [4][scan_tiles]
     uint32_t sort_tiles, scan_tiles;
-    // frame
-    FrameConst* fc;
+    // frames
+    uint32_t* foff;           // [nf+1] frame offsets (checked copy of the caller's)
+    uint32_t* fid;            // [n] frame of each point (original order; nf > 1 only)
+    FrameConst* fc;           // [nf]
+    uint32_t* keep_ex;        // [n+1] exclusive count of kept points (original order; nf > 1)
     // sort (sorted order = s)
-    uint64_t* keys_a;
+    uint64_t* keys_a;         // sorted keys end here
     uint64_t* keys_b;
-    uint32_t* idx_a;
+    uint32_t* idx_a;          // sorted original indices end here
     uint32_t* idx_b;
+    uint64_t* keys_src;       // where the keys are written before the sort (a or b by pass parity)
+    uint32_t* idx_src;
     float4* pos4;             // [n] sorted x, y, z, original index bits
     uint32_t* leaf_of;        // [n] sorted
     uint32_t* occ;            // [n] sorted

@@ -8,9 +8,13 @@ namespace gdn {
 
 // ---------------------------------------------------------------- zero fill
 
-__global__ void zero_kernel(uint4* p, size_t n16) {
+__global__ void zero_kernel(uint4* p, size_t n16, uint32_t* foff, uint32_t n, uint32_t one_frame) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
         p[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (one_frame && blockIdx.x == 0 && threadIdx.x == 0) {
+        foff[0] = 0u;
+        foff[1] = n;
+    }
 }
 
 void launch_zero(const Plan& P, hipStream_t st) {
@@ -18,70 +22,164 @@ void launch_zero(const Plan& P, hipStream_t st) {
     unsigned blocks = (unsigned)((n16 + 255) / 256);
     if (blocks > 2048) blocks = 2048;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0, st, (uint4*)P.zero_begin, n16);
+    hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0, st, (uint4*)P.zero_begin, n16, P.foff, P.n,
+                       P.nf == 1 ? 1u : 0u);
+}
+
+// ---------------------------------------------------------------- frame table
+//
+// Checked copy of the caller's frame offsets (int64[nf+1]): clamped to [0, n]
+// and made non-decreasing (a running maximum), with foff[0] = 0 and
+// foff[nf] = n. Any repair sets DEV_BAD_FRAMES; the batch is then processed
+// with the repaired table (memory-safe, results unspecified).
+__global__ __launch_bounds__(256) void frames_kernel(const int64_t* __restrict__ in, uint32_t nf, uint32_t n,
+                                                     uint32_t* foff, Counters* c) {
+    __shared__ uint32_t s_max[256];
+    constexpr uint32_t PER = (MAX_FRAMES + 1 + 255) / 256;
+    const uint32_t t = threadIdx.x, b0 = t * PER;
+    uint32_t v[PER];
+    uint32_t m = 0, bad = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < PER; ++i) {
+        const uint32_t f = b0 + i;
+        uint32_t x = 0;
+        if (f <= nf) {
+            const int64_t r = in[f];
+            x = r < 0 ? 0u : (r > (int64_t)n ? n : (uint32_t)r);
+            if (r < 0 || r > (int64_t)n) bad = 1;
+            if (f == 0 && r != 0) bad = 1;
+            if (f == nf && r != (int64_t)n) bad = 1;
+            if (f > 0 && r < in[f - 1]) bad = 1;
+        }
+        m = x > m ? x : m;
+        v[i] = m;  // running max within this thread's entries
+    }
+    s_max[t] = m;
+    __syncthreads();
+    if (t == 0) {
+        uint32_t run = 0;
+        for (int i = 0; i < 256; ++i) {
+            const uint32_t x = s_max[i];
+            s_max[i] = run;  // max over earlier threads
+            run = x > run ? x : run;
+        }
+    }
+    __syncthreads();
+    const uint32_t pre = s_max[t];
+#pragma unroll
+    for (uint32_t i = 0; i < PER; ++i) {
+        const uint32_t f = b0 + i;
+        if (f <= nf) {
+            uint32_t x = v[i] > pre ? v[i] : pre;
+            if (f == 0) x = 0u;
+            if (f == nf) x = n;
+            foff[f] = x;
+        }
+    }
+    if (bad) atomicOr(&c->status, DEV_BAD_FRAMES);
+}
+
+void launch_frames(const Plan& P, const int64_t* frame_off, hipStream_t st) {
+    hipLaunchKernelGGL(frames_kernel, dim3(1), dim3(256), 0, st, frame_off, P.nf, P.n, P.foff, P.ctr);
+}
+
+// Frame of point (original or sorted position) i: the last f with
+// foff[f] <= i, over frames [0, nf) (empty frames never match).
+__device__ __forceinline__ uint32_t frame_of(const uint32_t* foff, uint32_t nf, uint32_t i) {
+    uint32_t lo = 0, hi = nf;  // answer in [lo, hi)
+    while (hi - lo > 1u) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (foff[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
 }
 
 // ---------------------------------------------------------------- bbox
 
-__global__ __launch_bounds__(256) void bbox_kernel(const float* __restrict__ xyz, uint32_t n, Counters* c) {
-    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-    uint32_t bad = 0;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        float x = xyz[3 * (size_t)i], y = xyz[3 * (size_t)i + 1], z = xyz[3 * (size_t)i + 2];
-        if (isfinite(x) && isfinite(y) && isfinite(z)) {
-            mn[0] = fminf(mn[0], x); mx[0] = fmaxf(mx[0], x);
-            mn[1] = fminf(mn[1], y); mx[1] = fmaxf(mx[1], y);
-            mn[2] = fminf(mn[2], z); mx[2] = fmaxf(mx[2], z);
-        } else {
-            ++bad;
-        }
+// Waves take chunks of BBOX_CHUNK consecutive points (coalesced); a chunk
+// inside one frame is reduced across the wave and added to that frame's
+// accumulators once, a chunk across a frame border (at most nf - 1 of them)
+// adds point by point. Batches also record each point's frame.
+constexpr uint32_t BBOX_CHUNK = 1024;
+
+__global__ __launch_bounds__(256) void bbox_kernel(const float* __restrict__ xyz, Plan P) {
+    __shared__ uint32_t s_foff[MAX_FRAMES + 1];
+    const uint32_t n = P.n, nf = P.nf;
+    if (nf > 1) {
+        for (uint32_t f = threadIdx.x; f <= nf; f += blockDim.x) s_foff[f] = P.foff[f];
+        __syncthreads();
     }
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t nchunks = (n + BBOX_CHUNK - 1) / BBOX_CHUNK;
+    for (uint32_t c = wid; c < nchunks; c += nw) {
+        const uint32_t base = c * BBOX_CHUNK, end = min(n, base + BBOX_CHUNK);
+        const uint32_t f0 = nf > 1 ? frame_of(s_foff, nf, base) : 0u;
+        const uint32_t f1 = nf > 1 ? frame_of(s_foff, nf, end - 1u) : 0u;
+        float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+        uint32_t bad = 0;
+        for (uint32_t i = base + lane; i < end; i += 64u) {
+            const float x = xyz[3 * (size_t)i], y = xyz[3 * (size_t)i + 1], z = xyz[3 * (size_t)i + 2];
+            const bool ok = isfinite(x) && isfinite(y) && isfinite(z);
+            if (f0 == f1) {
+                if (ok) {
+                    mn[0] = fminf(mn[0], x); mx[0] = fmaxf(mx[0], x);
+                    mn[1] = fminf(mn[1], y); mx[1] = fmaxf(mx[1], y);
+                    mn[2] = fminf(mn[2], z); mx[2] = fmaxf(mx[2], z);
+                } else {
+                    ++bad;
+                }
+            } else {
+                const uint32_t f = frame_of(s_foff, nf, i);
+                FrameStat* fs = P.fstat + f;
+                if (ok) {
+                    atomicMax(&fs->bbox_nmin[0], ~f32_ordered(x)); atomicMax(&fs->bbox_max[0], f32_ordered(x));
+                    atomicMax(&fs->bbox_nmin[1], ~f32_ordered(y)); atomicMax(&fs->bbox_max[1], f32_ordered(y));
+                    atomicMax(&fs->bbox_nmin[2], ~f32_ordered(z)); atomicMax(&fs->bbox_max[2], f32_ordered(z));
+                } else {
+                    atomicAdd(&fs->nonfinite, 1u);
+                    atomicOr(&P.ctr->status, DEV_NONFINITE);
+                }
+            }
+            if (nf > 1) P.fid[i] = f0 == f1 ? f0 : frame_of(s_foff, nf, i);
+        }
+        if (f0 == f1) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
+            for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            mn[a] = fminf(mn[a], __shfl_xor(mn[a], o, 64));
-            mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], o, 64));
-        }
-        bad += __shfl_xor(bad, o, 64);
-    }
-    __shared__ float s_mn[3][4], s_mx[3][4];
-    __shared__ uint32_t s_bad[4];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
-        for (int a = 0; a < 3; ++a) { s_mn[a][wave] = mn[a]; s_mx[a][wave] = mx[a]; }
-        s_bad[wave] = bad;
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-        const int a = threadIdx.x;
-        float m0 = s_mn[a][0], m1 = s_mx[a][0];
-        for (int w = 1; w < 4; ++w) { m0 = fminf(m0, s_mn[a][w]); m1 = fmaxf(m1, s_mx[a][w]); }
-        if (m0 <= m1) {
-            atomicMax(&c->bbox_nmin[a], ~f32_ordered(m0));
-            atomicMax(&c->bbox_max[a], f32_ordered(m1));
-        }
-    }
-    if (threadIdx.x == 3) {
-        uint32_t b = s_bad[0] + s_bad[1] + s_bad[2] + s_bad[3];
-        if (b) {
-            atomicAdd(&c->nonfinite, b);
-            atomicOr(&c->status, DEV_NONFINITE);
+                for (int a = 0; a < 3; ++a) {
+                    mn[a] = fminf(mn[a], __shfl_xor(mn[a], o, 64));
+                    mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], o, 64));
+                }
+                bad += __shfl_xor(bad, o, 64);
+            }
+            if (lane < 3u && mn[lane] <= mx[lane]) {
+                FrameStat* fs = P.fstat + f0;
+                atomicMax(&fs->bbox_nmin[lane], ~f32_ordered(mn[lane]));
+                atomicMax(&fs->bbox_max[lane], f32_ordered(mx[lane]));
+            }
+            if (lane == 3u && bad) {
+                atomicAdd(&P.fstat[f0].nonfinite, bad);
+                atomicOr(&P.ctr->status, DEV_NONFINITE);
+            }
         }
     }
 }
 
 void launch_bbox(const Plan& P, const float* xyz, hipStream_t st) {
-    unsigned blocks = (P.n + 1023) / 1024;
-    if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(bbox_kernel, dim3(blocks), dim3(256), 0, st, xyz, P.n, P.ctr);
+    const uint32_t nchunks = (P.n + BBOX_CHUNK - 1) / BBOX_CHUNK;
+    unsigned blocks = (nchunks + 3) / 4;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(bbox_kernel, dim3(blocks), dim3(256), 0, st, xyz, P);
 }
 
 // ---------------------------------------------------------------- Morton keys
 
 // Root cube: side S = largest bbox extent at the bbox minimum; depth limit from
 // the minimum leaf side. Same FP64 expressions for every consumer.
-__device__ void frame_consts(const Counters* c, double min_leaf_side, FrameConst* f) {
+__device__ void frame_consts(const FrameStat* c, double min_leaf_side, FrameConst* f) {
     double S = 0.0;
     for (int a = 0; a < 3; ++a) {
         float lo = f32_from_ordered(~c->bbox_nmin[a]);
@@ -108,40 +206,49 @@ __device__ __forceinline__ uint32_t quantise(float x, float lo, double scale) {
     return (uint32_t)q;
 }
 
-// Keys, the identity payload and the 8 digit histograms of the sort.
-__global__ __launch_bounds__(256) void morton_kernel(const float* __restrict__ xyz, uint32_t n, Plan P,
-                                                     double min_leaf_side) {
+// Frame constants of every frame of a batch (one thread per frame).
+__global__ __launch_bounds__(256) void frame_const_kernel(Plan P, double min_leaf_side) {
+    for (uint32_t f = threadIdx.x; f < P.nf; f += blockDim.x) frame_consts(P.fstat + f, min_leaf_side, P.fc + f);
+}
+
+// Keys (quantised with the point's own frame constants), the identity
+// payload and the digit histograms of the sort: 8 key digits, then the frame
+// id digits of a batch. A single frame computes its constants per block.
+__global__ __launch_bounds__(256) void morton_kernel(const float* __restrict__ xyz, Plan P, double min_leaf_side) {
     __shared__ FrameConst s_fc;
-    __shared__ uint32_t s_hist[SORT_PASSES][256];
-    for (int i = threadIdx.x; i < SORT_PASSES * 256; i += blockDim.x) (&s_hist[0][0])[i] = 0u;
-    if (threadIdx.x == 0) {
-        frame_consts(P.ctr, min_leaf_side, &s_fc);
+    __shared__ uint32_t s_hist[SORT_PASSES_MAX][256];
+    const uint32_t n = P.n, nf = P.nf, nh = P.sort_passes;
+    for (uint32_t i = threadIdx.x; i < nh * 256u; i += blockDim.x) (&s_hist[0][0])[i] = 0u;
+    if (nf == 1 && threadIdx.x == 0) {
+        frame_consts(P.fstat, min_leaf_side, &s_fc);
         if (blockIdx.x == 0) *P.fc = s_fc;
     }
     __syncthreads();
-    const float lx = s_fc.lo[0], ly = s_fc.lo[1], lz = s_fc.lo[2];
-    const double scale = s_fc.scale;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        uint32_t qx = quantise(xyz[3 * (size_t)i], lx, scale);
-        uint32_t qy = quantise(xyz[3 * (size_t)i + 1], ly, scale);
-        uint32_t qz = quantise(xyz[3 * (size_t)i + 2], lz, scale);
-        uint64_t key = morton3(qx, qy, qz);
-        P.keys_a[i] = key;
-        P.idx_a[i] = i;
+        const uint32_t f = nf > 1 ? P.fid[i] : 0u;
+        const FrameConst& fc = nf > 1 ? P.fc[f] : s_fc;
+        const uint32_t qx = quantise(xyz[3 * (size_t)i], fc.lo[0], fc.scale);
+        const uint32_t qy = quantise(xyz[3 * (size_t)i + 1], fc.lo[1], fc.scale);
+        const uint32_t qz = quantise(xyz[3 * (size_t)i + 2], fc.lo[2], fc.scale);
+        const uint64_t key = morton3(qx, qy, qz);
+        P.keys_src[i] = key;
+        P.idx_src[i] = i;
 #pragma unroll
         for (int p = 0; p < SORT_PASSES; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
+        for (uint32_t p = SORT_PASSES; p < nh; ++p) atomicAdd(&s_hist[p][(f >> (8 * (p - SORT_PASSES))) & 255u], 1u);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < SORT_PASSES * 256; i += blockDim.x) {
+    for (uint32_t i = threadIdx.x; i < nh * 256u; i += blockDim.x) {
         uint32_t v = (&s_hist[0][0])[i];
         if (v) atomicAdd(&P.sort_hist[i], v);
     }
 }
 
 void launch_morton(const Plan& P, const Params& prm, const float* xyz, hipStream_t st) {
+    if (P.nf > 1) hipLaunchKernelGGL(frame_const_kernel, dim3(1), dim3(256), 0, st, P, prm.min_leaf_side);
     unsigned blocks = (P.n + 2047) / 2048;
     if (blocks > 512) blocks = 512;
-    hipLaunchKernelGGL(morton_kernel, dim3(blocks), dim3(256), 0, st, xyz, P.n, P, prm.min_leaf_side);
+    hipLaunchKernelGGL(morton_kernel, dim3(blocks), dim3(256), 0, st, xyz, P, prm.min_leaf_side);
 }
 
 // ---------------------------------------------------------------- radix sort
@@ -149,13 +256,15 @@ void launch_morton(const Plan& P, const Params& prm, const float* xyz, hipStream
 // One stable LSD pass over digit `pass` (8 bits) in the onesweep style: local
 // ranks by wave-level digit matching, digit offsets of earlier tiles by
 // decoupled look-back (bounded waits), global digit bases from the histogram.
+// Passes past the key's 8 take the digit from the frame id of the payload
+// (the original index), so a batch ends sorted by (frame, key, index).
 __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* __restrict__ kin,
                                                                 const uint32_t* __restrict__ vin,
                                                                 uint64_t* __restrict__ kout,
                                                                 uint32_t* __restrict__ vout, uint32_t n,
                                                                 int pass, const uint32_t* __restrict__ hist,
                                                                 uint32_t* status, uint32_t* tile_ctr,
-                                                                uint32_t* dev_status) {
+                                                                uint32_t* dev_status, const uint32_t* __restrict__ fid) {
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_w[SORT_BLOCK / 64][256];
     __shared__ uint32_t s_base[256];
@@ -176,7 +285,9 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
         bool ok = pos < n;
         key[i] = ok ? kin[pos] : 0ull;
         val[i] = ok ? vin[pos] : 0u;
-        dig[i] = ok ? (uint32_t)((key[i] >> shift) & 255u) : 256u;
+        const uint32_t d = pass < SORT_PASSES ? (uint32_t)((key[i] >> shift) & 255u)
+                                              : (fid[ok ? val[i] : 0u] >> (8 * (pass - SORT_PASSES))) & 255u;
+        dig[i] = ok ? d : 256u;
     }
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
@@ -273,15 +384,16 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
 }
 
 void launch_sort(const Plan& P, hipStream_t st) {
-    const uint64_t* kin = P.keys_a;
-    const uint32_t* vin = P.idx_a;
-    uint64_t* kout = P.keys_b;
-    uint32_t* vout = P.idx_b;
-    for (int pass = 0; pass < SORT_PASSES; ++pass) {
+    // the keys start where an even/odd number of passes leaves them in keys_a
+    const uint64_t* kin = P.keys_src;
+    const uint32_t* vin = P.idx_src;
+    uint64_t* kout = P.keys_src == P.keys_a ? P.keys_b : P.keys_a;
+    uint32_t* vout = P.idx_src == P.idx_a ? P.idx_b : P.idx_a;
+    for (uint32_t pass = 0; pass < P.sort_passes; ++pass) {
         hipLaunchKernelGGL(radix_pass_kernel, dim3(P.sort_tiles), dim3(SORT_BLOCK), 0, st, kin, vin, kout, vout,
-                           P.n, pass, P.sort_hist + 256 * pass,
+                           P.n, (int)pass, P.sort_hist + 256 * pass,
                            P.sort_status + (size_t)pass * P.sort_tiles * 256, &P.ctr->sort_tile_ctr[pass],
-                           &P.ctr->status);
+                           &P.ctr->status, (const uint32_t*)P.fid);
         const uint64_t* tk = kout;
         const uint32_t* tv = vout;
         kout = (uint64_t*)kin;
@@ -289,7 +401,6 @@ void launch_sort(const Plan& P, hipStream_t st) {
         kin = tk;
         vin = tv;
     }
-    // SORT_PASSES is even: the sorted keys end in keys_a / idx_a
 }
 
 // ---------------------------------------------------------------- permute

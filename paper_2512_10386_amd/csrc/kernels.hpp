@@ -5,8 +5,9 @@
 
 namespace gdn {
 
-// frame.hip: zero-fill, frame bbox, Morton keys, radix sort, permute
+// frame.hip: zero-fill, frame table, frame bboxes, Morton keys, radix sort, permute
 void launch_zero(const Plan& P, hipStream_t st);
+void launch_frames(const Plan& P, const int64_t* frame_off, hipStream_t st);
 void launch_bbox(const Plan& P, const float* xyz, hipStream_t st);
 void launch_morton(const Plan& P, const Params& prm, const float* xyz, hipStream_t st);
 void launch_sort(const Plan& P, hipStream_t st);
@@ -17,7 +18,7 @@ void launch_leaves(const Plan& P, const Params& prm, hipStream_t st);
 void launch_voxel(const Plan& P, const Params& prm, hipStream_t st);
 void launch_p1_compact(const Plan& P, hipStream_t st);
 void launch_halo(const Plan& P, hipStream_t st);
-void launch_knn_plan(const Plan& P, hipStream_t st);
+void launch_knn_plan(const Plan& P, const Params& prm, hipStream_t st);
 
 // knn.hip: brute-force kNN over leaf + halo candidates (chunk merge included)
 void launch_knn_bound(const Plan& P, int k, int num_cus, hipStream_t st);
@@ -31,7 +32,7 @@ void launch_score(const Plan& P, const Params& prm, const float* xyz, hipStream_
 void launch_topl(const Plan& P, const Params& prm, hipStream_t st);
 void launch_outputs(const Plan& P, uint8_t* keep, float* score, uint8_t* stage,
                     uint32_t* kept_idx, int64_t* n_kept, hipStream_t st);
-void launch_write_zero_count(int64_t* n_kept, hipStream_t st);
+void launch_write_zero_count(int64_t* n_kept, uint32_t nf, hipStream_t st);
 
 // dump.hip: intermediates back in original point order
 int launch_dump(const Plan& P, int what, void* dst, size_t dst_bytes, hipStream_t st);

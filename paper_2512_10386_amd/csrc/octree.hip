@@ -21,28 +21,32 @@ __device__ __forceinline__ int common_digits(uint64_t a, uint64_t b) {
 // and that cell holds more than leaf_cap points. The cell count is tested
 // with one windowed binary search (window leaf_cap + 1).
 
-struct BoundaryGet {
-    const uint64_t* keys;
-    const FrameConst* fc;
-    uint32_t n, cap;
-    __device__ uint32_t operator()(uint32_t j) const {
-        if (j == 0) return 1u;
-        const uint64_t a = keys[j - 1], b = keys[j];
-        const int l = common_digits(a, b);
-        if (l >= fc->dmax) return 0u;
-        const int sh = 3 * (MORTON_BITS - l);
-        const uint64_t P = b >> sh;
-        uint32_t lo = (j - 1 > cap) ? j - 1 - cap : 0u;
-        uint32_t hi = j - 1;
-        while (lo < hi) {
-            uint32_t mid = (lo + hi) >> 1;
-            if ((keys[mid] >> sh) < P) lo = mid + 1;
-            else hi = mid;
-        }
-        const uint64_t probe = (uint64_t)lo + cap;
-        return (probe < n && (keys[probe] >> sh) == P) ? 1u : 0u;
+// Frame of sorted position j (frames keep their input ranges after the sort).
+__device__ __forceinline__ uint32_t frame_of_sorted(const Plan& P, uint32_t j) {
+    return P.nf > 1 ? P.fid[P.idx_a[j]] : 0u;
+}
+
+// Boundary test of sorted position j inside its frame [fs, fe): the frame's
+// first point starts a leaf; otherwise the rule above with the frame's depth
+// limit and the search window clipped to the frame.
+__device__ uint32_t leaf_boundary(const uint64_t* keys, uint32_t j, uint32_t fs, uint32_t fe, int dmax,
+                                  uint32_t cap) {
+    if (j == fs) return 1u;
+    const uint64_t a = keys[j - 1], b = keys[j];
+    const int l = common_digits(a, b);
+    if (l >= dmax) return 0u;
+    const int sh = 3 * (MORTON_BITS - l);
+    const uint64_t P = b >> sh;
+    uint32_t lo = (j - 1 - fs > cap) ? j - 1 - cap : fs;
+    uint32_t hi = j - 1;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if ((keys[mid] >> sh) < P) lo = mid + 1;
+        else hi = mid;
     }
-};
+    const uint64_t probe = (uint64_t)lo + cap;
+    return (probe < fe && (keys[probe] >> sh) == P) ? 1u : 0u;
+}
 
 struct BoundaryEmit {
     uint32_t* leaf_of;
@@ -68,12 +72,14 @@ struct BoundaryFin {
 // is an over-full cell at the depth limit.
 __global__ __launch_bounds__(256) void leaf_table_kernel(Plan P, uint32_t cap) {
     const uint32_t nl = P.ctr->n_leaves;
-    const int dmax = P.fc->dmax;
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nl; t += gridDim.x * blockDim.x) {
         const uint32_t s = P.leaf_begin[t], e = P.leaf_begin[t + 1];
+        const uint32_t f = frame_of_sorted(P, s);
+        const uint32_t fs = P.foff[f], fe = P.foff[f + 1];
+        const int dmax = P.fc[f].dmax;
         int m = -1;
-        if (s > 0) m = common_digits(P.keys_a[s - 1], P.keys_a[s]);
-        if (e < P.n) m = max(m, common_digits(P.keys_a[e - 1], P.keys_a[e]));
+        if (s > fs) m = common_digits(P.keys_a[s - 1], P.keys_a[s]);
+        if (e < fe) m = max(m, common_digits(P.keys_a[e - 1], P.keys_a[e]));
         int level = (e - s <= cap) ? m + 1 : dmax;
         level = level < 0 ? 0 : (level > MORTON_BITS ? MORTON_BITS : level);
         P.leaf_level[t] = (uint32_t)level;
@@ -84,9 +90,10 @@ __global__ __launch_bounds__(256) void leaf_table_kernel(Plan P, uint32_t cap) {
 // The boundary tests run one thread per position (each is a chain of
 // dependent loads); the scan then only reads the flags.
 __global__ __launch_bounds__(256) void boundary_flag_kernel(Plan P, uint32_t cap) {
-    const BoundaryGet g{P.keys_a, P.fc, P.n, cap};
-    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < P.n; j += gridDim.x * blockDim.x)
-        P.bflag[j] = (uint8_t)g(j);
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < P.n; j += gridDim.x * blockDim.x) {
+        const uint32_t f = frame_of_sorted(P, j);
+        P.bflag[j] = (uint8_t)leaf_boundary(P.keys_a, j, P.foff[f], P.foff[f + 1], P.fc[f].dmax, cap);
+    }
 }
 
 struct FlagGet {
@@ -288,6 +295,8 @@ __global__ __launch_bounds__(256) void halo_kernel(Plan P) {
     for (uint32_t base = blockIdx.x * HALO_LEAVES; base < nl; base += gridDim.x * HALO_LEAVES) {
         const uint32_t t = base + grp;
         if (t < nl && g < HALO) {
+            const uint32_t f = frame_of_sorted(P, P.leaf_begin[t]);
+            const uint32_t fs = P.foff[f], fe = P.foff[f + 1];
             const int d = (int)P.leaf_level[t];
             const uint64_t pre = P.leaf_prefix[t];
             const int64_t cx = compact3(pre), cy = compact3(pre >> 1), cz = compact3(pre >> 2);
@@ -298,8 +307,8 @@ __global__ __launch_bounds__(256) void halo_kernel(Plan P) {
                 const int sh = 3 * (MORTON_BITS - d);
                 const uint64_t klo = morton3((uint32_t)nx, (uint32_t)ny, (uint32_t)nz) << sh;
                 const uint64_t khi = klo + (1ull << sh);
-                const uint32_t lo = lower_bound_u64(P.keys_a, P.n, klo);
-                const uint32_t hi = lower_bound_u64(P.keys_a, P.n, khi);
+                const uint32_t lo = fs + lower_bound_u64(P.keys_a + fs, fe - fs, klo);
+                const uint32_t hi = fs + lower_bound_u64(P.keys_a + fs, fe - fs, khi);
                 r = make_uint2(P.p1pos[lo], P.p1pos[hi]);
             }
             s_r[grp][g] = r;
@@ -346,22 +355,22 @@ void launch_halo(const Plan& P, hipStream_t st) {
 //
 // One workgroup. Work items are (leaf, tile of up to KNN_TQ queries,
 // candidate chunk). Leaves whose candidate set exceeds the chunk length are
-// split into chunks whose partial top-k lists are merged by the last chunk of
-// each tile to finish; the chunk length doubles until the partial lists and
-// items fit their workspace. This kernel fixes, per leaf, the chunking and
+// split into chunks whose partial top-k lists knn_merge_kernel combines; the
+// chunk length doubles until the partial lists and items fit their
+// workspace. This kernel fixes, per leaf, the chunking and
 // the index of its first item; items of chunked leaves (the heaviest) come
 // first in the queue, then the rest, both in leaf order. The items themselves
 // are written by the bound kernel, one tile per thread.
 
 constexpr int PLAN_BLOCK = 1024;
 
-__global__ __launch_bounds__(PLAN_BLOCK) void knn_plan_kernel(Plan P) {
+__global__ __launch_bounds__(PLAN_BLOCK) void knn_plan_kernel(Plan P, int chunk0) {
     __shared__ unsigned long long s_red[PLAN_BLOCK / 64][3];
     __shared__ uint32_t s_scan[PLAN_BLOCK / 64 + 1];
     __shared__ uint32_t s_cc, s_done, s_carry_l, s_carry_c, s_carry_u, s_chunked_items;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t nl = P.ctr->n_leaves;
-    if (tid == 0) { s_cc = KNN_CC0; s_done = 0; }
+    if (tid == 0) { s_cc = (uint32_t)chunk0; s_done = 0; }
     __syncthreads();
     for (int iter = 0; iter < 40; ++iter) {
         const uint32_t cc = s_cc;
@@ -456,8 +465,9 @@ __global__ __launch_bounds__(PLAN_BLOCK) void knn_plan_kernel(Plan P) {
     }
 }
 
-void launch_knn_plan(const Plan& P, hipStream_t st) {
-    hipLaunchKernelGGL(knn_plan_kernel, dim3(1), dim3(PLAN_BLOCK), 0, st, P);
+void launch_knn_plan(const Plan& P, const Params& prm, hipStream_t st) {
+    const int chunk0 = prm.knn_chunk > 0 ? prm.knn_chunk : KNN_CC0;
+    hipLaunchKernelGGL(knn_plan_kernel, dim3(1), dim3(PLAN_BLOCK), 0, st, P, chunk0);
 }
 
 }  // namespace gdn

@@ -422,19 +422,56 @@ struct KeepFin {
     }
 };
 
+// Batches: the scan records each point's count of kept points before it;
+// kept point i of frame f then lands at kept_idx[foff[f] + its rank within
+// the frame] as the frame-local index i - foff[f].
+struct BatchKeepEmit {
+    uint32_t* keep_ex;
+    __device__ void operator()(uint32_t i, uint32_t ex, uint32_t) const { keep_ex[i] = ex; }
+};
+struct BatchKeepFin {
+    Counters* c;
+    uint32_t* keep_ex;
+    uint32_t n;
+    __device__ void operator()(uint32_t total) const {
+        c->n_kept = total;
+        keep_ex[n] = total;
+    }
+};
+
+__global__ __launch_bounds__(256) void kept_frames_kernel(Plan P, const uint8_t* keep, uint32_t* kept_idx,
+                                                          int64_t* n_kept) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
+    for (uint32_t i = tid; i < P.n; i += nt) {
+        if (keep[i]) {
+            const uint32_t f = P.fid[i], fs = P.foff[f];
+            kept_idx[fs + (P.keep_ex[i] - P.keep_ex[fs])] = i - fs;
+        }
+    }
+    for (uint32_t f = tid; f < P.nf; f += nt) n_kept[f] = (int64_t)(P.keep_ex[P.foff[f + 1]] - P.keep_ex[P.foff[f]]);
+}
+
 void launch_outputs(const Plan& P, uint8_t* keep, float* score, uint8_t* stage, uint32_t* kept_idx,
                     int64_t* n_kept, hipStream_t st) {
     unsigned blocks = (P.n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(outputs_kernel, dim3(blocks), dim3(256), 0, st, P, keep, score, stage);
-    launch_scan(KeepGet{keep}, KeepEmit{kept_idx}, KeepFin{P.ctr, n_kept}, nullptr, P.n,
-                P.scan_status + 2 * (size_t)P.scan_tiles, &P.ctr->scan_tile_ctr[2], &P.ctr->status, st);
+    if (P.nf == 1) {
+        launch_scan(KeepGet{keep}, KeepEmit{kept_idx}, KeepFin{P.ctr, n_kept}, nullptr, P.n,
+                    P.scan_status + 2 * (size_t)P.scan_tiles, &P.ctr->scan_tile_ctr[2], &P.ctr->status, st);
+    } else {
+        launch_scan(KeepGet{keep}, BatchKeepEmit{P.keep_ex}, BatchKeepFin{P.ctr, P.keep_ex, P.n}, nullptr, P.n,
+                    P.scan_status + 2 * (size_t)P.scan_tiles, &P.ctr->scan_tile_ctr[2], &P.ctr->status, st);
+        hipLaunchKernelGGL(kept_frames_kernel, dim3(blocks), dim3(256), 0, st, P, keep, kept_idx, n_kept);
+    }
 }
 
-__global__ void write_zero_count_kernel(int64_t* n_kept) { *n_kept = 0; }
+__global__ void write_zero_counts_kernel(int64_t* n_kept, uint32_t nf) {
+    for (uint32_t f = threadIdx.x; f < nf; f += blockDim.x) n_kept[f] = 0;
+}
 
-void launch_write_zero_count(int64_t* n_kept, hipStream_t st) {
-    hipLaunchKernelGGL(write_zero_count_kernel, dim3(1), dim3(1), 0, st, n_kept);
+void launch_write_zero_count(int64_t* n_kept, uint32_t nf, hipStream_t st) {
+    hipLaunchKernelGGL(write_zero_counts_kernel, dim3(1), dim3(256), 0, st, n_kept, nf);
 }
 
 }  // namespace gdn

@@ -40,6 +40,9 @@ def test_defaults_match_the_paper_and_the_oracle(libgdn, oracle):
     p = libgdn.gdn_default_params()
     o = oracle.default_params()
     for f, _ in libgdn.gdn_params._fields_:
+        if f == "knn_chunk":  # work split of the kNN kernel: speed only, not a method parameter
+            assert p.knn_chunk == 0
+            continue
         assert getattr(p, f) == o[f], f
     assert (p.k, p.rho_percentile, p.min_vox_count) == (12, 0.2, 4)
 
@@ -57,3 +60,20 @@ def test_workspace_size_and_validation_on_host(libgdn):
         libgdn.gdn_workspace_size(0, p, 1 << 30)
     assert e.value.status == libgdn.GDN_ECAPACITY
     assert libgdn.lib().gdn_status_string(libgdn.GDN_ENOMEM) == b"workspace too small"
+
+
+def test_batch_workspace_size_and_validation_on_host(libgdn):
+    p = libgdn.make_params(k=32, leaf_cap=1024)
+    one = libgdn.gdn_workspace_size(0, p, 120000)
+    assert libgdn.gdn_workspace_size_batch(0, p, 120000, 1) == one
+    many = libgdn.gdn_workspace_size_batch(0, p, 120000, 64)
+    assert many > one  # frame table, frame ids and kept ranks
+    assert libgdn.gdn_workspace_size_batch(0, p, 0, 5) == 0
+    for nf, status in ((0, libgdn.GDN_EINVAL), (libgdn.GDN_MAX_FRAMES + 1, libgdn.GDN_ECAPACITY)):
+        with pytest.raises(libgdn.GdnError) as e:
+            libgdn.gdn_workspace_size_batch(0, p, 1000, nf)
+        assert e.value.status == status
+    libgdn.gdn_workspace_size_batch(0, p, 1000, libgdn.GDN_MAX_FRAMES)
+    with pytest.raises(libgdn.GdnError) as e:
+        libgdn.gdn_workspace_size(0, libgdn.make_params(knn_chunk=-1), 10)
+    assert e.value.status == libgdn.GDN_EINVAL
