@@ -6,7 +6,12 @@ kNN, density, percentile/median, score, top-lambda, compaction) over one
 synthetic 120k-point LiDAR frame at k=32, leaf cap 1024, with the input already
 resident in HBM. Prints ONE JSON line on stdout; progress goes to stderr.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+The line also carries the batched form ("batched vs plain"): 64 uneven LiDAR
+frames (6.2M points) in one pipeline pass, leaf cap and kNN chunk picked by the
+autotuner, replayed from a captured HIP graph, beside the same frames run one
+plain call at a time.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-batch]
 """
 import argparse
 import hashlib
@@ -63,6 +68,79 @@ def cpu_baseline(xyz, params, budget_s=12.0):
                       f"{el:.1f} s wall"}
 
 
+def bench_batch(steps):
+    """The 64-frame batch: autotune, graph replay, eager batch, plain loop."""
+    import numpy as np
+    import torch
+    from paper_2512_10386_amd import synth
+    from paper_2512_10386_amd.binding import BatchDenoiser, Denoiser, gdn_set_timing, gdn_timing
+
+    frames, _, params = synth.make("lidar_batch_64")
+    sizes = [len(f) for f in frames]
+    off = np.zeros(len(frames) + 1, np.int64)
+    off[1:] = np.cumsum(sizes)
+    n, nf = int(off[-1]), len(frames)
+    dev = torch.device("cuda", 0)
+    xyz = torch.from_numpy(np.concatenate(frames)).to(dev)
+    offd = torch.from_numpy(off).to(dev)
+    log(f"[bench] batch: {nf} frames, {n} points (min {min(sizes)}, max {max(sizes)})")
+    bd = BatchDenoiser(0, **params)
+    table = bd.autotune(xyz, offd, caps=synth.LIDAR_BATCH_CAPS, chunks=(8192, 16384, 32768), reps=2)
+    cap, chunk = bd.params.leaf_cap, bd.params.knn_chunk
+    log(f"[bench] autotune -> leaf_cap {cap}, knn_chunk {chunk}")
+    out = bd.alloc(n, nf)
+    for _ in range(3):
+        bd.graph(xyz, offd, out)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        bd.graph(xyz, offd, out)
+    t1.record()
+    torch.cuda.synchronize()
+    ms_graph = t0.elapsed_time(t1) / steps
+    # eager batch calls, with the library's kNN-kernel events
+    gdn_set_timing(bd.ctx, True)
+    for _ in range(steps):
+        bd(xyz, offd, out)
+    torch.cuda.synchronize()
+    per = [gdn_timing(bd.ctx, b) for b in range(steps)]
+    gdn_set_timing(bd.ctx, False)
+    ms_eager = statistics.fmean(t for t, _ in per)
+    knn_ms = statistics.fmean(k for _, k in per)
+    counts = bd.dump("COUNTS", n).cpu().numpy()
+    pairs = int(counts[2])
+    # the same frames as plain single-frame calls, back to back
+    pd = Denoiser(0, **dict(params, leaf_cap=cap, knn_chunk=chunk))
+    xs = [xyz[int(off[f]):int(off[f + 1])] for f in range(nf)]
+    outs = []
+    for x in xs:
+        outs.append(pd(x))
+    torch.cuda.synchronize()
+    t0.record()
+    reps = max(1, steps // 4)
+    for _ in range(reps):
+        for x, o in zip(xs, outs):
+            pd(x, o)
+    t1.record()
+    torch.cuda.synchronize()
+    ms_plain = t0.elapsed_time(t1) / reps
+    bd.close()
+    pd.close()
+    mp = lambda ms: round(n / (ms * 1e-3) / 1e6, 2)
+    res = {"workload": "lidar_batch_64", "frames": nf, "points": n, "k": params["k"],
+           "leaf_cap": cap, "knn_chunk": chunk, "steps": steps,
+           "ms_per_batch_graph": round(ms_graph, 4), "ms_per_batch_eager": round(ms_eager, 4),
+           "ms_plain_loop": round(ms_plain, 4),
+           "mpoints_s_graph": mp(ms_graph), "mpoints_s_eager": mp(ms_eager), "mpoints_s_plain_loop": mp(ms_plain),
+           "knn_kernel_ms": round(knn_ms, 4), "pairs": pairs,
+           "knn_tflops_algorithmic": round(pairs * FLOPS_PER_PAIR / (knn_ms * 1e-3) / 1e12, 3),
+           "autotune_ms": {f"{c}/{h}": round(v, 3) for (c, h), v in table.items()}}
+    log(f"[bench] batch: graph {ms_graph:.3f} ms ({res['mpoints_s_graph']} Mpts/s), eager {ms_eager:.3f} ms, "
+        f"plain loop {ms_plain:.3f} ms ({res['mpoints_s_plain_loop']} Mpts/s), kNN {knn_ms:.3f} ms")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +148,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="lidar_120k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched (64-frame) leg")
+    ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -180,6 +260,8 @@ def main():
         "latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4)},
         "roofline": roofline,
     }
+    if not args.no_batch:
+        rec["batched"] = bench_batch(args.batch_steps)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         rec["cpu_baseline"] = cpu_baseline(xyz, params)

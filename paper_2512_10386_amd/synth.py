@@ -174,6 +174,15 @@ def lidar_batch_sizes(seed: int = 4000, n_frames: int = 64,
     return [int(round(s / n_beams)) for s in sizes]
 
 
+def lidar_batch(seed: int = 4000, n_frames: int = 64, lo: int = 60_000, hi: int = 130_000):
+    """Uneven LiDAR frames for batched runs: frame f has the azimuth count
+    ``lidar_batch_sizes(seed, n_frames, lo, hi)[f]`` and scene seed ``seed + f``.
+    Returns (list of xyz arrays, list of label arrays)."""
+    sizes = lidar_batch_sizes(seed, n_frames, lo, hi)
+    out = [lidar_frame(seed=seed + f, n_az=s) for f, s in enumerate(sizes)]
+    return [x for x, _ in out], [lab for _, lab in out]
+
+
 # Workload recipes: generator, its arguments and the method parameters they
 # are run with. Parameters not named here take the library defaults.
 CONFIGS = {
@@ -181,12 +190,19 @@ CONFIGS = {
                              params=dict(k=16, leaf_cap=512)),
     "lidar_120k": dict(gen="lidar_frame", kwargs=dict(seed=2),
                        params=dict(k=32, leaf_cap=1024)),
+    # 64 frames of 60k-130k points (6.2M in all); the leaf cap is autotuned
+    # over LIDAR_BATCH_CAPS, 1024 is the starting value
+    "lidar_batch_64": dict(gen="lidar_batch", kwargs=dict(seed=4000, n_frames=64),
+                           params=dict(k=32, leaf_cap=1024)),
 }
+
+LIDAR_BATCH_CAPS = (256, 512, 1024, 2048)
 
 
 def make(name: str):
-    """Return (xyz, label, params) for a named workload recipe."""
+    """Return (xyz, label, params) for a named workload recipe (for a batch,
+    xyz and label are lists with one array per frame)."""
     c = CONFIGS[name]
-    fn = {"sphere_plane": sphere_plane, "lidar_frame": lidar_frame}[c["gen"]]
+    fn = {"sphere_plane": sphere_plane, "lidar_frame": lidar_frame, "lidar_batch": lidar_batch}[c["gen"]]
     xyz, label = fn(**c["kwargs"])
     return xyz, label, dict(c["params"])
