@@ -9,6 +9,7 @@
 
 #include "gdn.h"
 #include "kernels.hpp"
+#include "scan.hpp"
 
 // Events of one timed call: start, kNN start, kNN end, end.
 constexpr int TIMING_RING = 256;
@@ -54,24 +55,27 @@ gdn::Plan make_plan(uint32_t n, uint32_t nf, int k, char* base) {
     P.k = k;
     P.nf = nf;
     P.sort_passes = SORT_PASSES + (nf > 256u ? 2u : (nf > 1u ? 1u : 0u));
-    P.sort_tiles = (uint32_t)((N + SORT_TILE - 1) / SORT_TILE);
+    P.sort_items = n > SORT_BIG_N ? 16u : 4u;
+    const size_t sort_tile = (size_t)SORT_BLOCK * P.sort_items;
+    P.sort_tiles = (uint32_t)((N + sort_tile - 1) / sort_tile);
     if (P.sort_tiles == 0) P.sort_tiles = 1;
-    P.scan_tiles = (uint32_t)((N + SCAN_TILE - 1) / SCAN_TILE);
-    if (P.scan_tiles == 0) P.scan_tiles = 1;
-    P.items_max = 2u * n + 64u;
-    P.plist_max = 3u * n + 64u;
+    P.scan_tiles = scan_tiles_for(n);
+    // capacities stay below 2^30 (the look-back scans carry 30-bit sums)
+    P.items_max = (uint32_t)std::min<uint64_t>(2ull * n + 64u, (1ull << 30) - 64u);
+    P.plist_max = (uint32_t)std::min<uint64_t>(3ull * n + 64u, (1ull << 30) - 64u);
 
     const size_t z0 = off;
     P.ctr = (Counters*)take(sizeof(Counters));
     P.fstat = (FrameStat*)take(sizeof(FrameStat) * (size_t)nf);
     P.sort_hist = (uint32_t*)take(sizeof(uint32_t) * SORT_PASSES_MAX * 256);
     P.sort_status = (uint32_t*)take(sizeof(uint32_t) * (size_t)P.sort_passes * P.sort_tiles * 256);
-    P.scan_status = (uint32_t*)take(sizeof(uint32_t) * 4 * (size_t)P.scan_tiles);
+    P.scan_status = (uint32_t*)take(sizeof(uint32_t) * SCAN_SLOTS * (size_t)P.scan_tiles);
     P.zero_begin = base ? base + z0 : nullptr;
     P.zero_bytes = off - z0;
 
     P.foff = (uint32_t*)take(4 * ((size_t)nf + 1));
     P.fc = (FrameConst*)take(sizeof(FrameConst) * (size_t)nf);
+    P.bbox_part = (uint32_t*)take(32 * ((N + 1023) / 1024 + 1));
     if (nf > 1) {
         P.fid = (uint32_t*)take(4 * N);
         P.keep_ex = (uint32_t*)take(4 * (N + 1));

@@ -11,15 +11,16 @@ constexpr uint32_t QMAX = (1u << MORTON_BITS) - 1u;
 
 // Tile sizes.
 constexpr int SORT_BLOCK = 256;               // radix-sort workgroup
-constexpr int SORT_ITEMS = 4;                 // keys per thread
-constexpr int SORT_TILE = SORT_BLOCK * SORT_ITEMS;
+constexpr uint32_t SORT_BIG_N = 1u << 20;     // above: 16 keys per thread, else 4
 constexpr int SORT_PASSES = 8;                // 8-bit digits over the 63-bit key
 constexpr int SORT_FRAME_PASSES_MAX = 2;      // 8-bit digits of the frame id (batches)
 constexpr int SORT_PASSES_MAX = SORT_PASSES + SORT_FRAME_PASSES_MAX;
 constexpr uint32_t MAX_FRAMES = 4096;         // frames per batched call (frame table staged in LDS)
 constexpr int SCAN_BLOCK = 256;
 constexpr int SCAN_ITEMS = 16;
-constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
+constexpr uint32_t SCAN_SMALL_N = 1u << 20;   // scans up to this size: 4 items per thread
+constexpr int SCAN_SLOTS = 6;                 // scans per call: leaves, P1, keep, 3 kNN plan scans
+constexpr int PLAN_LEVELS = 8;                // candidate chunk lengths chunk0 << 0..7 (parallel plan)
 constexpr int KNN_TQ = 16;                    // queries per kNN work item (one wave)
 constexpr int KNN_CC0 = 16384;                // default initial candidate chunk
 constexpr int KNN_NCH_MAX = 32;               // max candidate chunks per leaf
@@ -54,11 +55,14 @@ struct Counters {
     uint32_t n_items;
     uint32_t n_kept;
     uint32_t sort_tile_ctr[SORT_PASSES_MAX];
-    uint32_t scan_tile_ctr[4];
+    uint32_t scan_tile_ctr[SCAN_SLOTS];
     unsigned long long pairs;
     uint32_t knn_next;        // dynamic work-queue cursor of the kNN kernel
     uint32_t n_chunked_items; // kNN items of chunked leaves (they come first)
-    uint32_t pad[3];
+    uint32_t plan_cc;         // chosen kNN chunk length (parallel plan)
+    uint32_t pad[2];
+    unsigned long long plan_acc[PLAN_LEVELS][3];  // per candidate chunk length: lists, items, chunked items
+    unsigned long long plan_pairs;
 };
 
 // Frame constants derived on the device from the bounding box.
@@ -107,11 +111,13 @@ struct Plan {
     FrameStat* fstat;         // [nf]
     uint32_t* sort_hist;      // [SORT_PASSES_MAX][256]
     uint32_t* sort_status;    // [SORT_PASSES_MAX][sort_tiles][256]
-    uint32_t* scan_status;    // [4][scan_tiles]
+    uint32_t* scan_status;    // [SCAN_SLOTS][scan_tiles]
     uint32_t sort_tiles, scan_tiles;
+    uint32_t sort_items;      // keys per thread of the radix passes (4 or 16)
     // frames
     uint32_t* foff;           // [nf+1] frame offsets (checked copy of the caller's)
     uint32_t* fid;            // [n] frame of each point (original order; nf > 1 only)
+    uint32_t* bbox_part;      // [ceil(n / 1024)][8] per-chunk box (chunks inside one frame)
     FrameConst* fc;           // [nf]
     uint32_t* keep_ex;        // [n+1] exclusive count of kept points (original order; nf > 1)
     // sort (sorted order = s)

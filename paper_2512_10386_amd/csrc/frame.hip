@@ -97,13 +97,29 @@ __device__ __forceinline__ uint32_t frame_of(const uint32_t* foff, uint32_t nf, 
 
 // ---------------------------------------------------------------- bbox
 
-// Waves take chunks of BBOX_CHUNK consecutive points (coalesced); a chunk
-// inside one frame is reduced across the wave and added to that frame's
-// accumulators once, a chunk across a frame border (at most nf - 1 of them)
-// adds point by point. Batches also record each point's frame.
+// Waves take chunks of BBOX_CHUNK consecutive points (coalesced). A chunk
+// inside one frame writes its reduced box to bbox_part[chunk] and a second
+// kernel folds each frame's chunks (no contended atomics); a chunk across a
+// frame border (at most nf - 1 of them) reduces each of its frames over the
+// wave and adds them with atomics. With few chunks (`direct`) every chunk
+// uses the atomics and there is no fold. Batches also record each point's
+// frame.
 constexpr uint32_t BBOX_CHUNK = 1024;
 
-__global__ __launch_bounds__(256) void bbox_kernel(const float* __restrict__ xyz, Plan P) {
+__device__ __forceinline__ void bbox_reduce_wave(float* mn, float* mx, uint32_t& bad) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            mn[a] = fminf(mn[a], __shfl_xor(mn[a], o, 64));
+            mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], o, 64));
+        }
+        bad += __shfl_xor(bad, o, 64);
+    }
+}
+
+__global__ __launch_bounds__(256) void bbox_kernel(const float* __restrict__ xyz, Plan P, bool direct,
+                                                   uint32_t chunk) {
     __shared__ uint32_t s_foff[MAX_FRAMES + 1];
     const uint32_t n = P.n, nf = P.nf;
     if (nf > 1) {
@@ -112,67 +128,96 @@ __global__ __launch_bounds__(256) void bbox_kernel(const float* __restrict__ xyz
     }
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
-    const uint32_t nchunks = (n + BBOX_CHUNK - 1) / BBOX_CHUNK;
+    const uint32_t nchunks = (n + chunk - 1) / chunk;
     for (uint32_t c = wid; c < nchunks; c += nw) {
-        const uint32_t base = c * BBOX_CHUNK, end = min(n, base + BBOX_CHUNK);
+        const uint32_t base = c * chunk, end = min(n, base + chunk);
         const uint32_t f0 = nf > 1 ? frame_of(s_foff, nf, base) : 0u;
         const uint32_t f1 = nf > 1 ? frame_of(s_foff, nf, end - 1u) : 0u;
-        float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-        uint32_t bad = 0;
-        for (uint32_t i = base + lane; i < end; i += 64u) {
-            const float x = xyz[3 * (size_t)i], y = xyz[3 * (size_t)i + 1], z = xyz[3 * (size_t)i + 2];
-            const bool ok = isfinite(x) && isfinite(y) && isfinite(z);
-            if (f0 == f1) {
-                if (ok) {
+        for (uint32_t f = f0; f <= f1; ++f) {
+            const uint32_t lo = f == f0 ? base : max(base, s_foff[f]);
+            const uint32_t hi = f == f1 ? end : min(end, s_foff[f + 1]);
+            float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+            uint32_t bad = 0;
+            for (uint32_t i = lo + lane; i < hi; i += 64u) {
+                const float x = xyz[3 * (size_t)i], y = xyz[3 * (size_t)i + 1], z = xyz[3 * (size_t)i + 2];
+                if (isfinite(x) && isfinite(y) && isfinite(z)) {
                     mn[0] = fminf(mn[0], x); mx[0] = fmaxf(mx[0], x);
                     mn[1] = fminf(mn[1], y); mx[1] = fmaxf(mx[1], y);
                     mn[2] = fminf(mn[2], z); mx[2] = fmaxf(mx[2], z);
                 } else {
                     ++bad;
                 }
+                if (nf > 1) P.fid[i] = f;
+            }
+            bbox_reduce_wave(mn, mx, bad);
+            if (f0 == f1 && !direct) {
+                // whole chunk in one frame: ordered-uint max of -min / max, bad count
+                uint32_t* part = P.bbox_part + 8 * (size_t)c;
+                if (lane < 3u) {
+                    part[lane] = mn[lane] <= mx[lane] ? ~f32_ordered(mn[lane]) : 0u;
+                    part[3 + lane] = mn[lane] <= mx[lane] ? f32_ordered(mx[lane]) : 0u;
+                }
+                if (lane == 3u) part[6] = bad;
             } else {
-                const uint32_t f = frame_of(s_foff, nf, i);
                 FrameStat* fs = P.fstat + f;
-                if (ok) {
-                    atomicMax(&fs->bbox_nmin[0], ~f32_ordered(x)); atomicMax(&fs->bbox_max[0], f32_ordered(x));
-                    atomicMax(&fs->bbox_nmin[1], ~f32_ordered(y)); atomicMax(&fs->bbox_max[1], f32_ordered(y));
-                    atomicMax(&fs->bbox_nmin[2], ~f32_ordered(z)); atomicMax(&fs->bbox_max[2], f32_ordered(z));
-                } else {
-                    atomicAdd(&fs->nonfinite, 1u);
+                if (lane < 3u && mn[lane] <= mx[lane]) {
+                    atomicMax(&fs->bbox_nmin[lane], ~f32_ordered(mn[lane]));
+                    atomicMax(&fs->bbox_max[lane], f32_ordered(mx[lane]));
+                }
+                if (lane == 3u && bad) {
+                    atomicAdd(&fs->nonfinite, bad);
                     atomicOr(&P.ctr->status, DEV_NONFINITE);
                 }
-            }
-            if (nf > 1) P.fid[i] = f0 == f1 ? f0 : frame_of(s_foff, nf, i);
-        }
-        if (f0 == f1) {
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    mn[a] = fminf(mn[a], __shfl_xor(mn[a], o, 64));
-                    mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], o, 64));
-                }
-                bad += __shfl_xor(bad, o, 64);
-            }
-            if (lane < 3u && mn[lane] <= mx[lane]) {
-                FrameStat* fs = P.fstat + f0;
-                atomicMax(&fs->bbox_nmin[lane], ~f32_ordered(mn[lane]));
-                atomicMax(&fs->bbox_max[lane], f32_ordered(mx[lane]));
-            }
-            if (lane == 3u && bad) {
-                atomicAdd(&P.fstat[f0].nonfinite, bad);
-                atomicOr(&P.ctr->status, DEV_NONFINITE);
             }
         }
     }
 }
 
+// One wave per frame: fold the frame's whole chunks into its accumulators.
+__global__ __launch_bounds__(256) void bbox_fold_kernel(Plan P) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t f = wid; f < P.nf; f += nw) {
+        const uint32_t fs = P.foff[f], fe = P.foff[f + 1];
+        const uint32_t c0 = (fs + BBOX_CHUNK - 1) / BBOX_CHUNK;
+        const uint32_t c1 = fe == P.n ? (fe + BBOX_CHUNK - 1) / BBOX_CHUNK : fe / BBOX_CHUNK;
+        uint32_t v[7] = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
+        for (uint32_t c = c0 + lane; c < c1; c += 64u) {
+            const uint32_t* part = P.bbox_part + 8 * (size_t)c;
+#pragma unroll
+            for (int a = 0; a < 6; ++a) v[a] = max(v[a], part[a]);
+            v[6] += part[6];
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+            for (int a = 0; a < 6; ++a) v[a] = max(v[a], (uint32_t)__shfl_xor((int)v[a], o, 64));
+            v[6] += (uint32_t)__shfl_xor((int)v[6], o, 64);
+        }
+        FrameStat* st = P.fstat + f;
+        if (lane < 3u) {
+            if (v[lane]) atomicMax(&st->bbox_nmin[lane], v[lane]);
+            if (v[3 + lane]) atomicMax(&st->bbox_max[lane], v[3 + lane]);
+        }
+        if (lane == 3u && v[6]) atomicAdd(&st->nonfinite, v[6]);
+        if (lane == 4u && (v[6] || st->nonfinite)) atomicOr(&P.ctr->status, DEV_NONFINITE);
+    }
+}
+
 void launch_bbox(const Plan& P, const float* xyz, hipStream_t st) {
-    const uint32_t nchunks = (P.n + BBOX_CHUNK - 1) / BBOX_CHUNK;
+    // few points: 4096-point chunks that all add their boxes with atomics (no
+    // fold launch); otherwise BBOX_CHUNK chunks and the fold
+    const bool direct = P.n <= (1u << 20);
+    const uint32_t chunk = direct ? 4096u : BBOX_CHUNK;
+    const uint32_t nchunks = (P.n + chunk - 1) / chunk;
     unsigned blocks = (nchunks + 3) / 4;
     if (blocks > 2048) blocks = 2048;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(bbox_kernel, dim3(blocks), dim3(256), 0, st, xyz, P);
+    hipLaunchKernelGGL(bbox_kernel, dim3(blocks), dim3(256), 0, st, xyz, P, direct, chunk);
+    if (direct) return;
+    unsigned fb = (P.nf + 3) / 4;
+    if (fb > 1024) fb = 1024;
+    hipLaunchKernelGGL(bbox_fold_kernel, dim3(fb), dim3(256), 0, st, P);
 }
 
 // ---------------------------------------------------------------- Morton keys
@@ -258,6 +303,7 @@ void launch_morton(const Plan& P, const Params& prm, const float* xyz, hipStream
 // decoupled look-back (bounded waits), global digit bases from the histogram.
 // Passes past the key's 8 take the digit from the frame id of the payload
 // (the original index), so a batch ends sorted by (frame, key, index).
+template <int ITEMS>
 __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* __restrict__ kin,
                                                                 const uint32_t* __restrict__ vin,
                                                                 uint64_t* __restrict__ kout,
@@ -275,12 +321,12 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
     if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
-    const uint32_t tbase = tile * SORT_TILE + wave * (64 * SORT_ITEMS);
+    const uint32_t tbase = tile * (SORT_BLOCK * ITEMS) + wave * (64 * ITEMS);
 
-    uint64_t key[SORT_ITEMS];
-    uint32_t val[SORT_ITEMS], dig[SORT_ITEMS], rank[SORT_ITEMS];
+    uint64_t key[ITEMS];
+    uint32_t val[ITEMS], dig[ITEMS], rank[ITEMS];
 #pragma unroll
-    for (int i = 0; i < SORT_ITEMS; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         uint32_t pos = tbase + i * 64 + lane;
         bool ok = pos < n;
         key[i] = ok ? kin[pos] : 0ull;
@@ -291,7 +337,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
     }
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-    for (int i = 0; i < SORT_ITEMS; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         const uint32_t d = dig[i];
         const bool ok = d < 256u;
         uint64_t m = __ballot(ok);
@@ -371,7 +417,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
     s_base[tid] = gex + excl;
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < SORT_ITEMS; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         const uint32_t d = dig[i];
         if (d < 256u) {
             const uint32_t o = s_base[d] + s_w[wave][d] + rank[i];
@@ -390,7 +436,9 @@ void launch_sort(const Plan& P, hipStream_t st) {
     uint64_t* kout = P.keys_src == P.keys_a ? P.keys_b : P.keys_a;
     uint32_t* vout = P.idx_src == P.idx_a ? P.idx_b : P.idx_a;
     for (uint32_t pass = 0; pass < P.sort_passes; ++pass) {
-        hipLaunchKernelGGL(radix_pass_kernel, dim3(P.sort_tiles), dim3(SORT_BLOCK), 0, st, kin, vin, kout, vout,
+        // small inputs: many small tiles (latency); large: fewer, fuller tiles
+        auto kern = P.sort_items == 4 ? radix_pass_kernel<4> : radix_pass_kernel<16>;
+        hipLaunchKernelGGL(kern, dim3(P.sort_tiles), dim3(SORT_BLOCK), 0, st, kin, vin, kout, vout,
                            P.n, (int)pass, P.sort_hist + 256 * pass,
                            P.sort_status + (size_t)pass * P.sort_tiles * 256, &P.ctr->sort_tile_ctr[pass],
                            &P.ctr->status, (const uint32_t*)P.fid);

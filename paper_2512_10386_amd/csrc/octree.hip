@@ -138,9 +138,14 @@ __device__ __forceinline__ uint64_t vox_key(float4 p, float mx_, float my_, floa
     return k;
 }
 
+// SLOTS: LDS hash capacity, picked from the leaf cap so that small-leaf
+// octrees keep many workgroups per CU; leaves above SLOTS/2 points (only
+// over-full leaves at the depth limit, or caps above 2048) use the global
+// per-leaf region.
+template <int SLOTS>
 __global__ __launch_bounds__(VOX_BLOCK) void voxel_kernel(Plan P, double beta, uint32_t nv) {
-    __shared__ unsigned long long s_key[VOX_LDS_SLOTS];
-    __shared__ uint32_t s_cnt[VOX_LDS_SLOTS];
+    __shared__ unsigned long long s_key[SLOTS];
+    __shared__ uint32_t s_cnt[SLOTS];
     __shared__ float s_red[6][VOX_BLOCK / 64];
     __shared__ float s_mn[3];
     __shared__ float s_h;
@@ -190,15 +195,21 @@ __global__ __launch_bounds__(VOX_BLOCK) void voxel_kernel(Plan P, double beta, u
         } else {
             const double h = (double)h32;
             const float m0 = s_mn[0], m1 = s_mn[1], m2 = s_mn[2];
-            const bool lds = nt <= VOX_LDS_SLOTS / 2;
-            const uint32_t slots = lds ? (uint32_t)VOX_LDS_SLOTS : 2u * nt;
+            // LDS table sized to the leaf: a power of two >= 2 nt (>= 64)
+            const bool lds = nt <= SLOTS / 2;
+            uint32_t slots = 2u * nt;
+            if (lds) {
+                uint32_t p2 = 64u;
+                while (p2 < slots) p2 <<= 1;
+                slots = p2;
+            }
             unsigned long long* tk = lds ? s_key : (unsigned long long*)(P.vox_keys + 2 * (size_t)b);
             uint32_t* tc = lds ? s_cnt : P.vox_cnt + 2 * (size_t)b;
             for (uint32_t i = tid; i < slots; i += VOX_BLOCK) { tk[i] = EMPTY; tc[i] = 0u; }
             __syncthreads();
             for (uint32_t s = b + tid; s < e; s += VOX_BLOCK) {
                 const unsigned long long k = vox_key(P.pos4[s], m0, m1, m2, h);
-                uint32_t slot = vox_hash(k) % slots;
+                uint32_t slot = lds ? (vox_hash(k) & (slots - 1u)) : vox_hash(k) % slots;
                 for (uint32_t probe = 0; probe < slots; ++probe) {
                     unsigned long long prev = atomicCAS(&tk[slot], EMPTY, k);
                     if (prev == EMPTY || prev == k) {
@@ -211,7 +222,7 @@ __global__ __launch_bounds__(VOX_BLOCK) void voxel_kernel(Plan P, double beta, u
             __syncthreads();
             for (uint32_t s = b + tid; s < e; s += VOX_BLOCK) {
                 const unsigned long long k = vox_key(P.pos4[s], m0, m1, m2, h);
-                uint32_t slot = vox_hash(k) % slots;
+                uint32_t slot = lds ? (vox_hash(k) & (slots - 1u)) : vox_hash(k) % slots;
                 uint32_t c = 0;
                 for (uint32_t probe = 0; probe < slots; ++probe) {
                     if (tk[slot] == k) { c = tc[slot]; break; }
@@ -226,10 +237,15 @@ __global__ __launch_bounds__(VOX_BLOCK) void voxel_kernel(Plan P, double beta, u
 }
 
 void launch_voxel(const Plan& P, const Params& prm, hipStream_t st) {
-    unsigned blocks = P.n < 2048 ? P.n : 2048;
+    unsigned blocks = P.n / 128;
+    if (blocks > 16384) blocks = 16384;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(voxel_kernel, dim3(blocks), dim3(VOX_BLOCK), 0, st, P, prm.beta,
-                       (uint32_t)prm.min_vox_count);
+    if (prm.leaf_cap <= 256)
+        hipLaunchKernelGGL(voxel_kernel<512>, dim3(blocks), dim3(VOX_BLOCK), 0, st, P, prm.beta,
+                           (uint32_t)prm.min_vox_count);
+    else
+        hipLaunchKernelGGL(voxel_kernel<VOX_LDS_SLOTS>, dim3(blocks), dim3(VOX_BLOCK), 0, st, P, prm.beta,
+                           (uint32_t)prm.min_vox_count);
 }
 
 // ---------------------------------------------------------------- P1 compaction
@@ -465,9 +481,149 @@ __global__ __launch_bounds__(PLAN_BLOCK) void knn_plan_kernel(Plan P, int chunk0
     }
 }
 
+// Parallel plan for large batches (the single workgroup above would walk
+// every leaf several times): one pass counts partial lists, items and
+// chunked items per leaf for each candidate chunk length chunk0 << l, a
+// single thread picks the first length that fits (else no chunking), and
+// three look-back scans over the leaves give the partial-list offsets and
+// the queue offsets of chunked and unchunked leaves.
+
+__device__ __forceinline__ uint32_t plan_nch(uint32_t n1, uint32_t nc, uint32_t cc) {
+    if (n1 == 0) return 1u;
+    uint32_t nch = (nc + cc - 1) / cc;
+    if (nch < 1) nch = 1;
+    if (nch > KNN_NCH_MAX) nch = KNN_NCH_MAX;
+    return nch;
+}
+
+__global__ __launch_bounds__(256) void plan_count_kernel(Plan P, uint32_t chunk0) {
+    __shared__ unsigned long long s_acc[PLAN_LEVELS * 3 + 1];
+    for (int i = threadIdx.x; i < PLAN_LEVELS * 3 + 1; i += blockDim.x) s_acc[i] = 0ull;
+    __syncthreads();
+    const uint32_t nl = P.ctr->n_leaves;
+    unsigned long long acc[PLAN_LEVELS * 3 + 1];
+#pragma unroll
+    for (int i = 0; i < PLAN_LEVELS * 3 + 1; ++i) acc[i] = 0ull;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nl; t += gridDim.x * blockDim.x) {
+        const uint32_t n1 = P.p1pos[P.leaf_begin[t + 1]] - P.p1pos[P.leaf_begin[t]], nc = P.leaf_ncand[t];
+        if (n1 == 0) continue;
+        const unsigned long long tiles = (n1 + KNN_TQ - 1) / KNN_TQ;
+#pragma unroll
+        for (int l = 0; l < PLAN_LEVELS; ++l) {
+            const uint32_t cc = chunk0 << l;
+            const uint32_t nch = plan_nch(n1, nc, cc);
+            if (nch > 1) {
+                acc[3 * l] += (unsigned long long)n1 * nch;
+                acc[3 * l + 2] += tiles * nch;
+            }
+            acc[3 * l + 1] += tiles * nch;
+        }
+        acc[PLAN_LEVELS * 3] += (unsigned long long)n1 * (nc - 1);
+    }
+#pragma unroll
+    for (int i = 0; i < PLAN_LEVELS * 3 + 1; ++i) {
+        unsigned long long v = acc[i];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0 && v) atomicAdd(&s_acc[i], v);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < PLAN_LEVELS * 3 + 1; i += blockDim.x) {
+        if (s_acc[i]) {
+            if (i < PLAN_LEVELS * 3) atomicAdd(&P.ctr->plan_acc[i / 3][i % 3], s_acc[i]);
+            else atomicAdd(&P.ctr->plan_pairs, s_acc[i]);
+        }
+    }
+}
+
+__global__ void plan_pick_kernel(Plan P, uint32_t chunk0) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    Counters* c = P.ctr;
+    uint32_t cc = 0x40000000u, chunked = 0;
+    unsigned long long items = 0;
+    for (int l = 0; l < PLAN_LEVELS; ++l) {
+        if (c->plan_acc[l][0] <= P.plist_max && c->plan_acc[l][1] <= P.items_max) {
+            cc = chunk0 << l;
+            items = c->plan_acc[l][1];
+            chunked = (uint32_t)c->plan_acc[l][2];
+            break;
+        }
+    }
+    if (cc == 0x40000000u) items = 0;  // no chunking: items counted by the scan below
+    c->plan_cc = cc;
+    c->n_chunked_items = chunked;
+    c->n_items = (uint32_t)items;
+    c->pairs = c->plan_pairs;
+}
+
+struct PlanLeaf {
+    const Plan* P;
+    __device__ void get(uint32_t t, uint32_t* n1, uint32_t* nc, uint32_t* nch) const {
+        *n1 = P->p1pos[P->leaf_begin[t + 1]] - P->p1pos[P->leaf_begin[t]];
+        *nc = P->leaf_ncand[t];
+        *nch = plan_nch(*n1, *nc, P->ctr->plan_cc);
+    }
+};
+struct ListsGet {
+    Plan P;
+    __device__ uint32_t operator()(uint32_t t) const {
+        uint32_t n1, nc, nch;
+        PlanLeaf{&P}.get(t, &n1, &nc, &nch);
+        return nch > 1 ? n1 * nch : 0u;
+    }
+};
+struct ListsEmit {
+    Plan P;
+    __device__ void operator()(uint32_t t, uint32_t ex, uint32_t) const {
+        uint32_t n1, nc, nch;
+        PlanLeaf{&P}.get(t, &n1, &nc, &nch);
+        P.leaf_nch[t] = nch;
+        P.leaf_cc[t] = (nc + nch - 1) / nch;
+        P.leaf_plist[t] = ex;
+    }
+};
+template <bool CHUNKED>
+struct ItemsGet {
+    Plan P;
+    __device__ uint32_t operator()(uint32_t t) const {
+        uint32_t n1, nc, nch;
+        PlanLeaf{&P}.get(t, &n1, &nc, &nch);
+        return ((nch > 1) == CHUNKED && n1) ? ((n1 + KNN_TQ - 1) / KNN_TQ) * nch : 0u;
+    }
+};
+template <bool CHUNKED>
+struct ItemsEmit {
+    Plan P;
+    __device__ void operator()(uint32_t t, uint32_t ex, uint32_t) const {
+        uint32_t n1, nc, nch;
+        PlanLeaf{&P}.get(t, &n1, &nc, &nch);
+        if ((nch > 1) == CHUNKED) P.leaf_item[t] = CHUNKED ? ex : P.ctr->n_chunked_items + ex;
+    }
+};
+struct NoFin {
+    __device__ void operator()(uint32_t) const {}
+};
+struct ItemsFin {
+    Counters* c;
+    __device__ void operator()(uint32_t total) const { c->n_items = c->n_chunked_items + total; }
+};
+
 void launch_knn_plan(const Plan& P, const Params& prm, hipStream_t st) {
     const int chunk0 = prm.knn_chunk > 0 ? prm.knn_chunk : KNN_CC0;
-    hipLaunchKernelGGL(knn_plan_kernel, dim3(1), dim3(PLAN_BLOCK), 0, st, P, chunk0);
+    if (P.n <= (1u << 19)) {
+        hipLaunchKernelGGL(knn_plan_kernel, dim3(1), dim3(PLAN_BLOCK), 0, st, P, chunk0);
+        return;
+    }
+    unsigned blocks = (P.n / 8 + 255) / 256;
+    if (blocks > 512) blocks = 512;
+    hipLaunchKernelGGL(plan_count_kernel, dim3(blocks), dim3(256), 0, st, P, (uint32_t)chunk0);
+    hipLaunchKernelGGL(plan_pick_kernel, dim3(1), dim3(64), 0, st, P, (uint32_t)chunk0);
+    const uint32_t* nl = &P.ctr->n_leaves;
+    launch_scan(ListsGet{P}, ListsEmit{P}, NoFin{}, nl, P.n, P.scan_status + 3 * (size_t)P.scan_tiles,
+                &P.ctr->scan_tile_ctr[3], &P.ctr->status, st);
+    launch_scan(ItemsGet<true>{P}, ItemsEmit<true>{P}, NoFin{}, nl, P.n, P.scan_status + 4 * (size_t)P.scan_tiles,
+                &P.ctr->scan_tile_ctr[4], &P.ctr->status, st);
+    launch_scan(ItemsGet<false>{P}, ItemsEmit<false>{P}, ItemsFin{P.ctr}, nl, P.n,
+                P.scan_status + 5 * (size_t)P.scan_tiles, &P.ctr->scan_tile_ctr[5], &P.ctr->status, st);
 }
 
 }  // namespace gdn

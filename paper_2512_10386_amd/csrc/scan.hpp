@@ -14,29 +14,44 @@ namespace gdn {
 // get(i)          -> value of element i (uint32, sum must stay < 2^30)
 // emit(i, ex, v)  -> called once per element with its exclusive prefix
 // fin(total)      -> called once with the grand total
-template <class Get, class Emit, class Fin>
+// A tile's elements are read and emitted striped (element base + i*SCAN_BLOCK
+// + thread: coalesced, and the get() calls of a thread are independent) and
+// scanned blocked (ITEMS consecutive elements per thread), with an LDS
+// transpose in between (padded one word per 32 against bank conflicts).
+__device__ __forceinline__ uint32_t scan_lds_at(uint32_t e) { return e + (e >> 5); }
+
+template <int ITEMS, class Get, class Emit, class Fin>
 __global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(Get get, Emit emit, Fin fin,
                                                           const uint32_t* n_dev, uint32_t n_host,
                                                           uint32_t* status, uint32_t* tile_ctr,
                                                           uint32_t* dev_status) {
     __shared__ uint32_t s_tile, s_excl;
     __shared__ uint32_t s_scan[SCAN_BLOCK / 64 + 1];
+    constexpr uint32_t TILE = SCAN_BLOCK * ITEMS;
+    __shared__ uint32_t s_val[TILE + TILE / 32];
+    __shared__ uint32_t s_pre[TILE + TILE / 32];
     const uint32_t n = n_dev ? *n_dev : n_host;
     if (threadIdx.x == 0) s_tile = atomicAdd(tile_ctr, 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
-    const uint32_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    const uint32_t ntiles = (n + TILE - 1) / TILE;
     if (tile >= ntiles) {
         if (n == 0 && tile == 0 && threadIdx.x == 0) fin(0u);
         return;
     }
-    const uint32_t base = tile * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
-    uint32_t v[SCAN_ITEMS];
+    const uint32_t tbase = tile * TILE;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t e = (uint32_t)i * SCAN_BLOCK + threadIdx.x;
+        const uint32_t idx = tbase + e;
+        s_val[scan_lds_at(e)] = idx < n ? get(idx) : 0u;
+    }
+    __syncthreads();
+    uint32_t v[ITEMS];
     uint32_t sum = 0;
 #pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        uint32_t idx = base + i;
-        v[i] = idx < n ? get(idx) : 0u;
+    for (int i = 0; i < ITEMS; ++i) {
+        v[i] = s_val[scan_lds_at(threadIdx.x * ITEMS + i)];
         sum += v[i];
     }
     uint32_t agg;
@@ -86,23 +101,40 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(Get get, Emit emit, Fi
     __syncthreads();
     uint32_t run = s_excl + ex;
 #pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        uint32_t idx = base + i;
-        if (idx < n) {
-            emit(idx, run, v[i]);
-            run += v[i];
-        }
+    for (int i = 0; i < ITEMS; ++i) {
+        s_pre[scan_lds_at(threadIdx.x * ITEMS + i)] = run;
+        run += v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t e = (uint32_t)i * SCAN_BLOCK + threadIdx.x;
+        const uint32_t idx = tbase + e;
+        if (idx < n) emit(idx, s_pre[scan_lds_at(e)], s_val[scan_lds_at(e)]);
     }
     if (tile == ntiles - 1 && threadIdx.x == 0) fin(s_excl + agg);
+}
+
+// Items per thread for a scan over at most n_max elements: small scans use
+// small tiles (more of them in flight), large ones full 16-item tiles. The
+// status words must hold scan_tiles_for(n_max) entries.
+inline uint32_t scan_items_for(uint32_t n_max) { return n_max <= SCAN_SMALL_N ? 4u : (uint32_t)SCAN_ITEMS; }
+inline uint32_t scan_tiles_for(uint32_t n_max) {
+    const uint32_t tile = SCAN_BLOCK * scan_items_for(n_max);
+    const uint32_t t = (n_max + tile - 1) / tile;
+    return t ? t : 1u;
 }
 
 template <class Get, class Emit, class Fin>
 inline void launch_scan(Get get, Emit emit, Fin fin, const uint32_t* n_dev, uint32_t n_max,
                         uint32_t* status, uint32_t* tile_ctr, uint32_t* dev_status, hipStream_t st) {
-    uint32_t tiles = (n_max + SCAN_TILE - 1) / SCAN_TILE;
-    if (tiles == 0) tiles = 1;
-    scan_kernel<Get, Emit, Fin><<<dim3(tiles), dim3(SCAN_BLOCK), 0, st>>>(get, emit, fin, n_dev, n_max, status,
-                                                                          tile_ctr, dev_status);
+    const uint32_t tiles = scan_tiles_for(n_max);
+    if (scan_items_for(n_max) == 4u)
+        scan_kernel<4, Get, Emit, Fin><<<dim3(tiles), dim3(SCAN_BLOCK), 0, st>>>(get, emit, fin, n_dev, n_max,
+                                                                                 status, tile_ctr, dev_status);
+    else
+        scan_kernel<SCAN_ITEMS, Get, Emit, Fin><<<dim3(tiles), dim3(SCAN_BLOCK), 0, st>>>(
+            get, emit, fin, n_dev, n_max, status, tile_ctr, dev_status);
 }
 
 }  // namespace gdn

@@ -5,6 +5,7 @@
 
 #include "kernels.hpp"
 #include "scan.hpp"
+#include "wave.hpp"
 
 namespace gdn {
 
@@ -16,9 +17,9 @@ constexpr double PI_D = 3.14159265358979323846;
 // r_K,i = the largest FP64 distance to the k neighbours; rho_i = K / (4/3 pi r^3).
 // A point with fewer than k candidates has rho = 0 (r = inf).
 //
-// Density and score gather their neighbours one lane each: a wave holds
-// 64 / kp queries, kp = k rounded up to a power of two, lane r of a segment
-// takes neighbour r, and segment reductions combine them.
+// The score gathers its neighbours one lane each: a wave holds 64 / kp
+// queries, kp = k rounded up to a power of two, lane r of a segment takes
+// neighbour r, and a segment reduction adds the terms.
 
 __device__ __forceinline__ uint32_t pow2_at_least(uint32_t k) {
     uint32_t p = 1;
@@ -26,63 +27,51 @@ __device__ __forceinline__ uint32_t pow2_at_least(uint32_t k) {
     return p;
 }
 
-__device__ __forceinline__ double seg_max(double v, uint32_t kp) {
-    for (uint32_t o = kp >> 1; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, (int)o, 64));
-    return v;
-}
-
 __device__ __forceinline__ double seg_sum(double v, uint32_t kp) {
     for (uint32_t o = kp >> 1; o > 0; o >>= 1) v += __shfl_xor(v, (int)o, 64);
     return v;
 }
 
+// One thread per query. The list is sorted by fp32 d2, and fp32 d2 is within
+// ~6e-7 relative of the exact value, so only the neighbours whose fp32 d2 is
+// within 2^-16 of the k-th can hold the FP64 maximum: walk down from the
+// k-th and stop at the first one below that (usually after one or two).
 __global__ __launch_bounds__(256) void density_kernel(Plan P, const float* __restrict__ xyz, int kk) {
     const uint32_t np1 = P.ctr->n_p1;
-    const uint32_t k = (uint32_t)kk, kp = pow2_at_least(k), qpw = 64u / kp;
-    const uint32_t lane = threadIdx.x & 63u, seg = lane / kp, r = lane % kp;
-    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
-    for (uint32_t q0 = wid * qpw; q0 < np1; q0 += nw * qpw) {
-        const uint32_t qi = q0 + seg;
-        const bool live = qi < np1;
-        double m2 = 0.0;
-        bool insufficient = true;
-        uint32_t i = 0;
-        if (live) {
-            i = __float_as_uint(P.cand4[qi].w);
-            const uint32_t* nb = P.nbr + (size_t)qi * k;
-            insufficient = nb[k - 1] == NO_NBR;
-            if (!insufficient && r < k) {
+    const uint32_t k = (uint32_t)kk;
+    for (uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x; qi < np1; qi += gridDim.x * blockDim.x) {
+        const uint32_t* nb = P.nbr + (size_t)qi * k;
+        const float* d2 = P.nbr_d2 + (size_t)qi * k;
+        double rho, r64;
+        if (nb[k - 1] == NO_NBR) {
+            rho = 0.0;
+            r64 = INFINITY;
+        } else {
+            const uint32_t i = __float_as_uint(P.cand4[qi].w);
+            const double xi = xyz[3 * (size_t)i], yi = xyz[3 * (size_t)i + 1], zi = xyz[3 * (size_t)i + 2];
+            const float thr = P.r2k[qi] * (1.0f - 1.0f / 65536.0f);
+            double m2 = 0.0;
+            for (int r = (int)k - 1; r >= 0; --r) {
+                if (d2[r] < thr) break;
                 const uint32_t j = nb[r];
-                if (j < P.n) {
-                    const double dx = (double)xyz[3 * (size_t)j] - (double)xyz[3 * (size_t)i];
-                    const double dy = (double)xyz[3 * (size_t)j + 1] - (double)xyz[3 * (size_t)i + 1];
-                    const double dz = (double)xyz[3 * (size_t)j + 2] - (double)xyz[3 * (size_t)i + 2];
-                    m2 = dx * dx + dy * dy + dz * dz;
-                }
+                if (j >= P.n) continue;
+                const double dx = (double)xyz[3 * (size_t)j] - xi;
+                const double dy = (double)xyz[3 * (size_t)j + 1] - yi;
+                const double dz = (double)xyz[3 * (size_t)j + 2] - zi;
+                const double v = dx * dx + dy * dy + dz * dz;
+                if (v > m2) m2 = v;
             }
+            r64 = sqrt(m2);
+            rho = (double)k / ((4.0 / 3.0) * PI_D * (r64 * r64 * r64));
         }
-        m2 = seg_max(m2, kp);
-        if (live && r == 0) {
-            double rho, r64;
-            if (insufficient) {
-                rho = 0.0;
-                r64 = INFINITY;
-            } else {
-                r64 = sqrt(m2);
-                rho = (double)k / ((4.0 / 3.0) * PI_D * (r64 * r64 * r64));
-            }
-            P.rho_c[qi] = rho;
-            P.r64_c[qi] = r64;
-        }
+        P.rho_c[qi] = rho;
+        P.r64_c[qi] = r64;
     }
 }
 
 void launch_density(const Plan& P, const Params& prm, const float* xyz, hipStream_t st) {
-    uint32_t kp = 1;
-    while (kp < (uint32_t)prm.k) kp <<= 1;
-    const uint64_t waves = ((uint64_t)P.n * kp + 63) / 64;
-    unsigned blocks = (unsigned)((waves + 3) / 4);
-    if (blocks > 8192) blocks = 8192;
+    unsigned blocks = (P.n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
     if (blocks == 0) blocks = 1;
     hipLaunchKernelGGL(density_kernel, dim3(blocks), dim3(256), 0, st, P, xyz, prm.k);
 }
@@ -144,6 +133,8 @@ struct LdsBits {
 };
 
 constexpr uint32_t SEL_LDS_MAX = 2048;  // leaves up to this size are selected from LDS
+constexpr uint32_t SMALL_LEAF = 256;    // leaves up to this size: one wave (4 values per lane), no LDS
+constexpr uint32_t SMALL_PATH_MIN_N = 1u << 20;  // the wave path is used above this many points
 
 struct R2Bits {
     const float* r2k;
@@ -183,7 +174,7 @@ __device__ void leaf_cut_and_median(RG r2, HG rho, uint32_t n1, double q, float*
     }
 }
 
-__global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params prm) {
+__global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params prm, bool small) {
     __shared__ uint32_t s_hist[256];
     __shared__ uint32_t s_sel[2];
     __shared__ uint32_t s_r2[SEL_LDS_MAX];
@@ -193,6 +184,7 @@ __global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params p
     for (uint32_t t = blockIdx.x; t < nl; t += gridDim.x) {
         const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
         const uint32_t n1 = qe - qb;
+        if (small && n1 <= SMALL_LEAF) continue;  // leaf_select_small_kernel
         if (n1 == 0) {
             if (threadIdx.x == 0) { P.leaf_rho_med[t] = 0.0; P.leaf_r2cut[t] = 0.0f; }
             continue;
@@ -226,10 +218,85 @@ __global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params p
     }
 }
 
+// Leaves with at most SMALL_LEAF (= 256) P1 points: one wave each, no block
+// barriers. The values (point i of the leaf in register i / 64 of lane
+// i % 64; padding ~0) are sorted descending across the wave by a bitonic
+// network (DPP exchanges; 64 values need one register, up to 256 four), and
+// ranks are read from the sorted order.
+struct WaveVals {
+    unsigned long long v[4];
+};
+
+__device__ __forceinline__ unsigned long long wave_rank_value(WaveVals w, uint32_t n1, uint32_t lane, uint32_t r) {
+    // ascending rank r (0-based, r < n1) of the n1 values; the padding sorts first
+    if (n1 <= 64u) {
+        const unsigned long long s = sort64_desc(w.v[0], lane);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)s, 63 - (int)r);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(s >> 32), 63 - (int)r);
+        return ((unsigned long long)hi << 32) | lo;
+    }
+    sort256_desc(w.v, lane);
+    return read_elem256(w.v, 255u - r);
+}
+
+__global__ __launch_bounds__(256) void leaf_select_small_kernel(Plan P, Params prm) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t nl = P.ctr->n_leaves;
+    const int k = prm.k;
+    const double ha = prm.alpha / 2.0;
+    for (uint32_t t = wid; t < nl; t += nw) {
+        const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
+        const uint32_t n1 = qe - qb;
+        if (n1 > SMALL_LEAF) continue;
+        if (n1 == 0) {
+            if (lane == 0) { P.leaf_rho_med[t] = 0.0; P.leaf_r2cut[t] = 0.0f; }
+            continue;
+        }
+        WaveVals r2v, rhov;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t i = (uint32_t)j * 64u + lane;
+            r2v.v[j] = i < n1 ? (unsigned long long)__float_as_uint(P.r2k[qb + i]) : ~0ull;
+            rhov.v[j] = i < n1 ? (unsigned long long)__double_as_longlong(P.rho_c[qb + i]) : ~0ull;
+        }
+        double cd = ceil((double)n1 * prm.rho_percentile / 100.0 + 0.5);
+        if (cd < 1.0) cd = 1.0;
+        if (cd > (double)n1) cd = (double)n1;
+        const uint32_t c = (uint32_t)cd;
+        const float cut = __uint_as_float((uint32_t)wave_rank_value(r2v, n1, lane, n1 - c));
+        double med;
+        if (n1 & 1u) {
+            med = __longlong_as_double((long long)wave_rank_value(rhov, n1, lane, (n1 - 1) / 2));
+        } else {
+            const double a = __longlong_as_double((long long)wave_rank_value(rhov, n1, lane, n1 / 2 - 1));
+            const double b = __longlong_as_double((long long)wave_rank_value(rhov, n1, lane, n1 / 2));
+            med = (a + b) / 2.0;
+        }
+        const double den = med * med + prm.eps;
+        for (uint32_t i = lane; i < n1; i += 64u) {
+            const uint32_t qi = qb + i;
+            const bool insufficient = P.nbr[(size_t)qi * k + (k - 1)] == NO_NBR;
+            const double rho = P.rho_c[qi];
+            P.p2[qi] = (!insufficient && P.r2k[qi] <= cut) ? 1 : 0;
+            P.afac_c[qi] = pow(rho / den, ha);
+            P.gpow_o[__float_as_uint(P.cand4[qi].w)] = pow(rho, ha);
+        }
+        if (lane == 0) { P.leaf_rho_med[t] = med; P.leaf_r2cut[t] = cut; }
+    }
+}
+
 void launch_leaf_select(const Plan& P, const Params& prm, hipStream_t st) {
+    // the wave path pays off for the many small leaves of large batches
+    const bool small = P.n > SMALL_PATH_MIN_N;
+    if (small) {
+        unsigned wb = (P.n / 128 + 3) / 4;
+        if (wb > 8192) wb = 8192;
+        hipLaunchKernelGGL(leaf_select_small_kernel, dim3(wb), dim3(256), 0, st, P, prm);
+    }
     unsigned blocks = P.n < 2048 ? P.n : 2048;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(leaf_select_kernel, dim3(blocks), dim3(SEL_BLOCK), 0, st, P, prm);
+    hipLaunchKernelGGL(leaf_select_kernel, dim3(blocks), dim3(SEL_BLOCK), 0, st, P, prm, small);
 }
 
 // ---------------------------------------------------------------- score
@@ -324,7 +391,7 @@ struct CandIdx {
     __device__ uint32_t operator()(uint32_t i) const { return __float_as_uint(cand4[qb + i].w); }
 };
 
-__global__ __launch_bounds__(SEL_BLOCK) void topl_kernel(Plan P, double lambda) {
+__global__ __launch_bounds__(SEL_BLOCK) void topl_kernel(Plan P, double lambda, bool small) {
     __shared__ uint32_t s_hist[256];
     __shared__ uint32_t s_sel[2];
     __shared__ uint32_t s_cnt;
@@ -334,6 +401,7 @@ __global__ __launch_bounds__(SEL_BLOCK) void topl_kernel(Plan P, double lambda) 
     for (uint32_t t = blockIdx.x; t < nl; t += gridDim.x) {
         const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
         const uint32_t n1 = qe - qb;
+        if (small && n1 <= SMALL_LEAF) continue;  // topl_small_kernel
         if (threadIdx.x == 0) s_cnt = 0;
         __syncthreads();
         uint32_t c = 0;
@@ -379,10 +447,92 @@ __global__ __launch_bounds__(SEL_BLOCK) void topl_kernel(Plan P, double lambda) 
     }
 }
 
+// Small leaves: theta = the m-th largest key from a wave sort; keys above it
+// are kept, and among the keys equal to it the `need` smallest indices.
+__global__ __launch_bounds__(256) void topl_small_kernel(Plan P, double lambda) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t nl = P.ctr->n_leaves;
+    for (uint32_t t = wid; t < nl; t += nw) {
+        const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
+        const uint32_t n1 = qe - qb;
+        if (n1 > SMALL_LEAF) continue;
+        const ScoreKey sk{P.score_c, P.p2, qb};
+        WaveVals kv;
+        uint32_t oi[4];
+        uint32_t n2 = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t i = (uint32_t)j * 64u + lane;
+            const bool in = i < n1;
+            kv.v[j] = in ? sk(i) : 0ull;
+            oi[j] = in ? __float_as_uint(P.cand4[qb + i].w) : 0xFFFFFFFFu;
+            n2 += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in && P.p2[qb + i]));
+        }
+        uint32_t m = 0;
+        if (n2 > 0) {
+            const double mf = ceil(lambda * (double)n2);
+            m = mf >= (double)n2 ? n2 : (uint32_t)mf;
+        }
+        unsigned long long theta = ~0ull;
+        uint32_t need = 0;
+        bool ties_cut = false;
+        if (m > 0) {
+            WaveVals srt = kv;
+            if (n1 <= 64u) {
+                srt.v[0] = sort64_desc(srt.v[0], lane);
+                const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)srt.v[0], (int)m - 1);
+                const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(srt.v[0] >> 32), (int)m - 1);
+                theta = ((unsigned long long)hi << 32) | lo;
+            } else {
+                sort256_desc(srt.v, lane);
+                theta = read_elem256(srt.v, m - 1);
+            }
+            uint32_t greater = 0, equal = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool in = (uint32_t)j * 64u + lane < n1;
+                greater += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in && kv.v[j] > theta));
+                equal += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in && kv.v[j] == theta));
+            }
+            need = m - greater;
+            ties_cut = equal > need;
+        }
+        // ties at theta ranked by original index (whole-wave ballots)
+        uint32_t below[4] = {0u, 0u, 0u, 0u};
+        if (ties_cut) {
+#pragma unroll
+            for (int j2 = 0; j2 < 4; ++j2) {
+                unsigned long long e = __builtin_amdgcn_ballot_w64((uint32_t)j2 * 64u + lane < n1 && kv.v[j2] == theta);
+                while (e) {
+                    const int l = __ffsll((long long)e) - 1;
+                    e &= e - 1ull;
+                    const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)oi[j2], l);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) below[j] += o < oi[j] ? 1u : 0u;
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t i = (uint32_t)j * 64u + lane;
+            const bool kept = m > 0 && (kv.v[j] > theta || (kv.v[j] == theta && (!ties_cut || below[j] < need)));
+            if (i < n1) P.stage_c[qb + i] = P.p2[qb + i] ? (kept ? 3 : 2) : 1;
+        }
+        if (lane == 0) P.leaf_m[t] = m;
+    }
+}
+
 void launch_topl(const Plan& P, const Params& prm, hipStream_t st) {
+    const bool small = P.n > SMALL_PATH_MIN_N;
+    if (small) {
+        unsigned wb = (P.n / 128 + 3) / 4;
+        if (wb > 8192) wb = 8192;
+        hipLaunchKernelGGL(topl_small_kernel, dim3(wb), dim3(256), 0, st, P, prm.keep_ratio);
+    }
     unsigned blocks = P.n < 2048 ? P.n : 2048;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(topl_kernel, dim3(blocks), dim3(SEL_BLOCK), 0, st, P, prm.keep_ratio);
+    hipLaunchKernelGGL(topl_kernel, dim3(blocks), dim3(SEL_BLOCK), 0, st, P, prm.keep_ratio, small);
 }
 
 // ---------------------------------------------------------------- outputs

@@ -1,0 +1,171 @@
+// Wave-level (64-lane) exchange helpers for gfx950: lane ^ M exchanges
+// without LDS, bitonic sorts and merges of one 64-bit key per lane, and
+// min / max reductions.
+#pragma once
+
+#include "common.hpp"
+
+namespace gdn {
+
+// Value of lane ^ M, without LDS: DPP quad permutes (1, 2), row rotations
+// (4, 8) and the gfx950 permlane swaps (16, 32).
+template <int M>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t x, uint32_t lane) {
+    if constexpr (M == 1) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0u, x, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    } else if constexpr (M == 2) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0u, x, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    } else if constexpr (M == 4) {
+        const uint32_t a = (uint32_t)__builtin_amdgcn_update_dpp(0u, x, 0x124, 0xF, 0xF, false);  // row_ror:4
+        const uint32_t b = (uint32_t)__builtin_amdgcn_update_dpp(0u, x, 0x12C, 0xF, 0xF, false);  // row_ror:12
+        return (lane & 4u) ? a : b;
+    } else if constexpr (M == 8) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0u, x, 0x128, 0xF, 0xF, false);  // row_ror:8
+    } else if constexpr (M == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        return (lane & 16u) ? (uint32_t)r[0] : (uint32_t)r[1];
+    } else {
+        static_assert(M == 32, "xor distance");
+        const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        return (lane & 32u) ? (uint32_t)r[0] : (uint32_t)r[1];
+    }
+}
+
+// Compare-exchange with lane ^ M: this lane keeps the smaller key iff
+// keep_min.
+template <int M>
+__device__ __forceinline__ unsigned long long cx(unsigned long long v, uint32_t lane, bool keep_min) {
+    const uint32_t lo = xor_lane<M>((uint32_t)v, lane);
+    const uint32_t hi = xor_lane<M>((uint32_t)(v >> 32), lane);
+    const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+    return ((o < v) == keep_min) ? o : v;
+}
+
+// One exchange step of the descending sort: blocks of SIZE lanes alternate
+// direction so that each stage leaves bitonic blocks of twice the size.
+template <int SIZE, int M>
+__device__ __forceinline__ unsigned long long sort_step(unsigned long long v, uint32_t lane) {
+    return cx<M>(v, lane, ((lane & (uint32_t)M) == 0u) == ((lane & (uint32_t)SIZE) != 0u));
+}
+
+// Bitonic sort of one key per lane, descending over lanes 0..63.
+__device__ __forceinline__ unsigned long long sort64_desc(unsigned long long v, uint32_t lane) {
+    v = sort_step<2, 1>(v, lane);
+    v = sort_step<4, 2>(v, lane);
+    v = sort_step<4, 1>(v, lane);
+    v = sort_step<8, 4>(v, lane);
+    v = sort_step<8, 2>(v, lane);
+    v = sort_step<8, 1>(v, lane);
+    v = sort_step<16, 8>(v, lane);
+    v = sort_step<16, 4>(v, lane);
+    v = sort_step<16, 2>(v, lane);
+    v = sort_step<16, 1>(v, lane);
+    v = sort_step<32, 16>(v, lane);
+    v = sort_step<32, 8>(v, lane);
+    v = sort_step<32, 4>(v, lane);
+    v = sort_step<32, 2>(v, lane);
+    v = sort_step<32, 1>(v, lane);
+    v = sort_step<64, 32>(v, lane);
+    v = sort_step<64, 16>(v, lane);
+    v = sort_step<64, 8>(v, lane);
+    v = sort_step<64, 4>(v, lane);
+    v = sort_step<64, 2>(v, lane);
+    v = sort_step<64, 1>(v, lane);
+    return v;
+}
+
+template <int M>
+__device__ __forceinline__ float xor_f32(float x, uint32_t lane) {
+    return __uint_as_float(xor_lane<M>(__float_as_uint(x), lane));
+}
+
+// Wave-wide min / max, result in every lane (fminf/fmaxf skip NaN).
+__device__ __forceinline__ float wave_min(float v, uint32_t lane) {
+    v = fminf(v, xor_f32<1>(v, lane));
+    v = fminf(v, xor_f32<2>(v, lane));
+    v = fminf(v, xor_f32<4>(v, lane));
+    v = fminf(v, xor_f32<8>(v, lane));
+    v = fminf(v, xor_f32<16>(v, lane));
+    return fminf(v, xor_f32<32>(v, lane));
+}
+
+__device__ __forceinline__ float wave_max(float v, uint32_t lane) {
+    v = fmaxf(v, xor_f32<1>(v, lane));
+    v = fmaxf(v, xor_f32<2>(v, lane));
+    v = fmaxf(v, xor_f32<4>(v, lane));
+    v = fmaxf(v, xor_f32<8>(v, lane));
+    v = fmaxf(v, xor_f32<16>(v, lane));
+    return fmaxf(v, xor_f32<32>(v, lane));
+}
+
+// Sort a bitonic sequence (one key per lane) ascending.
+__device__ __forceinline__ unsigned long long merge64_asc(unsigned long long v, uint32_t lane) {
+    v = cx<32>(v, lane, (lane & 32u) == 0u);
+    v = cx<16>(v, lane, (lane & 16u) == 0u);
+    v = cx<8>(v, lane, (lane & 8u) == 0u);
+    v = cx<4>(v, lane, (lane & 4u) == 0u);
+    v = cx<2>(v, lane, (lane & 2u) == 0u);
+    v = cx<1>(v, lane, (lane & 1u) == 0u);
+    return v;
+}
+
+// Bitonic sort of 256 keys held four per lane (element e = 64 j + lane in
+// register j), descending over e. Strides below 64 exchange across lanes,
+// strides 64 and 128 between registers of a lane.
+template <int SIZE, int M>
+__device__ __forceinline__ void sort256_step(unsigned long long (&v)[4], uint32_t lane) {
+    if constexpr (M < 64) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t e = (uint32_t)j * 64u + lane;
+            v[j] = cx<M>(v[j], lane, ((e & (uint32_t)M) == 0u) == ((e & (uint32_t)SIZE) != 0u));
+        }
+    } else {
+        constexpr int J = M / 64;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if ((j & J) != 0) continue;
+            const uint32_t e = (uint32_t)j * 64u + lane;
+            const bool asc = (e & (uint32_t)SIZE) != 0u;  // the block's direction (same for both)
+            const unsigned long long a = v[j], b = v[j | J];
+            const unsigned long long mn = a < b ? a : b, mx = a < b ? b : a;
+            v[j] = asc ? mn : mx;
+            v[j | J] = asc ? mx : mn;
+        }
+    }
+}
+
+template <int SIZE>
+__device__ __forceinline__ void sort256_stage(unsigned long long (&v)[4], uint32_t lane) {
+    if constexpr (SIZE >= 256) sort256_step<SIZE, 128>(v, lane);
+    if constexpr (SIZE >= 128) sort256_step<SIZE, 64>(v, lane);
+    if constexpr (SIZE >= 64) sort256_step<SIZE, 32>(v, lane);
+    if constexpr (SIZE >= 32) sort256_step<SIZE, 16>(v, lane);
+    if constexpr (SIZE >= 16) sort256_step<SIZE, 8>(v, lane);
+    if constexpr (SIZE >= 8) sort256_step<SIZE, 4>(v, lane);
+    if constexpr (SIZE >= 4) sort256_step<SIZE, 2>(v, lane);
+    sort256_step<SIZE, 1>(v, lane);
+}
+
+__device__ __forceinline__ void sort256_desc(unsigned long long (&v)[4], uint32_t lane) {
+    sort256_stage<2>(v, lane);
+    sort256_stage<4>(v, lane);
+    sort256_stage<8>(v, lane);
+    sort256_stage<16>(v, lane);
+    sort256_stage<32>(v, lane);
+    sort256_stage<64>(v, lane);
+    sort256_stage<128>(v, lane);
+    sort256_stage<512>(v, lane);  // final merge: every block descending
+}
+
+// Element e of a four-per-lane array (e uniform).
+__device__ __forceinline__ unsigned long long read_elem256(const unsigned long long (&v)[4], uint32_t e) {
+    const uint32_t j = e >> 6;
+    const int l = (int)(e & 63u);
+    const unsigned long long x = j == 0 ? v[0] : (j == 1 ? v[1] : (j == 2 ? v[2] : v[3]));
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+}  // namespace gdn

@@ -247,3 +247,22 @@ def test_empty_batch(bden):
     bden(xyz, offd, out)
     torch.cuda.synchronize()
     assert out.n_kept.cpu().tolist() == [0, 0, 0]
+
+
+def test_large_batch_paths_equal_plain(bden, den):
+    # over 1M points: 16-key radix tiles, 16-item scans, the parallel kNN plan,
+    # the folded frame boxes and the one-wave selects for leaves <= 256 P1
+    # points all run here, and every frame must still equal its plain run
+    # (which, under 1M points, takes the other paths)
+    params = dict(k=16, leaf_cap=256)
+    frames = [synth.lidar_frame(seed=60 + i, n_az=int(n))[0] for i, n in enumerate([1500, 1700, 1300, 1900, 1600,
+                                                                                    1800, 1400, 1750, 1650, 1550,
+                                                                                    1450, 1850])]
+    xyz, offd, off = to_dev(frames)
+    assert xyz.shape[0] > (1 << 20)
+    print(f"[batch] large: {len(frames)} frames, n={xyz.shape[0]}", flush=True)
+    bden.set_params(**params)
+    o = outputs(bden(xyz, offd), xyz.shape[0], len(frames))
+    dumps = batch_dumps(bden, xyz.shape[0], len(frames))
+    assert dumps["status"] == 0
+    check_frames_equal_plain(den, frames, off, o, dumps, params)
