@@ -9,9 +9,11 @@ resident in HBM. Prints ONE JSON line on stdout; progress goes to stderr.
 The line also carries the batched form ("batched vs plain"): 64 uneven LiDAR
 frames (6.2M points) in one pipeline pass, leaf cap and kNN chunk picked by the
 autotuner, replayed from a captured HIP graph, beside the same frames run one
-plain call at a time.
+plain call at a time, and the served form ("served"): a Poisson stream from 16
+sensors at 10 Hz through the continuous-batching server (p50/p99 latency),
+plus a saturating burst of 128 frames through the same server.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-batch]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-batch] [--no-serve]
 """
 import argparse
 import hashlib
@@ -141,6 +143,54 @@ def bench_batch(steps):
     return res
 
 
+def bench_serve(seconds):
+    """The served stream: 16 sensors at 10 Hz (Poisson arrivals) sending frames
+    of 20k-130k points through the continuous-batching server; then the same
+    server saturated with a burst of 128 frames."""
+    import numpy as np
+    import torch
+    from paper_2512_10386_amd import synth
+    from paper_2512_10386_amd.serve import Server, simulate
+
+    frames, _, params = synth.make("lidar_stream_pool")
+    dev = torch.device("cuda", 0)
+    devs = [torch.from_numpy(np.ascontiguousarray(f)).to(dev) for f in frames]
+    srv = Server(0, hbm_budget=24 << 30, max_slots=4, slot_points=1 << 20, slot_frames=16, **params)
+    log(f"[bench] serve: {len(frames)}-frame pool, {srv.n_slots} slots of {srv.bytes_per_slot / 2**20:.0f} MiB")
+    warm = min(2.0, seconds / 5)
+    r = simulate(srv, devs, n_sensors=16, rate_hz=10.0, duration_s=seconds + warm, warmup_s=warm, seed=5, log=log)
+    log(f"[bench] serve: {r['frames']} frames, p50 {r['p50_ms']:.3f} ms, p99 {r['p99_ms']:.3f} ms, "
+        f"{r['mpoints_s']:.2f} Mpts/s (offered)")
+    # saturation: 128 frames submitted at once, time until the last is done
+    order = [i % len(devs) for i in range(128)]
+    outs = [srv.alloc(devs[i].shape[0]) for i in order]
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(3):
+        t0 = time.perf_counter()
+        for i, o in zip(order, outs):
+            srv.submit(devs[i], o)
+        left = len(order)
+        while left:
+            fin, _, _ = srv.poll()
+            left -= len(fin)
+            if time.perf_counter() - t0 > 60:
+                raise RuntimeError("server burst did not finish")
+        el = time.perf_counter() - t0
+        best = el if best is None else min(best, el)
+    pts = sum(devs[i].shape[0] for i in order)
+    srv.close()
+    r.update({"workload": "lidar_stream_16x10hz", "sensors": 16, "rate_hz": 10.0, "k": params["k"],
+              "leaf_cap": params["leaf_cap"], "pool_frames": len(frames),
+              "pool_points_min": min(f.shape[0] for f in frames), "pool_points_max": max(f.shape[0] for f in frames),
+              "burst_frames": len(order), "burst_points": pts, "burst_ms": round(best * 1e3, 3),
+              "burst_mpoints_s": round(pts / best / 1e6, 2)})
+    for key in ("p50_ms", "p99_ms", "max_ms", "mpoints_s"):
+        r[key] = round(r[key], 4)
+    log(f"[bench] serve burst: {len(order)} frames in {best * 1e3:.2f} ms ({r['burst_mpoints_s']} Mpts/s)")
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +200,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched (64-frame) leg")
     ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-stream leg")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -262,6 +314,8 @@ def main():
     }
     if not args.no_batch:
         rec["batched"] = bench_batch(args.batch_steps)
+    if not args.no_serve:
+        rec["served"] = bench_serve(args.serve_seconds)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         rec["cpu_baseline"] = cpu_baseline(xyz, params)

@@ -159,6 +159,41 @@ gdn_status gdn_autotune(gdn_ctx *ctx, gdn_params *p, const int32_t *caps, int nc
                         uint8_t *keep, float *score, uint8_t *stage,
                         uint32_t *kept_idx, int64_t *n_kept, float *ms_out, void *stream);
 
+/*
+ * Continuous-batching request server for streamed frames (serving form of the
+ * batched path). gdn_server_create splits an HBM budget into slots (at most
+ * max_slots), each able to run one batch of up to slot_frames frames and
+ * slot_points points: its input buffer, workspace and outputs are allocated
+ * here (hipMalloc; the only calls that allocate device memory). Each slot has
+ * its own stream, so batches of different slots overlap on the device.
+ *   gdn_server_submit queues one frame (host side only; nothing runs).
+ *     xyz [n][3] and the outputs keep/score/stage(NULL ok)/kept_idx [n] and
+ *     n_kept (int64 scalar) are the caller's device buffers, laid out as for
+ *     gdn_denoise; they must stay valid until the ticket is reported done,
+ *     and xyz must be completely written before submit (the slots' streams
+ *     do not wait for the caller's). A frame larger than slot_points is
+ *     refused with GDN_ECAPACITY, an empty one with GDN_EINVAL.
+ *   gdn_server_poll retires finished batches, then packs waiting frames (in
+ *     arrival order) into every free slot and launches them; it never waits
+ *     for the GPU. It reports up to max_done finished tickets, and optionally
+ *     the queue length and the number of busy slots.
+ * Results of a frame equal those of gdn_denoise on it alone. Not thread-safe;
+ * poll from one thread. After a GDN_EHIP from poll the server is unusable.
+ * Destroy waits for running slots, drops frames still queued and frees the
+ * slots; destroy the server before its context. GDN_ENOMEM from create if
+ * the budget holds no slot (gdn_server_info gives the bytes per slot).
+ */
+typedef struct gdn_server gdn_server;
+gdn_status gdn_server_create(gdn_ctx *ctx, const gdn_params *p, size_t hbm_budget, int max_slots,
+                             int64_t slot_points, int slot_frames, gdn_server **out);
+gdn_status gdn_server_info(gdn_server *s, int *n_slots, size_t *bytes_per_slot);
+gdn_status gdn_server_submit(gdn_server *s, const float *xyz, int64_t n, uint8_t *keep, float *score,
+                             uint8_t *stage, uint32_t *kept_idx, int64_t *n_kept, int64_t *ticket);
+gdn_status gdn_server_poll(gdn_server *s, int64_t *done_tickets, int max_done, int *n_done,
+                           int *n_waiting, int *n_busy);
+void gdn_server_destroy(gdn_server *s);
+const char *gdn_server_last_error(gdn_server *s);
+
 /* Intermediates of the last gdn_denoise / gdn_denoise_batch / graph launch
  * on this context (its workspace must be untouched since). Per-point arrays
  * are in ORIGINAL (batch) point order; leaf arrays cover the whole batch. */

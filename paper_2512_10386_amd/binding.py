@@ -67,6 +67,15 @@ def lib():
         L.gdn_graph_launch.argtypes = [vp, vp]
         L.gdn_graph_destroy.argtypes = [vp]
         L.gdn_graph_destroy.restype = None
+        L.gdn_server_create.argtypes = [vp, C.POINTER(gdn_params), sz, C.c_int, i64, C.c_int, C.POINTER(vp)]
+        L.gdn_server_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(sz)]
+        L.gdn_server_submit.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, C.POINTER(i64)]
+        L.gdn_server_poll.argtypes = [vp, C.POINTER(i64), C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                      C.POINTER(C.c_int)]
+        L.gdn_server_destroy.argtypes = [vp]
+        L.gdn_server_destroy.restype = None
+        L.gdn_server_last_error.argtypes = [vp]
+        L.gdn_server_last_error.restype = C.c_char_p
         L.gdn_autotune.argtypes = [vp, C.POINTER(gdn_params), C.POINTER(C.c_int32), C.c_int,
                                    C.POINTER(C.c_int32), C.c_int, C.c_int, vp, i64, vp, i64, vp, sz,
                                    vp, vp, vp, vp, vp, C.POINTER(C.c_float), vp]
@@ -79,7 +88,8 @@ def lib():
         L.gdn_last_error.restype = C.c_char_p
         for f in ("gdn_default_params", "gdn_create", "gdn_workspace_size", "gdn_denoise",
                   "gdn_debug_dump", "gdn_set_timing", "gdn_timing", "gdn_workspace_size_batch",
-                  "gdn_denoise_batch", "gdn_graph_create", "gdn_graph_launch", "gdn_autotune"):
+                  "gdn_denoise_batch", "gdn_graph_create", "gdn_graph_launch", "gdn_autotune",
+                  "gdn_server_create", "gdn_server_info", "gdn_server_submit", "gdn_server_poll"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -163,6 +173,43 @@ def gdn_autotune(ctx, p, caps, chunks, reps, xyz, n, frame_off, nf, workspace, w
                                    xyz, n, frame_off, nf, workspace, workspace_bytes, keep, score, stage,
                                    kept_idx, n_kept, ms, stream))
     return list(ms)
+
+
+def _check_srv(srv, status):
+    if status != GDN_OK:
+        msg = lib().gdn_server_last_error(srv).decode() if srv else ""
+        raise GdnError(status, msg or lib().gdn_status_string(status).decode())
+
+
+def gdn_server_create(ctx, p, hbm_budget, max_slots, slot_points, slot_frames) -> int:
+    s = C.c_void_p()
+    _check(ctx, lib().gdn_server_create(ctx, C.byref(p), hbm_budget, max_slots, slot_points, slot_frames,
+                                        C.byref(s)))
+    return s.value
+
+
+def gdn_server_info(srv):
+    ns, b = C.c_int(), C.c_size_t()
+    _check_srv(srv, lib().gdn_server_info(srv, C.byref(ns), C.byref(b)))
+    return ns.value, b.value
+
+
+def gdn_server_submit(srv, xyz, n, keep, score, stage, kept_idx, n_kept) -> int:
+    t = C.c_int64()
+    _check_srv(srv, lib().gdn_server_submit(srv, xyz, n, keep, score, stage, kept_idx, n_kept, C.byref(t)))
+    return t.value
+
+
+def gdn_server_poll(srv, max_done: int = 256):
+    """(finished tickets, queue length, busy slots)"""
+    buf = (C.c_int64 * max_done)()
+    nd, nw, nb = C.c_int(), C.c_int(), C.c_int()
+    _check_srv(srv, lib().gdn_server_poll(srv, buf, max_done, C.byref(nd), C.byref(nw), C.byref(nb)))
+    return list(buf[:nd.value]), nw.value, nb.value
+
+
+def gdn_server_destroy(srv) -> None:
+    lib().gdn_server_destroy(srv)
 
 
 def gdn_debug_dump(ctx, what, dst, dst_bytes, stream) -> None:

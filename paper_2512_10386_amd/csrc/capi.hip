@@ -30,6 +30,7 @@ struct gdn_ctx {
 
 namespace gdn {
 size_t dump_bytes(uint32_t n, int k, int what);
+int context_device(const gdn_ctx* ctx) { return ctx ? ctx->device : 0; }
 }
 
 namespace {

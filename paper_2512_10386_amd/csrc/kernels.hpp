@@ -3,6 +3,8 @@
 
 #include "common.hpp"
 
+struct gdn_ctx;
+
 namespace gdn {
 
 // frame.hip: zero-fill, frame table, frame bboxes, Morton keys, radix sort, permute
@@ -36,5 +38,19 @@ void launch_write_zero_count(int64_t* n_kept, uint32_t nf, hipStream_t st);
 
 // dump.hip: intermediates back in original point order
 int launch_dump(const Plan& P, int what, void* dst, size_t dst_bytes, hipStream_t st);
+
+// capi.hip: the device a context is bound to, and a scope that makes a
+// device current (restoring the previous one)
+int context_device(const ::gdn_ctx* ctx);
+struct CurrentDevice {
+    int prev = -1;
+    bool changed = false;
+    explicit CurrentDevice(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) changed = hipSetDevice(dev) == hipSuccess;
+    }
+    ~CurrentDevice() {
+        if (changed) (void)hipSetDevice(prev);
+    }
+};
 
 }  // namespace gdn

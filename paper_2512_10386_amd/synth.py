@@ -194,6 +194,10 @@ CONFIGS = {
     # over LIDAR_BATCH_CAPS, 1024 is the starting value
     "lidar_batch_64": dict(gen="lidar_batch", kwargs=dict(seed=4000, n_frames=64),
                            params=dict(k=32, leaf_cap=1024)),
+    # frame pool of a served stream: 32 LiDAR frames of 20k-130k points that
+    # simulated sensors send round-robin
+    "lidar_stream_pool": dict(gen="lidar_batch", kwargs=dict(seed=5000, n_frames=32, lo=20_000, hi=130_000),
+                              params=dict(k=32, leaf_cap=1024)),
 }
 
 LIDAR_BATCH_CAPS = (256, 512, 1024, 2048)
