@@ -61,13 +61,18 @@ typedef struct {
     double  keep_ratio;     /* lambda: top fraction of P2 kept per leaf, (0, 1] */
     int32_t knn_chunk;      /* initial candidate chunk length of the kNN work split;
                                changes speed only, never results; 0 = default (16384) */
+    double  gamma;          /* exponent of the gravitational kernel, (d^2 + eps)^(-gamma/2):
+                               2 is Eq. 20 (computed as 1/(d^2+eps)); finite, >= 0 */
+    double  log_threshold;  /* NaN: the per-leaf top-lambda rule (Sec. 3); a finite value
+                               keeps instead every P2 point with ln F_i >= log_threshold */
 } gdn_params;
 
 typedef struct gdn_ctx gdn_ctx;
 
 /* Defaults: k=12, rho_percentile=0.2, min_vox_count=4 (the paper's defaults,
  * Sec. 4.3.1); beta=1, alpha=1, sigma=1, eps=1e-12, keep_ratio=0.98,
- * leaf_cap=512, min_leaf_side=0 (not valued in the paper); knn_chunk=0. */
+ * leaf_cap=512, min_leaf_side=0 (not valued in the paper); knn_chunk=0;
+ * gamma=2 (Eq. 20); log_threshold=NaN (top-lambda). */
 gdn_status gdn_default_params(gdn_params *out);
 
 /* Create a context bound to HIP device `device`. */
@@ -193,6 +198,38 @@ gdn_status gdn_server_poll(gdn_server *s, int64_t *done_tickets, int max_done, i
                            int *n_waiting, int *n_busy);
 void gdn_server_destroy(gdn_server *s);
 const char *gdn_server_last_error(gdn_server *s);
+
+/*
+ * Score fit: loss and gradient of a relaxed threshold on the score, for
+ * fitting the weight parameters to labelled frames. It reads the neighbour
+ * sets, densities, medians and P2 of the last gdn_denoise / gdn_denoise_batch
+ * / graph launch on this context (workspace untouched since; those stay
+ * fixed) and recomputes F_i of Eq. 21 at the given alpha (Eq. 17), sigma
+ * (Eq. 18, 19) and kernel exponent gamma ((d^2+eps)^(-gamma/2); Eq. 20 is
+ * gamma = 2), with eps of the last call. With y_i = 1 for a clean point
+ * (label 0) and 0 for noise (label 1), z_i = (ln F_i - tau) / temperature:
+ *   L = mean over the P2 points with 0 < F_i < inf of
+ *       BCE(sigmoid(z_i), y_i) = ln(1 + e^z_i) - y_i z_i.
+ *   xyz       [n][3] float32: the points of that last call
+ *   label     [n] uint8 device: 1 = noise, 0 = clean (batch positions)
+ *   workspace >= gdn_fit_workspace_size(n) bytes, 256-byte aligned
+ *   out       DEVICE double[6]: L, dL/dalpha, dL/dsigma, dL/dgamma,
+ *             dL/dtau, number of terms (FP64; L and gradients 0 if none)
+ * The sums are taken in a fixed order: equal inputs give equal bits.
+ * GDN_EINVAL if nothing was denoised, n differs from the last call, or a
+ * parameter is out of range (alpha, gamma >= 0, sigma, temperature > 0,
+ * all finite); GDN_ENOMEM if the workspace is too small.
+ */
+typedef struct {
+    double alpha;        /* density-weight exponent of Eq. 17 */
+    double sigma;        /* bandwidth scale of Eq. 18 */
+    double gamma;        /* kernel exponent, 2 = Eq. 20 */
+    double tau;          /* threshold on ln F */
+    double temperature;  /* sigmoid temperature T */
+} gdn_fit_params;
+gdn_status gdn_fit_workspace_size(gdn_ctx *ctx, int64_t n, size_t *bytes);
+gdn_status gdn_fit_loss_grad(gdn_ctx *ctx, const gdn_fit_params *fp, const float *xyz, const uint8_t *label,
+                             int64_t n, void *workspace, size_t workspace_bytes, double *out, void *stream);
 
 /* Intermediates of the last gdn_denoise / gdn_denoise_batch / graph launch
  * on this context (its workspace must be untouched since). Per-point arrays

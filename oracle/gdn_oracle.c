@@ -63,6 +63,8 @@ void orc_default_params(orc_params *p)
     p->sigma = 1.0;
     p->eps = 1e-12;
     p->keep_ratio = 0.98;
+    p->gamma = 2.0;
+    p->log_threshold = NAN;
 }
 
 static int params_ok(const orc_params *p)
@@ -77,6 +79,8 @@ static int params_ok(const orc_params *p)
     if (!(p->eps >= 0.0) || !isfinite(p->eps)) return 0;
     if (!(p->keep_ratio > 0.0 && p->keep_ratio <= 1.0)) return 0;
     if (isnan(p->min_leaf_side)) return 0;
+    if (!(p->gamma >= 0.0) || !isfinite(p->gamma)) return 0;
+    if (isinf(p->log_threshold)) return 0;
     return 1;
 }
 
@@ -499,7 +503,8 @@ int orc_denoise(const float *xyz, int64_t n, const orc_params *p, orc_out *o)
 
     /* Dual-weight gravitational score, Eq. 21 (= Eq. 15 with Eq. 17, 19, 20),
      * summed over N_K(i) in (d2, index) order. A zero bandwidth (all k
-     * neighbours coincide with i) gives d = 0 and the Gaussian factor 1. */
+     * neighbours coincide with i) gives d = 0 and the Gaussian factor 1.
+     * The kernel of Eq. 20 is taken to the power gamma/2 (gamma = 2: Eq. 20). */
     double *score = malloc(sizeof(double) * (size_t)n);
     for (int64_t i = 0; i < n; ++i) score[i] = -1.0;
 #ifdef _OPENMP
@@ -520,7 +525,7 @@ int orc_denoise(const float *xyz, int64_t n, const orc_params *p, orc_out *o)
             double d2 = dx * dx + dy * dy + dz * dz;
             double w_den = pow(rho[i] * rho[j] / den, p->alpha / 2.0);
             double w_dis = (d2 == 0.0) ? 1.0 : exp(-d2 / (2.0 * sr * sr));
-            double kern = 1.0 / (d2 + p->eps);
+            double kern = (p->gamma == 2.0) ? 1.0 / (d2 + p->eps) : pow(d2 + p->eps, -p->gamma / 2.0);
             F += w_den * w_dis * kern;
         }
         score[i] = F;
@@ -539,7 +544,16 @@ int orc_denoise(const float *xyz, int64_t n, const orc_params *p, orc_out *o)
                 if (p2[i]) { stage[i] = 2; sv[n2].f = score[i]; sv[n2].idx = i; ++n2; }
             }
             int64_t m = 0;
-            if (n2 > 0) {
+            if (!isnan(p->log_threshold)) {
+                /* threshold mode: ln F_i >= threshold, no ranking */
+                for (int64_t r = 0; r < n2; ++r) {
+                    if (log(sv[r].f) >= p->log_threshold) {
+                        stage[sv[r].idx] = 3;
+                        keep[sv[r].idx] = 1;
+                        ++m;
+                    }
+                }
+            } else if (n2 > 0) {
                 double mf = ceil(p->keep_ratio * (double)n2);
                 m = (int64_t)mf;
                 if (m > n2) m = n2;
@@ -589,5 +603,77 @@ int orc_denoise(const float *xyz, int64_t n, const orc_params *p, orc_out *o)
     free(leaf_h); free(cand_off); free(cand); free(queries); free(qleaf);
     free(nbr_i); free(nbr_d); free(nbr_cnt); free(r2k); free(r64); free(rho);
     free(insufficient); free(p2); free(rho_med); free(score); free(stage); free(keep);
+    return 0;
+}
+
+/* ------------------------------------------------------------- score fit */
+
+/* Score-fit loss and gradient. The score follows Eq. 21 with the kernel
+ * exponent gamma; its derivatives are taken term by term:
+ *   d/dalpha ln t_ij = (1/2) ln(rho_i rho_j / (rho_med^2 + eps))     (Eq. 17)
+ *   d/dsigma ln t_ij = d_ij^2 / (sigma^3 r_K,i^2)                    (Eq. 18, 19)
+ *   d/dgamma ln t_ij = -(1/2) ln(d_ij^2 + eps)                        (Eq. 20)
+ * so dF_i/dtheta = sum_j t_ij d/dtheta ln t_ij, and with p_i = sigmoid(z_i),
+ * dL/dz_i = (p_i - y_i) / |terms|, dz_i/dtheta = (dF_i/dtheta) / (T F_i),
+ * dz_i/dtau = -1/T. Terms with t_ij = 0 (a zero density) add nothing. */
+int orc_fit_loss_grad(const float *xyz, int64_t n, int k, double eps, const orc_out *o,
+                      const uint8_t *label, double alpha, double sigma, double gamma,
+                      double tau, double T, double *out)
+{
+    if (!(T > 0.0) || !(sigma > 0.0)) return -1;
+    double L = 0.0, ga = 0.0, gs = 0.0, gg = 0.0, gt = 0.0, cnt = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!o->p2[i]) continue;
+        double xi = xyz[3 * i], yi = xyz[3 * i + 1], zi = xyz[3 * i + 2];
+        /* r_K,i in FP64: the largest neighbour distance (as for Eq. 13) */
+        double m2 = 0.0;
+        for (int m = 0; m < k; ++m) {
+            uint32_t j = o->nbr_idx[(size_t)i * k + m];
+            double dx = (double)xyz[3 * (size_t)j] - xi;
+            double dy = (double)xyz[3 * (size_t)j + 1] - yi;
+            double dz = (double)xyz[3 * (size_t)j + 2] - zi;
+            double d2 = dx * dx + dy * dy + dz * dz;
+            if (d2 > m2) m2 = d2;
+        }
+        double r2 = m2;
+        double med = o->leaf_rho_med[o->leaf_of[i]];
+        double F = 0.0, dFa = 0.0, dFs = 0.0, dFg = 0.0;
+        for (int m = 0; m < k; ++m) {
+            uint32_t j = o->nbr_idx[(size_t)i * k + m];
+            double dx = (double)xyz[3 * (size_t)j] - xi;
+            double dy = (double)xyz[3 * (size_t)j + 1] - yi;
+            double dz = (double)xyz[3 * (size_t)j + 2] - zi;
+            double d2 = dx * dx + dy * dy + dz * dz;
+            double ratio = o->rho[i] * o->rho[j] / (med * med + eps);
+            double w_den = pow(ratio, alpha / 2.0);
+            double w_dis = (d2 == 0.0) ? 1.0 : exp(-d2 / (2.0 * sigma * sigma * r2));
+            double kern = pow(d2 + eps, -gamma / 2.0);
+            double t = w_den * w_dis * kern;
+            if (t == 0.0) continue;
+            F += t;
+            dFa += t * 0.5 * log(ratio);
+            if (d2 != 0.0) dFs += t * d2 / (sigma * sigma * sigma * r2);
+            dFg += t * (-0.5 * log(d2 + eps));
+        }
+        if (!(F > 0.0) || isinf(F)) continue;
+        double y = label[i] ? 0.0 : 1.0;
+        double z = (log(F) - tau) / T;
+        double p = 1.0 / (1.0 + exp(-z));
+        /* BCE(sigmoid(z), y) = log(1 + e^z) - y z, written without overflow */
+        L += (z > 0.0 ? z + log1p(exp(-z)) : log1p(exp(z))) - y * z;
+        double g = (p - y) / T;
+        ga += g * dFa / F;
+        gs += g * dFs / F;
+        gg += g * dFg / F;
+        gt += -g;
+        cnt += 1.0;
+    }
+    double c = cnt > 0.0 ? cnt : 1.0;
+    out[0] = L / c;
+    out[1] = ga / c;
+    out[2] = gs / c;
+    out[3] = gg / c;
+    out[4] = gt / c;
+    out[5] = cnt;
     return 0;
 }

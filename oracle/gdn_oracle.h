@@ -33,6 +33,10 @@ typedef struct {
     double  sigma;          /* bandwidth scale, Eq. 18 */
     double  eps;            /* epsilon of Eq. 17 and Eq. 20 */
     double  keep_ratio;     /* lambda of the per-leaf top-lambda rule */
+    double  gamma;          /* exponent of the gravitational kernel (d^2+eps)^(-gamma/2);
+                               2 gives Eq. 20 exactly (computed as 1/(d^2+eps)) */
+    double  log_threshold;  /* NaN: per-leaf top-lambda rule; otherwise keep the
+                               P2 points with ln F_i >= log_threshold instead */
 } orc_params;
 
 /* Every array is caller-allocated. Per-point arrays are indexed by ORIGINAL
@@ -78,6 +82,21 @@ void orc_default_params(orc_params *p);
 
 /* Whole pipeline. Returns 0 on success, -1 on invalid parameters. */
 int orc_denoise(const float *xyz, int64_t n, const orc_params *p, orc_out *o);
+
+/*
+ * Score-fit loss and its gradient (FP64), over the intermediates of a prior
+ * orc_denoise on the same points (o must hold nbr_idx, rho, p2, leaf_of and
+ * leaf_rho_med; the neighbour sets, densities, medians and P2 stay fixed).
+ * With F_i the score of Eq. 21 (kernel exponent gamma) at the given alpha,
+ * sigma, gamma, and y_i = 1 for a clean point (label 0), 0 for noise:
+ *   z_i = (ln F_i - tau) / T,  L = mean over i in P2 with 0 < F_i < inf of
+ *   BCE(sigmoid(z_i), y_i).
+ * out[6] = {L, dL/dalpha, dL/dsigma, dL/dgamma, dL/dtau, number of terms}.
+ * Returns -1 for T <= 0 or sigma <= 0.
+ */
+int orc_fit_loss_grad(const float *xyz, int64_t n, int k, double eps, const orc_out *o,
+                      const uint8_t *label, double alpha, double sigma, double gamma,
+                      double tau, double T, double *out);
 
 /* Individual steps exposed for pinning. */
 uint64_t orc_morton_interleave(uint32_t qx, uint32_t qy, uint32_t qz);

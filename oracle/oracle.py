@@ -33,7 +33,8 @@ class Params(C.Structure):
                 ("min_leaf_side", C.c_double), ("beta", C.c_double),
                 ("min_vox_count", C.c_int32), ("rho_percentile", C.c_double),
                 ("alpha", C.c_double), ("sigma", C.c_double),
-                ("eps", C.c_double), ("keep_ratio", C.c_double)]
+                ("eps", C.c_double), ("keep_ratio", C.c_double),
+                ("gamma", C.c_double), ("log_threshold", C.c_double)]
 
 
 _P = C.c_void_p
@@ -68,6 +69,9 @@ def lib():
         _lib.orc_morton_interleave.restype = C.c_uint64
         _lib.orc_percentile_rank.argtypes = [C.c_int64, C.c_double]
         _lib.orc_percentile_rank.restype = C.c_int64
+        _lib.orc_fit_loss_grad.argtypes = [_P, C.c_int64, C.c_int, C.c_double, C.POINTER(Out), _P,
+                                           C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, _P]
+        _lib.orc_fit_loss_grad.restype = C.c_int
     return _lib
 
 
@@ -134,3 +138,26 @@ def denoise(xyz: np.ndarray, **params) -> dict:
     res.update(n_kept=o.n_kept, n_leaves=nl, pairs=int(o.pairs),
                threads=o.threads, params=p)
     return res
+
+
+def fit_loss_grad(xyz: np.ndarray, res: dict, label: np.ndarray, alpha: float, sigma: float, gamma: float,
+                  tau: float, T: float) -> np.ndarray:
+    """Score-fit loss and gradient (orc_fit_loss_grad) over the intermediates
+    ``res`` of ``denoise(xyz, ...)``: [L, dL/dalpha, dL/dsigma, dL/dgamma,
+    dL/dtau, number of terms]."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float32)
+    n = xyz.shape[0]
+    k = int(res["params"]["k"])
+    keep = dict(nbr_idx=np.ascontiguousarray(res["nbr_idx"], np.uint32),
+                rho=np.ascontiguousarray(res["rho"], np.float64),
+                p2=np.ascontiguousarray(res["p2"], np.uint8),
+                leaf_of=np.ascontiguousarray(res["leaf_of"], np.uint32),
+                leaf_rho_med=np.ascontiguousarray(res["leaf_rho_med"], np.float64))
+    o = Out(**{name: arr.ctypes.data for name, arr in keep.items()})
+    lab = np.ascontiguousarray(label, np.uint8)
+    out = np.zeros(6, np.float64)
+    rc = lib().orc_fit_loss_grad(xyz.ctypes.data, n, k, float(res["params"]["eps"]), C.byref(o), lab.ctypes.data,
+                                 alpha, sigma, gamma, tau, T, out.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle rejected the fit parameters")
+    return out

@@ -32,7 +32,13 @@ class gdn_params(C.Structure):
                 ("min_vox_count", C.c_int32), ("rho_percentile", C.c_double),
                 ("alpha", C.c_double), ("sigma", C.c_double),
                 ("eps", C.c_double), ("keep_ratio", C.c_double),
-                ("knn_chunk", C.c_int32)]
+                ("knn_chunk", C.c_int32), ("gamma", C.c_double),
+                ("log_threshold", C.c_double)]
+
+
+class gdn_fit_params(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("sigma", C.c_double), ("gamma", C.c_double),
+                ("tau", C.c_double), ("temperature", C.c_double)]
 
 
 class GdnError(RuntimeError):
@@ -80,6 +86,8 @@ def lib():
                                    C.POINTER(C.c_int32), C.c_int, C.c_int, vp, i64, vp, i64, vp, sz,
                                    vp, vp, vp, vp, vp, C.POINTER(C.c_float), vp]
         L.gdn_debug_dump.argtypes = [vp, C.c_int, vp, sz, vp]
+        L.gdn_fit_workspace_size.argtypes = [vp, i64, C.POINTER(sz)]
+        L.gdn_fit_loss_grad.argtypes = [vp, C.POINTER(gdn_fit_params), vp, vp, i64, vp, sz, vp, vp]
         L.gdn_set_timing.argtypes = [vp, C.c_int]
         L.gdn_timing.argtypes = [vp, i64, C.POINTER(C.c_float), C.POINTER(C.c_float)]
         L.gdn_status_string.argtypes = [C.c_int]
@@ -89,6 +97,7 @@ def lib():
         for f in ("gdn_default_params", "gdn_create", "gdn_workspace_size", "gdn_denoise",
                   "gdn_debug_dump", "gdn_set_timing", "gdn_timing", "gdn_workspace_size_batch",
                   "gdn_denoise_batch", "gdn_graph_create", "gdn_graph_launch", "gdn_autotune",
+                  "gdn_fit_workspace_size", "gdn_fit_loss_grad",
                   "gdn_server_create", "gdn_server_info", "gdn_server_submit", "gdn_server_poll"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -210,6 +219,16 @@ def gdn_server_poll(srv, max_done: int = 256):
 
 def gdn_server_destroy(srv) -> None:
     lib().gdn_server_destroy(srv)
+
+
+def gdn_fit_workspace_size(ctx, n) -> int:
+    b = C.c_size_t()
+    _check(ctx, lib().gdn_fit_workspace_size(ctx, n, C.byref(b)))
+    return b.value
+
+
+def gdn_fit_loss_grad(ctx, fp, xyz, label, n, ws, ws_bytes, out, stream) -> None:
+    _check(ctx, lib().gdn_fit_loss_grad(ctx, C.byref(fp), xyz, label, n, ws, ws_bytes, out, stream))
 
 
 def gdn_debug_dump(ctx, what, dst, dst_bytes, stream) -> None:

@@ -22,6 +22,7 @@ struct gdn_ctx {
     int num_cus = 256;
     std::string err;
     gdn::Plan last{};
+    gdn::Params last_prm{};
     bool has_last = false;
     bool timing = false;
     std::vector<CallEvents> ring;
@@ -143,6 +144,8 @@ bool params_ok(const gdn_params* p, std::string* why) {
     if (!(p->eps >= 0.0) || !std::isfinite(p->eps)) return bad("eps must be finite and >= 0");
     if (!(p->keep_ratio > 0.0 && p->keep_ratio <= 1.0)) return bad("keep_ratio must be in (0, 1]");
     if (p->knn_chunk < 0 || p->knn_chunk > (1 << 28)) return bad("knn_chunk must be in [0, 2^28]");
+    if (!(p->gamma >= 0.0) || !std::isfinite(p->gamma)) return bad("gamma must be finite and >= 0");
+    if (std::isinf(p->log_threshold)) return bad("log_threshold must be finite or NaN");
     return true;
 }
 
@@ -159,6 +162,8 @@ gdn::Params to_params(const gdn_params* p) {
     q.eps = p->eps;
     q.keep_ratio = p->keep_ratio;
     q.knn_chunk = p->knn_chunk;
+    q.gamma = p->gamma;
+    q.log_thr = p->log_threshold;
     return q;
 }
 
@@ -196,6 +201,8 @@ gdn_status gdn_default_params(gdn_params* out) {
     out->eps = 1e-12;
     out->keep_ratio = 0.98;
     out->knn_chunk = 0;
+    out->gamma = 2.0;
+    out->log_threshold = std::nan("");
     return GDN_OK;
 }
 
@@ -341,6 +348,7 @@ static gdn_status run(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int64
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(ctx, GDN_EHIP, hipGetErrorString(e));
     ctx->last = P;
+    ctx->last_prm = prm;
     ctx->has_last = true;
     ctx->err.clear();
     return GDN_OK;
@@ -372,6 +380,7 @@ struct gdn_graph {
     gdn_ctx* ctx = nullptr;
     hipGraphExec_t exec = nullptr;
     gdn::Plan plan{};
+    gdn::Params prm{};
 };
 
 gdn_status gdn_graph_create(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int64_t n,
@@ -414,6 +423,7 @@ gdn_status gdn_graph_create(gdn_ctx* ctx, const gdn_params* p, const float* xyz,
     G->ctx = ctx;
     G->exec = exec;
     G->plan = ctx->last;
+    G->prm = ctx->last_prm;
     ctx->has_last = false;  // nothing has run yet
     *out = G;
     return GDN_OK;
@@ -425,6 +435,7 @@ gdn_status gdn_graph_launch(gdn_graph* g, void* stream) {
     if (hipGraphLaunch(g->exec, (hipStream_t)stream) != hipSuccess)
         return fail(g->ctx, GDN_EHIP, "hipGraphLaunch failed");
     g->ctx->last = g->plan;
+    g->ctx->last_prm = g->prm;
     g->ctx->has_last = true;
     return GDN_OK;
 }
@@ -505,6 +516,37 @@ gdn_status gdn_debug_dump(gdn_ctx* ctx, int what, void* dst, size_t dst_bytes, v
         return fail(ctx, GDN_EINVAL, "unknown dump item or dst too small");
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(ctx, GDN_EHIP, hipGetErrorString(e));
+    return GDN_OK;
+}
+
+gdn_status gdn_fit_workspace_size(gdn_ctx* ctx, int64_t n, size_t* bytes) {
+    if (!bytes) return fail(ctx, GDN_EINVAL, "bytes is NULL");
+    if (n < 0) return fail(ctx, GDN_EINVAL, "n < 0");
+    if (n > MAX_POINTS) return fail(ctx, GDN_ECAPACITY, "n exceeds 2^30-1 points");
+    *bytes = gdn::fit_workspace_bytes((uint32_t)n);
+    return GDN_OK;
+}
+
+gdn_status gdn_fit_loss_grad(gdn_ctx* ctx, const gdn_fit_params* fp, const float* xyz, const uint8_t* label,
+                             int64_t n, void* workspace, size_t workspace_bytes, double* out, void* stream) {
+    if (!ctx) return GDN_EINVAL;
+    if (!fp || !xyz || !label || !workspace || !out) return fail(ctx, GDN_EINVAL, "NULL argument");
+    if (!(fp->alpha >= 0.0) || !std::isfinite(fp->alpha)) return fail(ctx, GDN_EINVAL, "alpha must be finite and >= 0");
+    if (!(fp->sigma > 0.0) || !std::isfinite(fp->sigma)) return fail(ctx, GDN_EINVAL, "sigma must be finite and > 0");
+    if (!(fp->gamma >= 0.0) || !std::isfinite(fp->gamma)) return fail(ctx, GDN_EINVAL, "gamma must be finite and >= 0");
+    if (!std::isfinite(fp->tau)) return fail(ctx, GDN_EINVAL, "tau must be finite");
+    if (!(fp->temperature > 0.0) || !std::isfinite(fp->temperature))
+        return fail(ctx, GDN_EINVAL, "temperature must be finite and > 0");
+    if (!ctx->has_last) return fail(ctx, GDN_EINVAL, "no frame has been denoised on this context");
+    if (n != (int64_t)ctx->last.n) return fail(ctx, GDN_EINVAL, "n differs from the last denoised frame or batch");
+    if (((uintptr_t)workspace & 255u) != 0) return fail(ctx, GDN_EINVAL, "workspace must be 256-byte aligned");
+    if (workspace_bytes < gdn::fit_workspace_bytes((uint32_t)n)) return fail(ctx, GDN_ENOMEM, "workspace too small");
+    DeviceGuard guard(ctx->device);
+    const gdn::FitArgs a{fp->alpha, fp->sigma, fp->gamma, fp->tau, fp->temperature, ctx->last_prm.eps};
+    gdn::launch_fit(ctx->last, xyz, label, a, workspace, out, (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(ctx, GDN_EHIP, hipGetErrorString(e));
+    ctx->err.clear();
     return GDN_OK;
 }
 

@@ -92,6 +92,13 @@ struct Params {
     double eps;
     double keep_ratio;
     int32_t knn_chunk;        // initial kNN candidate chunk length (performance only)
+    double gamma;             // kernel exponent: (d^2 + eps)^(-gamma/2); 2 = Eq. 20
+    double log_thr;           // NaN: top-lambda; else keep P2 points with ln F >= log_thr
+};
+
+// Parameters of the score fit (loss and gradient of a relaxed ln F threshold).
+struct FitArgs {
+    double alpha, sigma, gamma, tau, T, eps;
 };
 
 // Pointers into the caller's workspace for a batch of nf frames, n points in

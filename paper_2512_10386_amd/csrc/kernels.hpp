@@ -36,6 +36,11 @@ void launch_outputs(const Plan& P, uint8_t* keep, float* score, uint8_t* stage,
                     uint32_t* kept_idx, int64_t* n_kept, hipStream_t st);
 void launch_write_zero_count(int64_t* n_kept, uint32_t nf, hipStream_t st);
 
+// fit.hip: score-fit loss and gradient over the last pass's intermediates
+size_t fit_workspace_bytes(uint32_t n);
+void launch_fit(const Plan& P, const float* xyz, const uint8_t* label, const FitArgs& a, void* workspace,
+                double* out, hipStream_t st);
+
 // dump.hip: intermediates back in original point order
 int launch_dump(const Plan& P, int what, void* dst, size_t dst_bytes, hipStream_t st);
 

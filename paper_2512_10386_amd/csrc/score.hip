@@ -2,6 +2,7 @@
 // (Eq. 16), the dual-weight gravitational score (Eq. 15-21), the per-leaf
 // top-lambda rule and the union of the leaves' kept points (Eq. 22).
 #include <climits>
+#include <cmath>
 
 #include "kernels.hpp"
 #include "scan.hpp"
@@ -308,7 +309,7 @@ void launch_leaf_select(const Plan& P, const Params& prm, hipStream_t st) {
 // a fixed pairwise tree (lane r holds term r), not left to right.
 
 __global__ __launch_bounds__(256) void score_kernel(Plan P, const float* __restrict__ xyz, int kk, double sigma,
-                                                    double eps) {
+                                                    double eps, double gamma) {
     const uint32_t np1 = P.ctr->n_p1;
     const uint32_t k = (uint32_t)kk, kp = pow2_at_least(k), qpw = 64u / kp;
     const uint32_t lane = threadIdx.x & 63u, seg = lane / kp, r = lane % kp;
@@ -328,7 +329,7 @@ __global__ __launch_bounds__(256) void score_kernel(Plan P, const float* __restr
                 const double d2 = dx * dx + dy * dy + dz * dz;
                 const double w_den = P.afac_c[qi] * P.gpow_o[j];
                 const double w_dis = (d2 == 0.0) ? 1.0 : exp(-d2 / (2.0 * sr * sr));
-                const double kern = 1.0 / (d2 + eps);
+                const double kern = gamma == 2.0 ? 1.0 / (d2 + eps) : pow(d2 + eps, -gamma / 2.0);
                 term = w_den * w_dis * kern;
             }
         }
@@ -344,7 +345,7 @@ void launch_score(const Plan& P, const Params& prm, const float* xyz, hipStream_
     unsigned blocks = (unsigned)((waves + 3) / 4);
     if (blocks > 8192) blocks = 8192;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(score_kernel, dim3(blocks), dim3(256), 0, st, P, xyz, prm.k, prm.sigma, prm.eps);
+    hipLaunchKernelGGL(score_kernel, dim3(blocks), dim3(256), 0, st, P, xyz, prm.k, prm.sigma, prm.eps, prm.gamma);
 }
 
 // ---------------------------------------------------------------- top-lambda
@@ -523,7 +524,21 @@ __global__ __launch_bounds__(256) void topl_small_kernel(Plan P, double lambda) 
     }
 }
 
+// Threshold mode: a P2 point is kept iff ln F >= thr (no ranking, no leaves).
+__global__ __launch_bounds__(256) void threshold_kernel(Plan P, double thr) {
+    const uint32_t np1 = P.ctr->n_p1;
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < np1; q += gridDim.x * blockDim.x)
+        P.stage_c[q] = P.p2[q] ? (log(P.score_c[q]) >= thr ? 3 : 2) : 1;
+}
+
 void launch_topl(const Plan& P, const Params& prm, hipStream_t st) {
+    if (!std::isnan(prm.log_thr)) {
+        unsigned blocks = (P.n + 255) / 256;
+        if (blocks > 4096) blocks = 4096;
+        if (blocks == 0) blocks = 1;
+        hipLaunchKernelGGL(threshold_kernel, dim3(blocks), dim3(256), 0, st, P, prm.log_thr);
+        return;
+    }
     const bool small = P.n > SMALL_PATH_MIN_N;
     if (small) {
         unsigned wb = (P.n / 128 + 3) / 4;

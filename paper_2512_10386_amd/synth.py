@@ -14,6 +14,9 @@ stand in for them with the same kinds of geometry, sizes and noise mixes:
 * ``lidar_frame``: a spinning 64-beam LiDAR frame over a ground plane, boxes and
   a far wall, with near-sensor snow returns, the stand-in for the CADC snow
   frame and the 50 m / 100 m FMCW frames (about 120k points).
+* ``torus_bumpy``: a torus and a bumpy sphere with Gaussian surface noise at a
+  given fraction of the bounding-box diagonal plus 10% uniform outliers, the
+  stand-in for the Bunny frames at several noise levels (score-fit sets).
 
 Every frame is returned as ``(xyz float32 [N,3], label uint8 [N])`` with
 label 1 marking an injected noise point. Rows are shuffled with a seeded
@@ -28,6 +31,8 @@ __all__ = [
     "lidar_frame",
     "lidar_batch_sizes",
     "uniform_cube",
+    "torus_bumpy",
+    "fit_set",
     "CONFIGS",
 ]
 
@@ -67,6 +72,61 @@ def uniform_cube(seed: int, n: int, side: float = 1.0):
     rng = np.random.default_rng(seed)
     xyz = rng.uniform(0.0, side, (n, 3)).astype(np.float32)
     return xyz, np.zeros(n, np.uint8)
+
+
+def torus_bumpy(seed: int = 30, noise_frac: float = 0.01, n_torus: int = 90_000, n_bumpy: int = 90_000,
+                n_out: int = 20_000):
+    """Torus (R = 1, r = 0.35, axis z, at the origin) + bumpy sphere
+    r(theta, phi) = 0.8 (1 + 0.1 sin(6 theta) cos(6 phi)) centred at (2.6, 0, 0),
+    both sampled close to area-uniform by rejection (torus: weight
+    (R + r cos v) / (R + r); sphere: weight r^2 / r_max^2, the slope of the
+    bumps ignored). Surface points get isotropic Gaussian noise of std
+    ``noise_frac`` x the clean bounding-box diagonal; ``n_out`` outliers
+    (label 1) are uniform in the clean box grown by 10% about its centre.
+    """
+    rng = np.random.default_rng(seed)
+    R, r = 1.0, 0.35
+    tor = np.zeros((0, 3))
+    while tor.shape[0] < n_torus:
+        m = 2 * (n_torus - tor.shape[0]) + 64
+        u = rng.uniform(0.0, 2 * np.pi, m)
+        v = rng.uniform(0.0, 2 * np.pi, m)
+        ok = rng.uniform(0.0, 1.0, m) < (R + r * np.cos(v)) / (R + r)
+        u, v = u[ok], v[ok]
+        pts = np.column_stack([(R + r * np.cos(v)) * np.cos(u), (R + r * np.cos(v)) * np.sin(u), r * np.sin(v)])
+        tor = np.concatenate([tor, pts])
+    tor = tor[:n_torus]
+    bum = np.zeros((0, 3))
+    rmax = 0.8 * 1.1
+    while bum.shape[0] < n_bumpy:
+        m = 2 * (n_bumpy - bum.shape[0]) + 64
+        g = rng.standard_normal((m, 3))
+        d = g / np.linalg.norm(g, axis=1, keepdims=True)
+        th = np.arccos(np.clip(d[:, 2], -1.0, 1.0))
+        ph = np.arctan2(d[:, 1], d[:, 0])
+        rr = 0.8 * (1.0 + 0.1 * np.sin(6 * th) * np.cos(6 * ph))
+        ok = rng.uniform(0.0, 1.0, m) < (rr / rmax) ** 2
+        bum = np.concatenate([bum, d[ok] * rr[ok, None] + np.array([2.6, 0.0, 0.0])])
+    bum = bum[:n_bumpy]
+    surf = np.concatenate([tor, bum])
+    lo, hi = surf.min(0), surf.max(0)
+    diag = float(np.linalg.norm(hi - lo))
+    surf = surf + rng.normal(0.0, noise_frac * diag, surf.shape)
+    c, h = (lo + hi) / 2, (hi - lo) / 2 * 1.1
+    out = rng.uniform(c - h, c + h, (n_out, 3))
+    xyz = np.concatenate([surf, out]).astype(np.float32)
+    label = np.concatenate([np.zeros(surf.shape[0], np.uint8), np.ones(n_out, np.uint8)])
+    return _shuffle(rng, xyz, label)
+
+
+FIT_NOISE = (0.005, 0.01, 0.02)
+
+
+def fit_set(seed: int = 30, n_torus: int = 90_000, n_bumpy: int = 90_000, n_out: int = 20_000):
+    """Score-fit frames: ``torus_bumpy`` at the noise levels FIT_NOISE, scene
+    seeds seed, seed + 1, seed + 2. Returns (list of xyz, list of labels)."""
+    fr = [torus_bumpy(seed + i, f, n_torus, n_bumpy, n_out) for i, f in enumerate(FIT_NOISE)]
+    return [x for x, _ in fr], [lab for _, lab in fr]
 
 
 # ---------------------------------------------------------------------------
@@ -196,6 +256,8 @@ CONFIGS = {
                            params=dict(k=32, leaf_cap=1024)),
     # frame pool of a served stream: 32 LiDAR frames of 20k-130k points that
     # simulated sensors send round-robin
+    # three 200k-point score-fit frames (noise 0.5%, 1%, 2% of the diagonal)
+    "fit_200k": dict(gen="fit_set", kwargs=dict(seed=30), params=dict(k=16, leaf_cap=512)),
     "lidar_stream_pool": dict(gen="lidar_batch", kwargs=dict(seed=5000, n_frames=32, lo=20_000, hi=130_000),
                               params=dict(k=32, leaf_cap=1024)),
 }
@@ -207,6 +269,7 @@ def make(name: str):
     """Return (xyz, label, params) for a named workload recipe (for a batch,
     xyz and label are lists with one array per frame)."""
     c = CONFIGS[name]
-    fn = {"sphere_plane": sphere_plane, "lidar_frame": lidar_frame, "lidar_batch": lidar_batch}[c["gen"]]
+    fn = {"sphere_plane": sphere_plane, "lidar_frame": lidar_frame, "lidar_batch": lidar_batch,
+          "fit_set": fit_set}[c["gen"]]
     xyz, label = fn(**c["kwargs"])
     return xyz, label, dict(c["params"])

@@ -53,8 +53,9 @@ def leaf_thresholds(ref):
     return th
 
 
-def compare(g, ref, exact_rho=False):
-    """Assert GPU results match the oracle to the parity bar; return stats."""
+def compare(g, ref, exact_rho=False, log_threshold=None):
+    """Assert GPU results match the oracle to the parity bar; return stats.
+    With log_threshold (threshold keep mode) the cut is e^threshold in every leaf."""
     n = len(ref["keep"])
     stats = {}
     if n == 0:
@@ -102,7 +103,7 @@ def compare(g, ref, exact_rho=False):
     assert ok32.all(), "score (fp32 output)"
     assert np.all(g["score"][~s2] == -1.0)
     # labels: may differ only within the tolerance band around the leaf threshold
-    th = leaf_thresholds(ref)
+    th = leaf_thresholds(ref) if log_threshold is None else np.full(ref["n_leaves"], np.exp(log_threshold))
     diff = np.nonzero(g["keep"] != ref["keep"])[0]
     for i in diff:
         t = ref["leaf_of"][i]
