@@ -65,6 +65,7 @@ void orc_default_params(orc_params *p)
     p->keep_ratio = 0.98;
     p->gamma = 2.0;
     p->log_threshold = NAN;
+    p->stages = 7;
 }
 
 static int params_ok(const orc_params *p)
@@ -81,6 +82,7 @@ static int params_ok(const orc_params *p)
     if (isnan(p->min_leaf_side)) return 0;
     if (!(p->gamma >= 0.0) || !isfinite(p->gamma)) return 0;
     if (isinf(p->log_threshold)) return 0;
+    if (p->stages < 0 || p->stages > 7) return 0;
     return 1;
 }
 
@@ -365,7 +367,7 @@ int orc_denoise(const float *xyz, int64_t n, const orc_params *p, orc_out *o)
             free(vk);
         }
         for (uint32_t s = b; s < e; ++s)
-            p1[sidx[s]] = occ[sidx[s]] >= (uint32_t)p->min_vox_count;
+            p1[sidx[s]] = !(p->stages & 1) || occ[sidx[s]] >= (uint32_t)p->min_vox_count;
     }
 
     /* Candidate set of each leaf: the P1 points whose level-d cell lies in
@@ -493,7 +495,7 @@ int orc_denoise(const float *xyz, int64_t n, const orc_params *p, orc_out *o)
             rho_med[l] = (n1 % 2) ? dv[(n1 - 1) / 2] : (dv[n1 / 2 - 1] + dv[n1 / 2]) / 2.0;
             for (uint32_t s = L[l].begin; s < L[l].end; ++s) {
                 uint32_t i = sidx[s];
-                if (p1[i] && !insufficient[i] && r2k[i] <= cut) p2[i] = 1;
+                if (p1[i] && !insufficient[i] && (!(p->stages & 2) || r2k[i] <= cut)) p2[i] = 1;
             }
             if (o->leaf_n1) o->leaf_n1[l] = (uint32_t)n1;
         }
@@ -511,7 +513,7 @@ int orc_denoise(const float *xyz, int64_t n, const orc_params *p, orc_out *o)
 #pragma omp parallel for schedule(dynamic, 64)
 #endif
     for (int64_t i = 0; i < n; ++i) {
-        if (!p2[i]) continue;
+        if (!p2[i] || !(p->stages & 4)) continue;
         double med = rho_med[leaf_of[i]];
         double den = med * med + p->eps;
         double xi = xyz[3 * i], yi = xyz[3 * i + 1], zi = xyz[3 * i + 2];
@@ -544,7 +546,14 @@ int orc_denoise(const float *xyz, int64_t n, const orc_params *p, orc_out *o)
                 if (p2[i]) { stage[i] = 2; sv[n2].f = score[i]; sv[n2].idx = i; ++n2; }
             }
             int64_t m = 0;
-            if (!isnan(p->log_threshold)) {
+            if (!(p->stages & 4)) {
+                /* A3 disabled: every P2 point is kept */
+                for (int64_t r = 0; r < n2; ++r) {
+                    stage[sv[r].idx] = 3;
+                    keep[sv[r].idx] = 1;
+                }
+                m = n2;
+            } else if (!isnan(p->log_threshold)) {
                 /* threshold mode: ln F_i >= threshold, no ranking */
                 for (int64_t r = 0; r < n2; ++r) {
                     if (log(sv[r].f) >= p->log_threshold) {
@@ -675,5 +684,73 @@ int orc_fit_loss_grad(const float *xyz, int64_t n, int k, double eps, const orc_
     out[3] = gg / c;
     out[4] = gt / c;
     out[5] = cnt;
+    return 0;
+}
+
+/* ------------------------------------------------------ evaluation (Eq. 29, 30) */
+
+int orc_nearest(const float *a, int64_t na, const float *b, int64_t nb, uint32_t *idx, float *d2)
+{
+    if (nb <= 0) return -1;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+    for (int64_t i = 0; i < na; ++i) {
+        float best = INFINITY;
+        uint32_t bi = 0;
+        for (int64_t j = 0; j < nb; ++j) {
+            float dx = b[3 * j] - a[3 * i];
+            float dy = b[3 * j + 1] - a[3 * i + 1];
+            float dz = b[3 * j + 2] - a[3 * i + 2];
+            float d = (dx * dx + dy * dy) + dz * dz;
+            if (d < best) {
+                best = d;
+                bi = (uint32_t)j;
+            }
+        }
+        idx[i] = bi;
+        d2[i] = best;
+    }
+    return 0;
+}
+
+/* mean over a of the FP64 squared distance to its nearest point of b */
+static double mean_nearest_d2(const float *a, int64_t na, const float *b, int64_t nb)
+{
+    uint32_t *idx = malloc(sizeof(uint32_t) * (size_t)na);
+    float *d2 = malloc(sizeof(float) * (size_t)na);
+    orc_nearest(a, na, b, nb, idx, d2);
+    double s = 0.0;
+    for (int64_t i = 0; i < na; ++i) {
+        uint32_t j = idx[i];
+        double dx = (double)b[3 * (size_t)j] - (double)a[3 * i];
+        double dy = (double)b[3 * (size_t)j + 1] - (double)a[3 * i + 1];
+        double dz = (double)b[3 * (size_t)j + 2] - (double)a[3 * i + 2];
+        s += dx * dx + dy * dy + dz * dz;
+    }
+    free(idx);
+    free(d2);
+    return s / (double)na;
+}
+
+int orc_eval_metrics(const float *clean, int64_t nc, const float *den, int64_t nd, double *out)
+{
+    if (nc <= 0 || nd <= 0) return -1;
+    float lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = clean[a];
+    for (int64_t i = 1; i < nc; ++i)
+        for (int a = 0; a < 3; ++a) {
+            if (clean[3 * i + a] < lo[a]) lo[a] = clean[3 * i + a];
+            if (clean[3 * i + a] > hi[a]) hi[a] = clean[3 * i + a];
+        }
+    double m2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double e = (double)hi[a] - (double)lo[a];
+        m2 += e * e;
+    }
+    out[0] = mean_nearest_d2(clean, nc, den, nd);
+    out[1] = mean_nearest_d2(den, nd, clean, nc);
+    out[2] = out[0] + out[1];
+    out[3] = 10.0 * log10(m2 / out[0]);
     return 0;
 }

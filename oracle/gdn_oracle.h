@@ -37,6 +37,11 @@ typedef struct {
                                2 gives Eq. 20 exactly (computed as 1/(d^2+eps)) */
     double  log_threshold;  /* NaN: per-leaf top-lambda rule; otherwise keep the
                                P2 points with ln F_i >= log_threshold instead */
+    int32_t stages;         /* enabled modules (Table 9): bit 0 A1 voxel filter (Eq. 12),
+                               bit 1 A2 density filter (Eq. 14), bit 2 A3 score and
+                               top-lambda (Eq. 15-21); 7 = the full method.
+                               A1 off: P1 = all points. A2 off: P2 = the P1 points with
+                               k neighbours. A3 off: no score (-1), P2 is kept. */
 } orc_params;
 
 /* Every array is caller-allocated. Per-point arrays are indexed by ORIGINAL
@@ -97,6 +102,26 @@ int orc_denoise(const float *xyz, int64_t n, const orc_params *p, orc_out *o);
 int orc_fit_loss_grad(const float *xyz, int64_t n, int k, double eps, const orc_out *o,
                       const uint8_t *label, double alpha, double sigma, double gamma,
                       double tau, double T, double *out);
+
+/*
+ * Nearest neighbour of every point of a in b (brute force): fp32 squared
+ * distance ((dx*dx + dy*dy) + dz*dz), ties to the smaller index of b.
+ * idx[na], d2[na]. Returns -1 if nb == 0.
+ */
+int orc_nearest(const float *a, int64_t na, const float *b, int64_t nb, uint32_t *idx, float *d2);
+
+/*
+ * Quality of a denoised cloud against the clean one (Eq. 29, 30), with each
+ * clean point matched to its nearest denoised point and vice versa
+ * (orc_nearest), squared distances of the matched pairs in FP64:
+ *   out[0] = MSE = mean over clean of the squared distance to the denoised set
+ *   out[1] = mean over denoised of the squared distance to the clean set
+ *   out[2] = CD = out[0] + out[1]                                   (Eq. 30)
+ *   out[3] = PSNR = 10 log10(M^2 / MSE), M = diagonal of the clean
+ *            cloud's bounding box (from its fp32 min/max)           (Eq. 29)
+ * Returns -1 if either cloud is empty.
+ */
+int orc_eval_metrics(const float *clean, int64_t nc, const float *den, int64_t nd, double *out);
 
 /* Individual steps exposed for pinning. */
 uint64_t orc_morton_interleave(uint32_t qx, uint32_t qy, uint32_t qz);

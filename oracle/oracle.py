@@ -34,7 +34,8 @@ class Params(C.Structure):
                 ("min_vox_count", C.c_int32), ("rho_percentile", C.c_double),
                 ("alpha", C.c_double), ("sigma", C.c_double),
                 ("eps", C.c_double), ("keep_ratio", C.c_double),
-                ("gamma", C.c_double), ("log_threshold", C.c_double)]
+                ("gamma", C.c_double), ("log_threshold", C.c_double),
+                ("stages", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -72,6 +73,10 @@ def lib():
         _lib.orc_fit_loss_grad.argtypes = [_P, C.c_int64, C.c_int, C.c_double, C.POINTER(Out), _P,
                                            C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, _P]
         _lib.orc_fit_loss_grad.restype = C.c_int
+        _lib.orc_nearest.argtypes = [_P, C.c_int64, _P, C.c_int64, _P, _P]
+        _lib.orc_nearest.restype = C.c_int
+        _lib.orc_eval_metrics.argtypes = [_P, C.c_int64, _P, C.c_int64, _P]
+        _lib.orc_eval_metrics.restype = C.c_int
     return _lib
 
 
@@ -160,4 +165,25 @@ def fit_loss_grad(xyz: np.ndarray, res: dict, label: np.ndarray, alpha: float, s
                                  alpha, sigma, gamma, tau, T, out.ctypes.data)
     if rc != 0:
         raise ValueError("oracle rejected the fit parameters")
+    return out
+
+
+def nearest(a: np.ndarray, b: np.ndarray):
+    """Nearest point of b for every point of a: (idx uint32, fp32 d2)."""
+    a = np.ascontiguousarray(a, np.float32)
+    b = np.ascontiguousarray(b, np.float32)
+    idx = np.zeros(max(len(a), 1), np.uint32)
+    d2 = np.zeros(max(len(a), 1), np.float32)
+    if lib().orc_nearest(a.ctypes.data, len(a), b.ctypes.data, len(b), idx.ctypes.data, d2.ctypes.data) != 0:
+        raise ValueError("empty reference set")
+    return idx[:len(a)], d2[:len(a)]
+
+
+def eval_metrics(clean: np.ndarray, den: np.ndarray) -> np.ndarray:
+    """[MSE, mean denoised->clean, CD (Eq. 30), PSNR dB (Eq. 29)]."""
+    clean = np.ascontiguousarray(clean, np.float32)
+    den = np.ascontiguousarray(den, np.float32)
+    out = np.zeros(4, np.float64)
+    if lib().orc_eval_metrics(clean.ctypes.data, len(clean), den.ctypes.data, len(den), out.ctypes.data) != 0:
+        raise ValueError("empty cloud")
     return out
