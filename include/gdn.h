@@ -65,14 +65,23 @@ typedef struct {
                                2 is Eq. 20 (computed as 1/(d^2+eps)); finite, >= 0 */
     double  log_threshold;  /* NaN: the per-leaf top-lambda rule (Sec. 3); a finite value
                                keeps instead every P2 point with ln F_i >= log_threshold */
+    int32_t stages;         /* enabled modules, GDN_STAGE_* bits (the switches of Table 9);
+                               GDN_STAGES_ALL = the method. A1 off: P1 = every point.
+                               A2 off: P2 = the P1 points with k neighbours. A3 off: no
+                               score (-1) and every P2 point is kept. */
 } gdn_params;
+
+#define GDN_STAGE_VOXEL   1  /* A1: voxel occupancy filter, Eq. 12 */
+#define GDN_STAGE_DENSITY 2  /* A2: kNN density percentile filter, Eq. 14 */
+#define GDN_STAGE_SCORE   4  /* A3: weighted gravitational score and top-lambda, Eq. 15-21 */
+#define GDN_STAGES_ALL    7
 
 typedef struct gdn_ctx gdn_ctx;
 
 /* Defaults: k=12, rho_percentile=0.2, min_vox_count=4 (the paper's defaults,
  * Sec. 4.3.1); beta=1, alpha=1, sigma=1, eps=1e-12, keep_ratio=0.98,
  * leaf_cap=512, min_leaf_side=0 (not valued in the paper); knn_chunk=0;
- * gamma=2 (Eq. 20); log_threshold=NaN (top-lambda). */
+ * gamma=2 (Eq. 20); log_threshold=NaN (top-lambda); stages=GDN_STAGES_ALL. */
 gdn_status gdn_default_params(gdn_params *out);
 
 /* Create a context bound to HIP device `device`. */
@@ -230,6 +239,31 @@ typedef struct {
 gdn_status gdn_fit_workspace_size(gdn_ctx *ctx, int64_t n, size_t *bytes);
 gdn_status gdn_fit_loss_grad(gdn_ctx *ctx, const gdn_fit_params *fp, const float *xyz, const uint8_t *label,
                              int64_t n, void *workspace, size_t workspace_bytes, double *out, void *stream);
+
+/*
+ * Evaluation (Sec. 4.1): exact nearest neighbours and the quality metrics of
+ * a denoised cloud.
+ * gdn_nearest: for every point of a [na][3] its nearest point of b [nb][3],
+ *   brute force, fp32 squared distance (dx*dx + dy*dy) + dz*dz, ties to the
+ *   smaller index: idx [na] uint32, d2 [na] float (device arrays). A query
+ *   with a NaN coordinate gets idx 0, d2 +inf.
+ * gdn_eval_metrics: clean [nc][3] against denoised [nd][3]; each point is
+ *   matched to its nearest point of the other cloud, squared distances of
+ *   the matched pairs in FP64; out DEVICE double[4]:
+ *     MSE = mean over clean of the squared distance to the denoised cloud,
+ *     the mean over denoised of the squared distance to the clean cloud,
+ *     CD = the sum of the two (Eq. 30),
+ *     PSNR = 10 log10(M^2 / MSE) dB with M the diagonal of the clean cloud's
+ *     bounding box (Eq. 29); +inf when MSE = 0.
+ * Both need 1 <= na, nb, nc, nd <= 2^30-1 (GDN_EINVAL / GDN_ECAPACITY) and a
+ * 256-byte aligned workspace of the reported size (GDN_ENOMEM).
+ */
+gdn_status gdn_nearest_workspace_size(gdn_ctx *ctx, int64_t na, size_t *bytes);
+gdn_status gdn_nearest(gdn_ctx *ctx, const float *a, int64_t na, const float *b, int64_t nb,
+                       void *workspace, size_t workspace_bytes, uint32_t *idx, float *d2, void *stream);
+gdn_status gdn_eval_workspace_size(gdn_ctx *ctx, int64_t nc, int64_t nd, size_t *bytes);
+gdn_status gdn_eval_metrics(gdn_ctx *ctx, const float *clean, int64_t nc, const float *den, int64_t nd,
+                            void *workspace, size_t workspace_bytes, double *out, void *stream);
 
 /* Intermediates of the last gdn_denoise / gdn_denoise_batch / graph launch
  * on this context (its workspace must be untouched since). Per-point arrays

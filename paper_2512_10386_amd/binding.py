@@ -20,6 +20,7 @@ GDN_DEV_NONFINITE = 1
 GDN_DEV_WAIT_LIMIT = 2
 GDN_DEV_BAD_FRAMES = 4
 GDN_MAX_FRAMES = 4096
+GDN_STAGE_VOXEL, GDN_STAGE_DENSITY, GDN_STAGE_SCORE, GDN_STAGES_ALL = 1, 2, 4, 7
 
 DUMP = dict(STATUS=0, COUNTS=1, KEYS=2, ORDER=3, LEAF_OF=4, LEAF_TABLE=5, OCC=6, P1=7,
             NBR_IDX=8, NBR_D2=9, R2K=10, RHO=11, P2=12, LEAF_RHO_MED=13, SCORE64=14,
@@ -33,7 +34,7 @@ class gdn_params(C.Structure):
                 ("alpha", C.c_double), ("sigma", C.c_double),
                 ("eps", C.c_double), ("keep_ratio", C.c_double),
                 ("knn_chunk", C.c_int32), ("gamma", C.c_double),
-                ("log_threshold", C.c_double)]
+                ("log_threshold", C.c_double), ("stages", C.c_int32)]
 
 
 class gdn_fit_params(C.Structure):
@@ -87,6 +88,10 @@ def lib():
                                    vp, vp, vp, vp, vp, C.POINTER(C.c_float), vp]
         L.gdn_debug_dump.argtypes = [vp, C.c_int, vp, sz, vp]
         L.gdn_fit_workspace_size.argtypes = [vp, i64, C.POINTER(sz)]
+        L.gdn_nearest_workspace_size.argtypes = [vp, i64, C.POINTER(sz)]
+        L.gdn_nearest.argtypes = [vp, vp, i64, vp, i64, vp, sz, vp, vp, vp]
+        L.gdn_eval_workspace_size.argtypes = [vp, i64, i64, C.POINTER(sz)]
+        L.gdn_eval_metrics.argtypes = [vp, vp, i64, vp, i64, vp, sz, vp, vp]
         L.gdn_fit_loss_grad.argtypes = [vp, C.POINTER(gdn_fit_params), vp, vp, i64, vp, sz, vp, vp]
         L.gdn_set_timing.argtypes = [vp, C.c_int]
         L.gdn_timing.argtypes = [vp, i64, C.POINTER(C.c_float), C.POINTER(C.c_float)]
@@ -97,7 +102,8 @@ def lib():
         for f in ("gdn_default_params", "gdn_create", "gdn_workspace_size", "gdn_denoise",
                   "gdn_debug_dump", "gdn_set_timing", "gdn_timing", "gdn_workspace_size_batch",
                   "gdn_denoise_batch", "gdn_graph_create", "gdn_graph_launch", "gdn_autotune",
-                  "gdn_fit_workspace_size", "gdn_fit_loss_grad",
+                  "gdn_fit_workspace_size", "gdn_fit_loss_grad", "gdn_nearest_workspace_size",
+                  "gdn_nearest", "gdn_eval_workspace_size", "gdn_eval_metrics",
                   "gdn_server_create", "gdn_server_info", "gdn_server_submit", "gdn_server_poll"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -229,6 +235,26 @@ def gdn_fit_workspace_size(ctx, n) -> int:
 
 def gdn_fit_loss_grad(ctx, fp, xyz, label, n, ws, ws_bytes, out, stream) -> None:
     _check(ctx, lib().gdn_fit_loss_grad(ctx, C.byref(fp), xyz, label, n, ws, ws_bytes, out, stream))
+
+
+def gdn_nearest_workspace_size(ctx, na) -> int:
+    b = C.c_size_t()
+    _check(ctx, lib().gdn_nearest_workspace_size(ctx, na, C.byref(b)))
+    return b.value
+
+
+def gdn_nearest(ctx, a, na, b, nb, ws, ws_bytes, idx, d2, stream) -> None:
+    _check(ctx, lib().gdn_nearest(ctx, a, na, b, nb, ws, ws_bytes, idx, d2, stream))
+
+
+def gdn_eval_workspace_size(ctx, nc, nd) -> int:
+    b = C.c_size_t()
+    _check(ctx, lib().gdn_eval_workspace_size(ctx, nc, nd, C.byref(b)))
+    return b.value
+
+
+def gdn_eval_metrics(ctx, clean, nc, den, nd, ws, ws_bytes, out, stream) -> None:
+    _check(ctx, lib().gdn_eval_metrics(ctx, clean, nc, den, nd, ws, ws_bytes, out, stream))
 
 
 def gdn_debug_dump(ctx, what, dst, dst_bytes, stream) -> None:

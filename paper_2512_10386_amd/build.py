@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgdn.so")
 OBJDIR = os.path.join(ROOT, "_build")
-SOURCES = ["frame.hip", "octree.hip", "knn.hip", "score.hip", "dump.hip", "capi.hip", "server.hip", "fit.hip"]
+SOURCES = ["frame.hip", "octree.hip", "knn.hip", "score.hip", "dump.hip", "capi.hip", "server.hip", "fit.hip", "eval.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # No FMA contraction anywhere: the fp32 squared distances that decide the

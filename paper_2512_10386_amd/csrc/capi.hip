@@ -146,6 +146,7 @@ bool params_ok(const gdn_params* p, std::string* why) {
     if (p->knn_chunk < 0 || p->knn_chunk > (1 << 28)) return bad("knn_chunk must be in [0, 2^28]");
     if (!(p->gamma >= 0.0) || !std::isfinite(p->gamma)) return bad("gamma must be finite and >= 0");
     if (std::isinf(p->log_threshold)) return bad("log_threshold must be finite or NaN");
+    if (p->stages < 0 || p->stages > GDN_STAGES_ALL) return bad("stages must be a subset of GDN_STAGES_ALL");
     return true;
 }
 
@@ -164,6 +165,12 @@ gdn::Params to_params(const gdn_params* p) {
     q.knn_chunk = p->knn_chunk;
     q.gamma = p->gamma;
     q.log_thr = p->log_threshold;
+    q.stages = p->stages;
+    // A1 off: every voxel holds at least its own point, so n_v = 1 passes all.
+    if (!(p->stages & GDN_STAGE_VOXEL)) q.min_vox_count = 1;
+    // A2 off: with q = 0 the percentile rank is 1, the cut is the largest r^2,
+    // and every point with k neighbours passes.
+    if (!(p->stages & GDN_STAGE_DENSITY)) q.rho_percentile = 0.0;
     return q;
 }
 
@@ -203,6 +210,7 @@ gdn_status gdn_default_params(gdn_params* out) {
     out->knn_chunk = 0;
     out->gamma = 2.0;
     out->log_threshold = std::nan("");
+    out->stages = GDN_STAGES_ALL;
     return GDN_OK;
 }
 
@@ -340,8 +348,12 @@ static gdn_status run(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int64
     gdn::launch_knn_merge(P, prm.k, ctx->num_cus, st);
     gdn::launch_density(P, prm, xyz, st);
     gdn::launch_leaf_select(P, prm, st);
-    gdn::launch_score(P, prm, xyz, st);
-    gdn::launch_topl(P, prm, st);
+    if (prm.stages & GDN_STAGE_SCORE) {
+        gdn::launch_score(P, prm, xyz, st);
+        gdn::launch_topl(P, prm, st);
+    } else {
+        gdn::launch_keep_p2(P, st);
+    }
     gdn::launch_outputs(P, keep, score, stage, kept_idx, n_kept, st);
     if (ce) (void)hipEventRecord(ce->ev[3], st);
 
@@ -546,6 +558,65 @@ gdn_status gdn_fit_loss_grad(gdn_ctx* ctx, const gdn_fit_params* fp, const float
     gdn::launch_fit(ctx->last, xyz, label, a, workspace, out, (hipStream_t)stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(ctx, GDN_EHIP, hipGetErrorString(e));
+    ctx->err.clear();
+    return GDN_OK;
+}
+
+static gdn_status cloud_size(gdn_ctx* ctx, int64_t n, const char* what) {
+    if (n < 1) return fail(ctx, GDN_EINVAL, std::string(what) + " is empty");
+    if (n > MAX_POINTS) return fail(ctx, GDN_ECAPACITY, std::string(what) + " exceeds 2^30-1 points");
+    return GDN_OK;
+}
+
+gdn_status gdn_nearest_workspace_size(gdn_ctx* ctx, int64_t na, size_t* bytes) {
+    if (!bytes) return fail(ctx, GDN_EINVAL, "bytes is NULL");
+    const gdn_status e = cloud_size(ctx, na, "the query cloud");
+    if (e != GDN_OK) return e;
+    *bytes = gdn::nearest_workspace_bytes((uint32_t)na);
+    return GDN_OK;
+}
+
+gdn_status gdn_nearest(gdn_ctx* ctx, const float* a, int64_t na, const float* b, int64_t nb, void* workspace,
+                       size_t workspace_bytes, uint32_t* idx, float* d2, void* stream) {
+    if (!ctx) return GDN_EINVAL;
+    gdn_status e = cloud_size(ctx, na, "the query cloud");
+    if (e == GDN_OK) e = cloud_size(ctx, nb, "the reference cloud");
+    if (e != GDN_OK) return e;
+    if (!a || !b || !workspace || !idx || !d2) return fail(ctx, GDN_EINVAL, "NULL argument");
+    if (((uintptr_t)workspace & 255u) != 0) return fail(ctx, GDN_EINVAL, "workspace must be 256-byte aligned");
+    if (workspace_bytes < gdn::nearest_workspace_bytes((uint32_t)na))
+        return fail(ctx, GDN_ENOMEM, "workspace too small");
+    DeviceGuard guard(ctx->device);
+    gdn::launch_nearest(a, (uint32_t)na, b, (uint32_t)nb, workspace, idx, d2, (hipStream_t)stream);
+    hipError_t he = hipGetLastError();
+    if (he != hipSuccess) return fail(ctx, GDN_EHIP, hipGetErrorString(he));
+    ctx->err.clear();
+    return GDN_OK;
+}
+
+gdn_status gdn_eval_workspace_size(gdn_ctx* ctx, int64_t nc, int64_t nd, size_t* bytes) {
+    if (!bytes) return fail(ctx, GDN_EINVAL, "bytes is NULL");
+    gdn_status e = cloud_size(ctx, nc, "the clean cloud");
+    if (e == GDN_OK) e = cloud_size(ctx, nd, "the denoised cloud");
+    if (e != GDN_OK) return e;
+    *bytes = gdn::eval_workspace_bytes((uint32_t)nc, (uint32_t)nd);
+    return GDN_OK;
+}
+
+gdn_status gdn_eval_metrics(gdn_ctx* ctx, const float* clean, int64_t nc, const float* den, int64_t nd,
+                            void* workspace, size_t workspace_bytes, double* out, void* stream) {
+    if (!ctx) return GDN_EINVAL;
+    gdn_status e = cloud_size(ctx, nc, "the clean cloud");
+    if (e == GDN_OK) e = cloud_size(ctx, nd, "the denoised cloud");
+    if (e != GDN_OK) return e;
+    if (!clean || !den || !workspace || !out) return fail(ctx, GDN_EINVAL, "NULL argument");
+    if (((uintptr_t)workspace & 255u) != 0) return fail(ctx, GDN_EINVAL, "workspace must be 256-byte aligned");
+    if (workspace_bytes < gdn::eval_workspace_bytes((uint32_t)nc, (uint32_t)nd))
+        return fail(ctx, GDN_ENOMEM, "workspace too small");
+    DeviceGuard guard(ctx->device);
+    gdn::launch_eval(clean, (uint32_t)nc, den, (uint32_t)nd, workspace, out, (hipStream_t)stream);
+    hipError_t he = hipGetLastError();
+    if (he != hipSuccess) return fail(ctx, GDN_EHIP, hipGetErrorString(he));
     ctx->err.clear();
     return GDN_OK;
 }

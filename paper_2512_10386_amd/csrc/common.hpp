@@ -94,6 +94,7 @@ struct Params {
     int32_t knn_chunk;        // initial kNN candidate chunk length (performance only)
     double gamma;             // kernel exponent: (d^2 + eps)^(-gamma/2); 2 = Eq. 20
     double log_thr;           // NaN: top-lambda; else keep P2 points with ln F >= log_thr
+    int32_t stages;           // enabled modules: 1 voxel filter, 2 density filter, 4 score
 };
 
 // Parameters of the score fit (loss and gradient of a relaxed ln F threshold).

@@ -32,6 +32,7 @@ void launch_density(const Plan& P, const Params& prm, const float* xyz, hipStrea
 void launch_leaf_select(const Plan& P, const Params& prm, hipStream_t st);
 void launch_score(const Plan& P, const Params& prm, const float* xyz, hipStream_t st);
 void launch_topl(const Plan& P, const Params& prm, hipStream_t st);
+void launch_keep_p2(const Plan& P, hipStream_t st);
 void launch_outputs(const Plan& P, uint8_t* keep, float* score, uint8_t* stage,
                     uint32_t* kept_idx, int64_t* n_kept, hipStream_t st);
 void launch_write_zero_count(int64_t* n_kept, uint32_t nf, hipStream_t st);
@@ -40,6 +41,14 @@ void launch_write_zero_count(int64_t* n_kept, uint32_t nf, hipStream_t st);
 size_t fit_workspace_bytes(uint32_t n);
 void launch_fit(const Plan& P, const float* xyz, const uint8_t* label, const FitArgs& a, void* workspace,
                 double* out, hipStream_t st);
+
+// eval.hip: exact nearest neighbours between clouds, PSNR / Chamfer metrics
+size_t nearest_workspace_bytes(uint32_t na);
+void launch_nearest(const float* a, uint32_t na, const float* b, uint32_t nb, void* ws, uint32_t* idx, float* d2,
+                    hipStream_t st);
+size_t eval_workspace_bytes(uint32_t nc, uint32_t nd);
+void launch_eval(const float* clean, uint32_t nc, const float* den, uint32_t nd, void* ws, double* out,
+                 hipStream_t st);
 
 // dump.hip: intermediates back in original point order
 int launch_dump(const Plan& P, int what, void* dst, size_t dst_bytes, hipStream_t st);

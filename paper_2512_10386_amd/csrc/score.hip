@@ -531,6 +531,22 @@ __global__ __launch_bounds__(256) void threshold_kernel(Plan P, double thr) {
         P.stage_c[q] = P.p2[q] ? (log(P.score_c[q]) >= thr ? 3 : 2) : 1;
 }
 
+// Score module switched off: every P2 point is kept, none is scored.
+__global__ __launch_bounds__(256) void keep_p2_kernel(Plan P) {
+    const uint32_t np1 = P.ctr->n_p1;
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < np1; q += gridDim.x * blockDim.x) {
+        P.stage_c[q] = P.p2[q] ? 3 : 1;
+        P.score_c[q] = -1.0;
+    }
+}
+
+void launch_keep_p2(const Plan& P, hipStream_t st) {
+    unsigned blocks = (P.n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(keep_p2_kernel, dim3(blocks), dim3(256), 0, st, P);
+}
+
 void launch_topl(const Plan& P, const Params& prm, hipStream_t st) {
     if (!std::isnan(prm.log_thr)) {
         unsigned blocks = (P.n + 255) / 256;
