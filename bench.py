@@ -18,6 +18,7 @@ plus a saturating burst of 128 frames through the same server.
 import argparse
 import hashlib
 import json
+import math
 import os
 import statistics
 import sys
@@ -191,6 +192,70 @@ def bench_serve(seconds):
     return r
 
 
+def bench_ablation(reps):
+    """Module switches of Tables 8/9 on the 20k scanned-object stand-in:
+    F1, PSNR, CD and GPU ms per frame for each combination."""
+    from paper_2512_10386_amd import synth
+    from paper_2512_10386_amd.evaluate import ablation
+    xyz, label, params = synth.make("sphere_plane_20k")
+    rows = ablation(xyz, label, params, reps=reps)
+    for r in rows:
+        log(f"[bench] ablation {r['name']:>20}: F1 {r['f1']:.4f} PSNR {r['psnr_db']:.2f} dB "
+            f"CD {r['cd']:.3e} {r['ms']:.3f} ms")
+    def num(v):  # JSON has no inf/NaN: a PSNR of +inf (nothing clean lost) is reported as null
+        return (round(v, 6) if math.isfinite(v) else None) if isinstance(v, float) else v
+    return {"workload": "sphere_plane_20k", "points": int(xyz.shape[0]), "k": params["k"],
+            "rows": [{k: num(v) for k, v in r.items()} for r in rows]}
+
+
+def bench_fit(steps):
+    """Score fit on the three 200k-point frames (one batch): time of one
+    loss + gradient evaluation, and a short Adam run from the defaults with
+    F1 of the fitted threshold rule against the plain top-lambda rule."""
+    import numpy as np
+    import torch
+    from paper_2512_10386_amd import synth
+    from paper_2512_10386_amd.binding import BatchDenoiser
+    from paper_2512_10386_amd.fit import ScoreFit, f1_scores, fit_params
+    xs, ls, params = synth.make("fit_200k")
+    off = np.zeros(len(xs) + 1, np.int64)
+    off[1:] = np.cumsum([len(x) for x in xs])
+    dev = torch.device("cuda", 0)
+    xyz = torch.from_numpy(np.concatenate(xs)).to(dev)
+    lab_np = np.concatenate(ls)
+    lab = torch.from_numpy(lab_np).to(dev)
+    offd = torch.from_numpy(off).to(dev)
+    sf = ScoreFit(xyz, lab, frame_off=offd, temperature=0.5, **params)
+    torch.cuda.synchronize()
+    score = sf.res.score.cpu().numpy()
+    p2 = score >= 0
+    tau0 = float(np.median(np.log(score[p2])))
+    for _ in range(3):
+        sf.loss_grad(1.0, 1.0, 2.0, tau0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        sf.loss_grad(1.0, 1.0, 2.0, tau0)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 20
+    theta, losses = fit_params(sf, [1.0, 1.0, 2.0, tau0], steps=steps, lr=0.05)
+    plain_keep = sf.res.keep.cpu().numpy()
+    sf.close()
+    bd = BatchDenoiser(0, **dict(params, alpha=theta[0], sigma=theta[1], gamma=theta[2], log_threshold=theta[3]))
+    fitted_keep = bd(xyz, offd).keep.cpu().numpy()
+    bd.close()
+    f_plain = f1_scores(plain_keep, lab_np)[2]
+    f_fit = f1_scores(fitted_keep, lab_np)[2]
+    log(f"[bench] fit: loss+grad {ms:.3f} ms over {int(off[-1])} points; loss {losses[0]:.4f} -> {losses[-1]:.4f}; "
+        f"F1 plain {f_plain:.4f} fitted {f_fit:.4f}")
+    return {"workload": "fit_200k", "points": int(off[-1]), "frames": len(xs), "k": params["k"],
+            "ms_loss_grad": round(ms, 4), "adam_steps": steps, "loss_first": round(losses[0], 6),
+            "loss_last": round(losses[-1], 6), "theta_alpha_sigma_gamma_tau": [round(v, 5) for v in theta],
+            "f1_plain_top_lambda": round(f_plain, 5), "f1_fitted_threshold": round(f_fit, 5)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +267,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream leg")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--no-extras", action="store_true", help="skip the ablation and fit legs")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -316,11 +382,14 @@ def main():
         rec["batched"] = bench_batch(args.batch_steps)
     if not args.no_serve:
         rec["served"] = bench_serve(args.serve_seconds)
+    if not args.no_extras:
+        rec["ablation"] = bench_ablation(10)
+        rec["fit"] = bench_fit(60)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         rec["cpu_baseline"] = cpu_baseline(xyz, params)
         log(f"[bench] cpu baseline {rec['cpu_baseline']}")
-    print(json.dumps(rec), flush=True)
+    print(json.dumps(rec, allow_nan=False), flush=True)
 
 
 if __name__ == "__main__":
