@@ -2,7 +2,7 @@
 // r_K,i on the voxel-filtered set P1).
 //
 // Work item = (leaf, up to 16 queries, candidate chunk), one wave each.
-// Lane-per-candidate: each lane holds 4 candidates of a 256-candidate block
+// Lane-per-candidate: each lane holds 8 candidates of a 512-candidate block
 // (coalesced loads, the next block prefetched), reused for the item's 16
 // queries, whose coordinates are wave-uniform (scalar loads). Squared
 // distances are fp32 (dx*dx + dy*dy) + dz*dz without contraction, so the
@@ -10,13 +10,17 @@
 //
 // Each query keeps, in LDS, its k best (d2, original index) keys (d2 bits <<
 // 32 | index), sorted, one per lane when loaded, and a pending buffer of up
-// to 64 keys. A candidate block is tested against the query's current k-th
+// to 64 candidates (their P1 positions, 4 bytes each: the keys are rebuilt
+// when the buffer is merged, which halves the LDS a wave needs). A candidate block is tested against the query's current k-th
 // distance with one compare per lane; the candidates that pass are appended
 // to the pending buffer (ballot + lane rank). A full buffer, and the buffer
 // at the end of the chunk, is merged into the list: the 64 pending keys are
 // sorted descending by a wave-wide bitonic network, the elementwise minimum
 // with the ascending list holds the 64 smallest keys of both as a bitonic
 // sequence, and six more exchange steps sort it. The list keeps the first k.
+// When k <= 32, buffers holding at most 32 keys at the end of an item are
+// merged on 32-lane halves, two queries at once (15 + 5 exchange steps for
+// both instead of 21 + 6 for one).
 //
 // Bound: knn_bound_kernel gives each query tau >= its k-th squared distance
 // (from k of its own candidates), so its list starts as k placeholder keys
@@ -38,9 +42,11 @@ namespace gdn {
 constexpr uint32_t NONE32 = 0xFFFFFFFFu;
 constexpr unsigned long long KEY_EMPTY = (unsigned long long)LLONG_MAX;
 constexpr int QPW = KNN_TQ;  // queries per wave item
-constexpr int CPL = 4;       // candidates per lane per block
+constexpr int CPL = 8;       // candidates per lane per block
 constexpr int CBLK = 64 * CPL;
 constexpr int PEND = 64;     // pending keys per query
+constexpr int PEND_HALF = 32;  // pending keys a half-wave merge takes (k <= 32)
+constexpr uint32_t KNN_POS_MIN_N = 1u << 20;  // above: pending buffers of positions
 
 __device__ __forceinline__ float dist2(const float4 q, const float4 c) {
     const float dx = c.x - q.x, dy = c.y - q.y, dz = c.z - q.z;
@@ -183,12 +189,48 @@ __device__ __forceinline__ float bound_of(uint32_t hi) {
     return hi == 0x7FFFFFFFu ? INFINITY : __uint_as_float(hi);
 }
 
-// Merge query j's pending keys into its list, dropping the query's own key
-// (the hot loop does not test for it); returns the new distance bound.
-__device__ __forceinline__ float flush(unsigned long long* __restrict__ lst, unsigned long long* __restrict__ pend,
-                                       uint32_t cnt, uint32_t lane, uint32_t k, unsigned long long selfkey) {
+// Coordinates of query j of a tile (lane j holds them).
+__device__ __forceinline__ float4 query_of(float4 qv, uint32_t j) {
+    return make_float4(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(qv.x), (int)j)),
+                       __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qv.y), (int)j)),
+                       __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qv.z), (int)j)), 0.f);
+}
+
+// Pending buffers hold either the keys themselves (POS = false) or the
+// candidates' P1 positions (POS = true, half the LDS: more waves per CU, one
+// gather per merge). A position's key is rebuilt with the same fp32
+// expression as in the hot loop, so it is bit-identical to the one that
+// passed the test.
+template <bool POS>
+struct Pending {
+    using T = unsigned long long;
+};
+template <>
+struct Pending<true> {
+    using T = uint32_t;
+};
+
+template <bool POS>
+__device__ __forceinline__ unsigned long long pending_key(const float4* __restrict__ cand4,
+                                                          const typename Pending<POS>::T* __restrict__ pend,
+                                                          uint32_t e, float4 q) {
+    if constexpr (POS) {
+        const float4 c = cand4[pend[e]];
+        return make_key(dist2(q, c), __float_as_uint(c.w));
+    } else {
+        return pend[e];
+    }
+}
+
+// Merge query j's pending candidates into its list, dropping the query's own
+// key (the hot loop does not test for it); returns the new distance bound.
+template <bool POS>
+__device__ __forceinline__ float flush(unsigned long long* __restrict__ lst,
+                                       const typename Pending<POS>::T* __restrict__ pend, uint32_t cnt,
+                                       uint32_t lane, uint32_t k, unsigned long long selfkey,
+                                       const float4* __restrict__ cand4, float4 q) {
     wave_lds_sync();
-    unsigned long long v = lane < cnt ? pend[lane] : KEY_EMPTY;
+    unsigned long long v = lane < cnt ? pending_key<POS>(cand4, pend, lane, q) : KEY_EMPTY;
     if (v == selfkey) v = KEY_EMPTY;
     const unsigned long long L = lane < k ? lst[lane] : KEY_EMPTY;
     v = sort64_desc(v, lane);
@@ -198,14 +240,48 @@ __device__ __forceinline__ float flush(unsigned long long* __restrict__ lst, uns
     return bound_of((uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)k - 1));
 }
 
+// k <= 32: the lists of two queries, one per 32-lane half (`two` = false:
+// only the lower half's query). Each half merges at most 32 pending keys.
+// Returns the new bounds of both through b0 / b1.
+template <bool POS>
+__device__ __forceinline__ void flush_half(unsigned long long* __restrict__ lst0,
+                                           const typename Pending<POS>::T* __restrict__ pend0,
+                                           uint32_t cnt0, unsigned long long self0, float4 q0,
+                                           unsigned long long* __restrict__ lst1,
+                                           const typename Pending<POS>::T* __restrict__ pend1,
+                                           uint32_t cnt1, unsigned long long self1, float4 q1, bool two,
+                                           uint32_t lane, uint32_t k, const float4* __restrict__ cand4, float* b0,
+                                           float* b1) {
+    wave_lds_sync();
+    const bool up = lane >= 32u;
+    const uint32_t h = lane & 31u;
+    const bool act = !up || two;
+    unsigned long long* const lst = up ? lst1 : lst0;
+    const typename Pending<POS>::T* const pend = up ? pend1 : pend0;
+    const uint32_t cnt = up ? cnt1 : cnt0;
+    unsigned long long v = act && h < cnt ? pending_key<POS>(cand4, pend, h, up ? q1 : q0) : KEY_EMPTY;
+    if (v == (up ? self1 : self0)) v = KEY_EMPTY;
+    const unsigned long long L = act && h < k ? lst[h] : KEY_EMPTY;
+    v = sort32x2_desc(v, lane);
+    v = merge32x2_asc(L < v ? L : v, lane);
+    if (act && h < k) lst[h] = v;
+    wave_lds_sync();
+    const uint32_t hi = (uint32_t)(v >> 32);
+    *b0 = bound_of((uint32_t)__builtin_amdgcn_readlane((int)hi, (int)k - 1));
+    *b1 = bound_of((uint32_t)__builtin_amdgcn_readlane((int)hi, 32 + (int)k - 1));
+}
+
 // One wave per block. Dynamic LDS: per query, the list (k keys) and the
-// pending buffer (PEND keys).
+// pending buffer (PEND keys or candidate positions).
+template <bool POS>
 __global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restrict__ cand4, int kk) {
+    using PT = typename Pending<POS>::T;
     extern __shared__ unsigned long long s_dyn[];
     const uint32_t lane = threadIdx.x;
     const uint32_t k = (uint32_t)kk;
+    const bool half = k <= 32u;
     unsigned long long* const s_list = s_dyn;                    // [QPW][k]
-    unsigned long long* const s_pend = s_dyn + (size_t)QPW * k;  // [QPW][PEND]
+    PT* const s_pend = (PT*)(s_dyn + (size_t)QPW * k);  // [QPW][PEND]
     const uint32_t n_items = P.ctr->n_items;
     for (;;) {
         uint32_t got = 0;
@@ -255,6 +331,7 @@ __global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restric
         const uint32_t c_lo = w.chunk * cc;
         const uint32_t c_hi = min(ncand, c_lo + cc);
         float4 cn[CPL];
+        uint32_t cni[CPL];  // their P1 indices
         // candidates [pos, pos + CBLK) of the concatenated order into cn
         auto load_block = [&](uint32_t pos) {
             const uint32_t last = min(c_hi, pos + (uint32_t)CBLK) - 1u;
@@ -269,10 +346,12 @@ __global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restric
                         off = (uint32_t)__builtin_amdgcn_readlane((int)coff, (int)r);
                 if (Lg < c_hi) {
                     cn[g] = cand4[off + Lg];
+                    cni[g] = off + Lg;
                 } else {
                     // NaN coordinates: d2 <= bound never holds
                     const float nan = __uint_as_float(0x7FC00000u);
                     cn[g] = make_float4(nan, nan, nan, __uint_as_float(NONE32));
+                    cni[g] = NONE32;
                 }
             }
         };
@@ -302,25 +381,29 @@ __global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restric
         if (nblk > 0) load_block(c_lo + (uint32_t)b_start * CBLK);
         for (int b = nblk > 0 ? b_start : -1; b >= 0;) {
             float4 c[CPL];
+            uint32_t ci[CPL];
 #pragma unroll
-            for (int g = 0; g < CPL; ++g) c[g] = cn[g];
+            for (int g = 0; g < CPL; ++g) {
+                c[g] = cn[g];
+                ci[g] = cni[g];
+            }
             const int b_next = next_block();
             if (b_next >= 0) load_block(c_lo + (uint32_t)b_next * CBLK);
             b = b_next;
             // append query j's passing candidates (masks m) to its pending
             // buffer, merging the buffer into the list when it would overflow
-            auto append = [&](uint32_t j, float wj, unsigned long long (&m)[CPL], const float (&d)[CPL]) {
+            auto append = [&](uint32_t j, float wj, unsigned long long (&m)[CPL], const float (&d)[CPL], float4 q) {
                 uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)pcnt, (int)j);
                 const unsigned long long selfkey =
                     (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j);
-                unsigned long long* const pend = s_pend + (size_t)j * PEND;
+                PT* const pend = s_pend + (size_t)j * PEND;
                 unsigned long long* const lst = s_list + (size_t)j * k;
 #pragma unroll
                 for (int g = 0; g < CPL; ++g) {
                     if (m[g] == 0ull) continue;
                     uint32_t pc = (uint32_t)__popcll(m[g]);
                     if (cnt + pc > (uint32_t)PEND) {
-                        wj = flush(lst, pend, cnt, lane, k, selfkey);
+                        wj = fminf(wj, flush<POS>(lst, pend, cnt, lane, k, selfkey, cand4, q));
                         cnt = 0;
 #pragma unroll
                         for (int h = g; h < CPL; ++h) m[h] = __builtin_amdgcn_ballot_w64(d[h] <= wj);
@@ -329,7 +412,12 @@ __global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restric
                     }
                     const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
                         (uint32_t)(m[g] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[g], 0u));
-                    if ((m[g] >> lane) & 1ull) pend[cnt + rank] = make_key(d[g], __float_as_uint(c[g].w));
+                    if ((m[g] >> lane) & 1ull) {
+                        if constexpr (POS)
+                            pend[cnt + rank] = ci[g];
+                        else
+                            pend[cnt + rank] = make_key(d[g], __float_as_uint(c[g].w));
+                    }
                     cnt += pc;
                 }
                 if (lane == j) {
@@ -360,28 +448,81 @@ __global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restric
             while (qm != 0ull) {
                 const uint32_t j = (uint32_t)__ffsll((long long)qm) - 1u;
                 qm &= qm - 1ull;
-                const float4 q = make_float4(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(qv.x), (int)j)),
-                                             __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qv.y), (int)j)),
-                                             __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qv.z), (int)j)), 0.f);
-                const float wj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(worst), (int)j));
+                const float4 q = query_of(qv, j);
+                float wj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(worst), (int)j));
                 float d[CPL];
                 unsigned long long m[CPL];
                 unsigned long long any = 0ull;
+                uint32_t tot = 0;
 #pragma unroll
                 for (int g = 0; g < CPL; ++g) {
                     d[g] = dist2(q, c[g]);
                     m[g] = __builtin_amdgcn_ballot_w64(d[g] <= wj);
                     any |= m[g];
+                    tot += (uint32_t)__popcll(m[g]);
                 }
-                if (any != 0ull) append(j, wj, m, d);
+                // A block that would overflow the pending buffer first lowers
+                // the bound: if at least k + 1 of its candidates (one may be
+                // the query itself) lie within wj * 2^(-1/4), the k-th
+                // distance cannot exceed that, so nothing needed is lost.
+                if (tot > (uint32_t)PEND - (uint32_t)__builtin_amdgcn_readlane((int)pcnt, (int)j) &&
+                    tot > k + 1u && wj < INFINITY) {
+                    for (int i = 0; i < 12; ++i) {
+                        const float t2 = wj * 0.84089642f;
+                        uint32_t c2 = 0;
+#pragma unroll
+                        for (int g = 0; g < CPL; ++g)
+                            c2 += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(d[g] <= t2));
+                        if (c2 < k + 1u) break;
+                        wj = t2;
+                    }
+                    any = 0ull;
+#pragma unroll
+                    for (int g = 0; g < CPL; ++g) {
+                        m[g] = __builtin_amdgcn_ballot_w64(d[g] <= wj);
+                        any |= m[g];
+                    }
+                    if (lane == j) worst = wj;
+                }
+                if (any != 0ull) append(j, wj, m, d, q);
             }
         }
-        // drain the pending buffers
-        for (uint32_t j = 0; j < qn; ++j) {
-            const uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)pcnt, (int)j);
-            const unsigned long long selfkey =
-                (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j);
-            if (cnt) (void)flush(s_list + (size_t)j * k, s_pend + (size_t)j * PEND, cnt, lane, k, selfkey);
+        // drain the pending buffers: when k <= 32, two queries per merge if
+        // both hold at most 32 pending keys
+        if (half) {
+            for (uint32_t j = 0; j < qn; j += 2u) {
+                const uint32_t j1 = j + 1u;
+                const bool two = j1 < qn;
+                const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)pcnt, (int)j);
+                const uint32_t c1 = two ? (uint32_t)__builtin_amdgcn_readlane((int)pcnt, (int)j1) : 0u;
+                if ((c0 | c1) == 0u) continue;
+                const unsigned long long s0 =
+                    (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j);
+                const unsigned long long s1 =
+                    two ? (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j1) : 0ull;
+                unsigned long long* const l0 = s_list + (size_t)j * k;
+                PT* const p0 = s_pend + (size_t)j * PEND;
+                const float4 q0 = query_of(qv, j);
+                const float4 q1 = two ? query_of(qv, j1) : q0;
+                if (c0 <= (uint32_t)PEND_HALF && c1 <= (uint32_t)PEND_HALF) {
+                    float b0, b1;
+                    // without a second query the upper half touches no memory
+                    flush_half<POS>(l0, p0, c0, s0, q0, l0 + k, p0 + PEND, c1, s1, q1, two, lane, k, cand4, &b0,
+                                    &b1);
+                } else {
+                    if (c0) (void)flush<POS>(l0, p0, c0, lane, k, s0, cand4, q0);
+                    if (c1) (void)flush<POS>(l0 + k, p0 + PEND, c1, lane, k, s1, cand4, q1);
+                }
+            }
+        } else {
+            for (uint32_t j = 0; j < qn; ++j) {
+                const uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)pcnt, (int)j);
+                const unsigned long long selfkey =
+                    (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j);
+                if (cnt)
+                    (void)flush<POS>(s_list + (size_t)j * k, s_pend + (size_t)j * PEND, cnt, lane, k, selfkey,
+                                     cand4, query_of(qv, j));
+            }
         }
 
         if (nch > 1) {
@@ -511,11 +652,22 @@ void launch_knn_bound(const Plan& P, int k, int num_cus, hipStream_t st) {
     hipLaunchKernelGGL(knn_bound_kernel, dim3(blocks), dim3(256), 0, st, P, (const float4*)P.cand4, k);
 }
 
-size_t knn_lds_bytes(int k) { return (size_t)QPW * ((size_t)k + PEND) * sizeof(unsigned long long); }
+size_t knn_lds_bytes(int k, bool pos) {
+    return (size_t)QPW * ((size_t)k * sizeof(unsigned long long) +
+                          (size_t)PEND * (pos ? sizeof(uint32_t) : sizeof(unsigned long long)));
+}
 
 void launch_knn(const Plan& P, int k, int num_cus, hipStream_t st) {
     const unsigned blocks = (unsigned)(num_cus > 0 ? num_cus : 256) * 16u;
-    hipLaunchKernelGGL(knn_kernel, dim3(blocks), dim3(64), knn_lds_bytes(k), st, P, (const float4*)P.cand4, k);
+    // Large batches run long enough for occupancy to pay (positions); a single
+    // frame's run is set by its longest items, where a gather per merge costs
+    // more (keys).
+    if (P.n > KNN_POS_MIN_N)
+        hipLaunchKernelGGL(knn_kernel<true>, dim3(blocks), dim3(64), knn_lds_bytes(k, true), st, P,
+                           (const float4*)P.cand4, k);
+    else
+        hipLaunchKernelGGL(knn_kernel<false>, dim3(blocks), dim3(64), knn_lds_bytes(k, false), st, P,
+                           (const float4*)P.cand4, k);
 }
 
 void launch_knn_merge(const Plan& P, int k, int num_cus, hipStream_t st) {

@@ -74,6 +74,28 @@ __device__ __forceinline__ unsigned long long sort64_desc(unsigned long long v, 
     return v;
 }
 
+// Bitonic sort of each 32-lane half (one key per lane), both halves
+// descending: the stages of sort64_desc up to blocks of 16, then a final
+// merge whose direction depends only on the exchange bit.
+__device__ __forceinline__ unsigned long long sort32x2_desc(unsigned long long v, uint32_t lane) {
+    v = sort_step<2, 1>(v, lane);
+    v = sort_step<4, 2>(v, lane);
+    v = sort_step<4, 1>(v, lane);
+    v = sort_step<8, 4>(v, lane);
+    v = sort_step<8, 2>(v, lane);
+    v = sort_step<8, 1>(v, lane);
+    v = sort_step<16, 8>(v, lane);
+    v = sort_step<16, 4>(v, lane);
+    v = sort_step<16, 2>(v, lane);
+    v = sort_step<16, 1>(v, lane);
+    v = sort_step<64, 16>(v, lane);
+    v = sort_step<64, 8>(v, lane);
+    v = sort_step<64, 4>(v, lane);
+    v = sort_step<64, 2>(v, lane);
+    v = sort_step<64, 1>(v, lane);
+    return v;
+}
+
 template <int M>
 __device__ __forceinline__ float xor_f32(float x, uint32_t lane) {
     return __uint_as_float(xor_lane<M>(__float_as_uint(x), lane));
@@ -101,6 +123,16 @@ __device__ __forceinline__ float wave_max(float v, uint32_t lane) {
 // Sort a bitonic sequence (one key per lane) ascending.
 __device__ __forceinline__ unsigned long long merge64_asc(unsigned long long v, uint32_t lane) {
     v = cx<32>(v, lane, (lane & 32u) == 0u);
+    v = cx<16>(v, lane, (lane & 16u) == 0u);
+    v = cx<8>(v, lane, (lane & 8u) == 0u);
+    v = cx<4>(v, lane, (lane & 4u) == 0u);
+    v = cx<2>(v, lane, (lane & 2u) == 0u);
+    v = cx<1>(v, lane, (lane & 1u) == 0u);
+    return v;
+}
+
+// Sort a bitonic sequence in each 32-lane half ascending.
+__device__ __forceinline__ unsigned long long merge32x2_asc(unsigned long long v, uint32_t lane) {
     v = cx<16>(v, lane, (lane & 16u) == 0u);
     v = cx<8>(v, lane, (lane & 8u) == 0u);
     v = cx<4>(v, lane, (lane & 4u) == 0u);
