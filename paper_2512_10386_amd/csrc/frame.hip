@@ -205,10 +205,11 @@ __global__ __launch_bounds__(256) void bbox_fold_kernel(Plan P) {
 }
 
 void launch_bbox(const Plan& P, const float* xyz, hipStream_t st) {
-    // few points: 4096-point chunks that all add their boxes with atomics (no
-    // fold launch); otherwise BBOX_CHUNK chunks and the fold
+    // few points: 512-point chunks (one wave each, enough waves to cover the
+    // load latency) that all add their boxes with atomics (no fold launch);
+    // otherwise BBOX_CHUNK chunks and the fold
     const bool direct = P.n <= (1u << 20);
-    const uint32_t chunk = direct ? 4096u : BBOX_CHUNK;
+    const uint32_t chunk = direct ? 512u : BBOX_CHUNK;
     const uint32_t nchunks = (P.n + chunk - 1) / chunk;
     unsigned blocks = (nchunks + 3) / 4;
     if (blocks > 2048) blocks = 2048;

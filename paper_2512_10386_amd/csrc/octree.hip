@@ -292,25 +292,48 @@ void launch_p1_compact(const Plan& P, hipStream_t st) {
 // positions, the P1 prefix sums its compacted range. Ranges are sorted and
 // joined where contiguous.
 
-__device__ __forceinline__ uint32_t lower_bound_u64(const uint64_t* a, uint32_t n, uint64_t x) {
-    uint32_t lo = 0, hi = n;
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (a[mid] < x) lo = mid + 1;
-        else hi = mid;
+// Both ends of a key range, the two binary searches interleaved so that their
+// loads overlap.
+__device__ __forceinline__ void lower_bound2_u64(const uint64_t* a, uint32_t n, uint64_t x0, uint64_t x1,
+                                                 uint32_t* r0, uint32_t* r1) {
+    uint32_t lo0 = 0, hi0 = n, lo1 = 0, hi1 = n;
+    while (lo0 < hi0 || lo1 < hi1) {
+        const uint32_t m0 = (lo0 + hi0) >> 1, m1 = (lo1 + hi1) >> 1;
+        const uint64_t v0 = lo0 < hi0 ? a[m0] : 0ull;
+        const uint64_t v1 = lo1 < hi1 ? a[m1] : 0ull;
+        if (lo0 < hi0) {
+            if (v0 < x0) lo0 = m0 + 1;
+            else hi0 = m0;
+        }
+        if (lo1 < hi1) {
+            if (v1 < x1) lo1 = m1 + 1;
+            else hi1 = m1;
+        }
     }
-    return lo;
+    *r0 = lo0;
+    *r1 = lo1;
 }
 
-constexpr int HALO_LEAVES = 8;  // leaves per 256-thread block (32 threads each)
+constexpr int HALO_LEAVES = 8;  // leaves per 256-thread block (32 threads each, 27 used)
 
+// Per leaf, 27 threads find the key ranges of the 27 same-level cells around
+// it (clipped to the grid and to the frame), then the non-empty ranges are
+// sorted by rank counting and runs of touching ranges merged with ballots;
+// the result is the leaf's candidate ranges in P1 order.
 __global__ __launch_bounds__(256) void halo_kernel(Plan P) {
-    __shared__ uint2 s_r[HALO_LEAVES][HALO];
+    __shared__ uint2 s_r[HALO_LEAVES][32];
+    __shared__ uint2 s_s[HALO_LEAVES][32];
     const int tid = threadIdx.x, grp = tid >> 5, g = tid & 31;
+    const uint32_t lane = (uint32_t)tid & 63u;
     const uint32_t nl = P.ctr->n_leaves;
+    // this thread's half of the wave
+    const unsigned long long half = (lane & 32u) ? 0xFFFFFFFF00000000ull : 0x00000000FFFFFFFFull;
+    const unsigned long long below = lane == 0u ? 0ull : (~0ull >> (64u - lane));
     for (uint32_t base = blockIdx.x * HALO_LEAVES; base < nl; base += gridDim.x * HALO_LEAVES) {
         const uint32_t t = base + grp;
-        if (t < nl && g < HALO) {
+        const bool live = t < nl;
+        uint2 r = make_uint2(0u, 0u);
+        if (live && g < HALO) {
             const uint32_t f = frame_of_sorted(P, P.leaf_begin[t]);
             const uint32_t fs = P.foff[f], fe = P.foff[f + 1];
             const int d = (int)P.leaf_level[t];
@@ -318,43 +341,46 @@ __global__ __launch_bounds__(256) void halo_kernel(Plan P) {
             const int64_t cx = compact3(pre), cy = compact3(pre >> 1), cz = compact3(pre >> 2);
             const int64_t nx = cx + (g % 3) - 1, ny = cy + (g / 3) % 3 - 1, nz = cz + g / 9 - 1;
             const int64_t side = (int64_t)1 << d;
-            uint2 r = make_uint2(0u, 0u);
             if (nx >= 0 && ny >= 0 && nz >= 0 && nx < side && ny < side && nz < side) {
                 const int sh = 3 * (MORTON_BITS - d);
                 const uint64_t klo = morton3((uint32_t)nx, (uint32_t)ny, (uint32_t)nz) << sh;
                 const uint64_t khi = klo + (1ull << sh);
-                const uint32_t lo = fs + lower_bound_u64(P.keys_a + fs, fe - fs, klo);
-                const uint32_t hi = fs + lower_bound_u64(P.keys_a + fs, fe - fs, khi);
-                r = make_uint2(P.p1pos[lo], P.p1pos[hi]);
+                uint32_t lo, hi;
+                lower_bound2_u64(P.keys_a + fs, fe - fs, klo, khi, &lo, &hi);
+                r = make_uint2(P.p1pos[fs + lo], P.p1pos[fs + hi]);
             }
-            s_r[grp][g] = r;
         }
+        const bool ne = r.y > r.x;  // distinct cells: non-empty ranges have distinct starts
+        s_r[grp][g] = r;
         __syncthreads();
-        if (t < nl && g == 0) {
-            // insertion sort of the non-empty ranges, in place (slot j <= i)
-            uint2* v = s_r[grp];
-            int m = 0;
+        uint32_t rank = 0;
+        if (ne)
             for (int i = 0; i < HALO; ++i) {
-                const uint2 r = v[i];
-                if (r.y > r.x) {
-                    int j = m++;
-                    while (j > 0 && v[j - 1].x > r.x) { v[j] = v[j - 1]; --j; }
-                    v[j] = r;
-                }
+                const uint2 o = s_r[grp][i];
+                rank += (o.y > o.x && o.x < r.x) ? 1u : 0u;
             }
-            int out = 0;
-            uint32_t tot = 0;
-            for (int i = 0; i < m; ++i) {
-                if (out > 0 && v[i].x == P.leaf_ranges[(size_t)t * HALO + out - 1].y) {
-                    P.leaf_ranges[(size_t)t * HALO + out - 1].y = v[i].y;
-                } else {
-                    P.leaf_ranges[(size_t)t * HALO + out] = v[i];
-                    ++out;
-                }
-                tot += v[i].y - v[i].x;
-            }
-            P.leaf_nr[t] = (uint32_t)out;
-            P.leaf_ncand[t] = tot;
+        if (ne) s_s[grp][rank] = r;
+        const uint32_t m = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(ne) & half);
+        __syncthreads();
+        // runs of touching ranges: a run starts where the previous range ends elsewhere
+        uint2 cur = make_uint2(0u, 0u);
+        bool st = false;
+        if ((uint32_t)g < m) {
+            cur = s_s[grp][g];
+            st = g == 0 || s_s[grp][g - 1].y != cur.x;
+        }
+        const unsigned long long sm = __builtin_amdgcn_ballot_w64(st) & half;
+        if (live && st) {
+            const unsigned long long later = sm & ~(below | (1ull << lane));
+            const uint32_t nxt = later ? (uint32_t)__ffsll((long long)later) - 1u - (lane & 32u) : m;
+            const uint32_t o = (uint32_t)__popcll(sm & below);
+            P.leaf_ranges[(size_t)t * HALO + o] = make_uint2(cur.x, s_s[grp][nxt - 1u].y);
+        }
+        uint32_t len = (uint32_t)g < m ? cur.y - cur.x : 0u;
+        for (int o = 16; o > 0; o >>= 1) len += (uint32_t)__shfl_xor((int)len, o, 32);
+        if (live && g == 0) {
+            P.leaf_nr[t] = (uint32_t)__popcll(sm);
+            P.leaf_ncand[t] = len;
         }
         __syncthreads();
     }
