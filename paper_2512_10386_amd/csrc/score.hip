@@ -79,7 +79,8 @@ void launch_density(const Plan& P, const Params& prm, const float* xyz, hipStrea
 
 // ---------------------------------------------------------------- block radix select
 
-// Wave 0 finds the histogram bin holding ascending rank r; out = {bin, count below it}.
+// Wave 0 finds the histogram bin holding ascending rank r; out = {bin, count
+// below it, count in it}.
 __device__ __forceinline__ void find_bin(const uint32_t* hist, uint32_t r, uint32_t* out) {
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
@@ -99,12 +100,17 @@ __device__ __forceinline__ void find_bin(const uint32_t* hist, uint32_t r, uint3
             }
             out[0] = (uint32_t)b;
             out[1] = acc;
+            out[2] = hist[b];
         }
     }
 }
 
 // Value of ascending rank r (0-based, r < cnt) among get(0..cnt-1), by 8-bit
-// MSD passes over LDS histograms. Whole block must call it.
+// MSD passes over LDS histograms; once the selected bin holds a single value,
+// that value is the answer and is fetched directly. Whole block must call it.
+// s_sel needs SEL_SCRATCH words.
+constexpr int SEL_SCRATCH = 6;
+
 template <typename T, class Get>
 __device__ T block_select(Get get, uint32_t cnt, uint32_t r, uint32_t* s_hist, uint32_t* s_sel) {
     constexpr int BITS = 8 * (int)sizeof(T);
@@ -122,9 +128,60 @@ __device__ T block_select(Get get, uint32_t cnt, uint32_t r, uint32_t* s_hist, u
         r -= s_sel[1];
         prefix |= (T)s_sel[0] << shift;
         mask |= (T)255 << shift;
+        const bool single = s_sel[2] == 1u;
         __syncthreads();
+        if (single && shift > 0) {
+            // exactly one value carries this prefix
+            for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+                const T v = get(i);
+                if ((v & mask) == prefix) {
+                    s_sel[3] = (uint32_t)v;
+                    if constexpr (sizeof(T) > 4) s_sel[4] = (uint32_t)((unsigned long long)v >> 32);
+                }
+            }
+            __syncthreads();
+            T out = (T)s_sel[3];
+            if constexpr (sizeof(T) > 4) out |= (T)((unsigned long long)s_sel[4] << 32);
+            __syncthreads();
+            return out;
+        }
     }
     return prefix;
+}
+
+// Given a = the value of ascending rank r, the value of rank r + 1: a again
+// if more than r + 1 values are <= a, else the smallest value above a.
+template <typename T, class Get>
+__device__ T block_next_rank(Get get, uint32_t cnt, uint32_t r, T a, uint32_t* s_sel) {
+    __shared__ uint32_t s_le[SEL_BLOCK / 64];
+    __shared__ T s_mn[SEL_BLOCK / 64];
+    uint32_t le = 0;
+    T mn = ~(T)0;
+    for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const T v = get(i);
+        if (v <= a) ++le;
+        else if (v < mn) mn = v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        le += (uint32_t)__shfl_xor((int)le, o, 64);
+        const T x = (T)__shfl_xor(mn, o, 64);
+        mn = x < mn ? x : mn;
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_le[w] = le;
+        s_mn[w] = mn;
+    }
+    __syncthreads();
+    uint32_t L = 0;
+    T M = ~(T)0;
+    for (int q = 0; q < SEL_BLOCK / 64; ++q) {
+        L += s_le[q];
+        M = s_mn[q] < M ? s_mn[q] : M;
+    }
+    __syncthreads();
+    (void)s_sel;
+    return L > r + 1u ? a : M;
 }
 
 template <typename T>
@@ -169,15 +226,15 @@ __device__ void leaf_cut_and_median(RG r2, HG rho, uint32_t n1, double q, float*
     if (n1 & 1u) {
         *med = __longlong_as_double((long long)block_select<unsigned long long>(rho, n1, (n1 - 1) / 2, s_hist, s_sel));
     } else {
-        const double a = __longlong_as_double((long long)block_select<unsigned long long>(rho, n1, n1 / 2 - 1, s_hist, s_sel));
-        const double b = __longlong_as_double((long long)block_select<unsigned long long>(rho, n1, n1 / 2, s_hist, s_sel));
-        *med = (a + b) / 2.0;
+        const unsigned long long ab = block_select<unsigned long long>(rho, n1, n1 / 2 - 1, s_hist, s_sel);
+        const unsigned long long bb = block_next_rank<unsigned long long>(rho, n1, n1 / 2 - 1, ab, s_sel);
+        *med = (__longlong_as_double((long long)ab) + __longlong_as_double((long long)bb)) / 2.0;
     }
 }
 
 __global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params prm, bool small) {
     __shared__ uint32_t s_hist[256];
-    __shared__ uint32_t s_sel[2];
+    __shared__ uint32_t s_sel[SEL_SCRATCH];
     __shared__ uint32_t s_r2[SEL_LDS_MAX];
     __shared__ unsigned long long s_rho[SEL_LDS_MAX];
     const uint32_t nl = P.ctr->n_leaves;
@@ -394,7 +451,7 @@ struct CandIdx {
 
 __global__ __launch_bounds__(SEL_BLOCK) void topl_kernel(Plan P, double lambda, bool small) {
     __shared__ uint32_t s_hist[256];
-    __shared__ uint32_t s_sel[2];
+    __shared__ uint32_t s_sel[SEL_SCRATCH];
     __shared__ uint32_t s_cnt;
     __shared__ unsigned long long s_key[SEL_LDS_MAX];
     __shared__ uint32_t s_idx[SEL_LDS_MAX];
