@@ -24,6 +24,7 @@ constexpr int PLAN_LEVELS = 8;                // candidate chunk lengths chunk0 
 constexpr int KNN_TQ = 16;                    // queries per kNN work item (one wave)
 constexpr int KNN_CC0 = 16384;                // default initial candidate chunk
 constexpr int KNN_NCH_MAX = 32;               // max candidate chunks per leaf
+constexpr uint32_t KNN_STREAMS = 8;           // kNN work-queue streams (cursors)
 constexpr int HALO = 27;
 constexpr int VOX_BLOCK = 256;
 constexpr int VOX_LDS_SLOTS = 4096;           // LDS hash slots (leaves <= 2048 pts)
@@ -57,12 +58,14 @@ struct Counters {
     uint32_t sort_tile_ctr[SORT_PASSES_MAX];
     uint32_t scan_tile_ctr[SCAN_SLOTS];
     unsigned long long pairs;
-    uint32_t knn_next;        // dynamic work-queue cursor of the kNN kernel
     uint32_t n_chunked_items; // kNN items of chunked leaves (they come first)
     uint32_t plan_cc;         // chosen kNN chunk length (parallel plan)
     uint32_t pad[2];
     unsigned long long plan_acc[PLAN_LEVELS][3];  // per candidate chunk length: lists, items, chunked items
     unsigned long long plan_pairs;
+    // kNN work queue: item i belongs to stream i % KNN_STREAMS; one cursor
+    // per stream, each on its own 128-byte line
+    uint32_t knn_q[KNN_STREAMS][32];
 };
 
 // Frame constants derived on the device from the bounding box.

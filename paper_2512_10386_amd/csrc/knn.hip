@@ -283,10 +283,25 @@ __global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restric
     unsigned long long* const s_list = s_dyn;                    // [QPW][k]
     PT* const s_pend = (PT*)(s_dyn + (size_t)QPW * k);  // [QPW][PEND]
     const uint32_t n_items = P.ctr->n_items;
+    // Work queue: every wave starts on item blockIdx.x without an atomic;
+    // the rest are claimed from KNN_STREAMS interleaved streams (item i in
+    // stream i % KNN_STREAMS, cursor per stream past the items handed out
+    // statically), own stream first, then the others. One device-scope
+    // cursor for all would serialise every claim on one address.
+    const uint32_t G = gridDim.x;
+    const uint32_t s0 = blockIdx.x % KNN_STREAMS;
+    uint32_t it = blockIdx.x;
+    uint32_t sv = 0;  // streams visited after the own one
     for (;;) {
-        uint32_t got = 0;
-        if (lane == 0) got = atomicAdd(&P.ctr->knn_next, 1u);
-        const uint32_t it = __builtin_amdgcn_readfirstlane(__shfl(got, 0, 64));
+        while (it >= n_items && sv < KNN_STREAMS) {
+            const uint32_t s = (s0 + sv) % KNN_STREAMS;
+            uint32_t got = 0;
+            if (lane == 0) got = atomicAdd(&P.ctr->knn_q[s][0], 1u);
+            got = __builtin_amdgcn_readfirstlane(__shfl(got, 0, 64));
+            const uint32_t base = G > s ? (G - s + KNN_STREAMS - 1) / KNN_STREAMS : 0u;  // static items of s
+            it = (base + got) * KNN_STREAMS + s;
+            if (it >= n_items) ++sv;
+        }
         if (it >= n_items) break;
         const KnnItem w = P.items[it];
         const uint32_t t = w.leaf;
@@ -538,6 +553,7 @@ __global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restric
             }
         }
         wave_lds_sync();
+        it = n_items;  // claim the next one
     }
 }
 
