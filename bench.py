@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3      # MI355X: 256 CU x 2.4 GHz x 256 flop/clk (packed FMA)
+FP32_PACKED_NO_FMA_TOPS = 78.6      # two fp32 ops per lane-cycle (packed add/mul, no FMA)
 FP32_EXACT_CEILING_TOPS = 39.3       # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, one op per lane-cycle
 FLOPS_PER_PAIR = 8                   # 3 sub + 3 mul + 2 add per (query, candidate) pair
 
@@ -354,6 +355,7 @@ def main():
         "pairs_per_launch": pairs,
         "flops_per_pair": FLOPS_PER_PAIR,
         "kernel_ms": round(knn_ms, 5),
+        "packed_no_fma_ceiling": FP32_PACKED_NO_FMA_TOPS,
         "exact_fp32_ceiling": FP32_EXACT_CEILING_TOPS,
         "frac_of_exact_ceiling": round(achieved / FP32_EXACT_CEILING_TOPS, 4),
     }
