@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from paper_2512_10386_amd import synth
-from tests.parity import compare, run_gpu
+from tests.parity import compare, leaf_thresholds, run_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -266,3 +266,47 @@ def test_large_batch_paths_equal_plain(bden, den):
     dumps = batch_dumps(bden, xyz.shape[0], len(frames))
     assert dumps["status"] == 0
     check_frames_equal_plain(den, frames, off, o, dumps, params)
+
+
+def test_bench_batch_configuration_sampled_frames_vs_oracle(bden, oracle):
+    """The 64-frame LiDAR batch (6.2M points) in the configuration the
+    benchmark times after autotuning (leaf cap 256, candidate chunks of
+    32768; above 1M points the kNN keeps candidate positions in its buffers):
+    three sampled frames against the oracle at the same parameters, down to
+    the neighbour lists, and every frame's counts and device status."""
+    import torch
+    frames, _, params = synth.make("lidar_batch_64")
+    params = dict(params, leaf_cap=256, knn_chunk=32768)
+    xyz, offd, off = to_dev(frames)
+    n, nf = xyz.shape[0], len(frames)
+    assert n > (1 << 20)
+    bden.set_params(**params)
+    res = bden(xyz, offd)
+    o = outputs(res, n, nf)
+    torch.cuda.synchronize()
+    assert int(bden.dump("STATUS", n).cpu().numpy()[0]) == 0
+    nbr = bden.dump("NBR_IDX", n).cpu().numpy().view(np.uint32)
+    keep = o["keep"]
+    for f in range(nf):
+        a, b = int(off[f]), int(off[f + 1])
+        assert o["n_kept"][f] == int(keep[a:b].sum()), f
+    oparams = {k: v for k, v in params.items() if k != "knn_chunk"}
+    for f in (0, 31, 63):
+        a, b = int(off[f]), int(off[f + 1])
+        ref = oracle.denoise(frames[f], **oparams)
+        tag = f"frame {f} (n={b - a})"
+        p1 = ref["p1"] == 1
+        nb = nbr[a:b].copy()
+        nb[nb != 0xFFFFFFFF] -= a
+        assert np.array_equal(nb[p1], ref["nbr_idx"][p1]), tag
+        F = ref["score"]
+        m = F >= 0
+        assert np.allclose(o["score"][a:b][m], F[m], rtol=1e-5, atol=0), tag
+        # keep labels may differ only within the score tolerance of a leaf's cut
+        th = leaf_thresholds(ref)
+        diff = np.nonzero(keep[a:b] != ref["keep"])[0]
+        for i in diff:
+            t = ref["leaf_of"][i]
+            assert ref["p2"][i] == 1 and abs(F[i] - th[t]) <= 1e-5 * th[t], (tag, i)
+        same = keep[a:b] == ref["keep"]
+        assert np.array_equal(o["stage"][a:b][same], ref["stage"][same]), tag
