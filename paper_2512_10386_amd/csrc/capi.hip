@@ -123,7 +123,7 @@ gdn::Plan make_plan(uint32_t n, uint32_t nf, int k, char* base) {
     P.p2 = (uint8_t*)take(N);
     P.stage_c = (uint8_t*)take(N);
     P.score_c = (double*)take(8 * N);
-    P.gpow_o = (double*)take(8 * N);
+    P.rec_o = (NbrRec*)take(sizeof(NbrRec) * N);
     P.items = (KnnItem*)take(sizeof(KnnItem) * (size_t)P.items_max);
     P.plist = (uint64_t*)take(8 * (size_t)P.plist_max * k);
     P.bytes = off;
@@ -349,7 +349,7 @@ static gdn_status run(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int64
     gdn::launch_density(P, prm, xyz, st);
     gdn::launch_leaf_select(P, prm, st);
     if (prm.stages & GDN_STAGE_SCORE) {
-        gdn::launch_score(P, prm, xyz, st);
+        gdn::launch_score(P, prm, st);
         gdn::launch_topl(P, prm, st);
     } else {
         gdn::launch_keep_p2(P, st);

@@ -416,15 +416,49 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
     uint32_t total;
     uint32_t gex = block_excl_scan(hist[tid], s_scan, &total);
     s_base[tid] = gex + excl;
-    __syncthreads();
+    if constexpr (ITEMS >= 16) {
+        // Large tiles: stage the tile in LDS in digit order, then write each
+        // digit's run with consecutive threads (coalesced) instead of
+        // scattering from registers.
+        __shared__ uint64_t s_k[SORT_BLOCK * ITEMS];
+        __shared__ uint32_t s_v[SORT_BLOCK * ITEMS];
+        __shared__ uint32_t s_toff[256];
+        uint32_t ttot;
+        const uint32_t tex = block_excl_scan(tcnt, s_scan, &ttot);
+        s_toff[tid] = tex;
+        __syncthreads();
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t d = dig[i];
-        if (d < 256u) {
-            const uint32_t o = s_base[d] + s_w[wave][d] + rank[i];
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t d = dig[i];
+            if (d < 256u) {
+                const uint32_t lp = s_toff[d] + s_w[wave][d] + rank[i];
+                s_k[lp] = key[i];
+                s_v[lp] = val[i];
+            }
+        }
+        __syncthreads();
+        for (uint32_t p = tid; p < ttot; p += SORT_BLOCK) {
+            const uint64_t kk = s_k[p];
+            const uint32_t vv = s_v[p];
+            const uint32_t d = pass < SORT_PASSES ? (uint32_t)((kk >> shift) & 255u)
+                                                  : (fid[vv] >> (8 * (pass - SORT_PASSES))) & 255u;
+            const uint32_t o = s_base[d] + (p - s_toff[d]);
             if (o < n) {  // always true unless a look-back wait expired
-                kout[o] = key[i];
-                vout[o] = val[i];
+                kout[o] = kk;
+                vout[o] = vv;
+            }
+        }
+    } else {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t d = dig[i];
+            if (d < 256u) {
+                const uint32_t o = s_base[d] + s_w[wave][d] + rank[i];
+                if (o < n) {  // always true unless a look-back wait expired
+                    kout[o] = key[i];
+                    vout[o] = val[i];
+                }
             }
         }
     }

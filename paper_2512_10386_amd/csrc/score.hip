@@ -269,7 +269,8 @@ __global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params p
             P.p2[qi] = (!insufficient && P.r2k[qi] <= cut) ? 1 : 0;
             P.afac_c[qi] = pow(P.rho_c[qi] / den, ha);
             // rho_j^(alpha/2) of Eq. 17's factored density weight, by original index
-            P.gpow_o[__float_as_uint(P.cand4[qi].w)] = pow(P.rho_c[qi], ha);
+            const float4 c = P.cand4[qi];
+            P.rec_o[__float_as_uint(c.w)] = NbrRec{c, pow(P.rho_c[qi], ha), 0.0};
         }
         if (threadIdx.x == 0) { P.leaf_rho_med[t] = med; P.leaf_r2cut[t] = cut; }
         __syncthreads();
@@ -338,7 +339,8 @@ __global__ __launch_bounds__(256) void leaf_select_small_kernel(Plan P, Params p
             const double rho = P.rho_c[qi];
             P.p2[qi] = (!insufficient && P.r2k[qi] <= cut) ? 1 : 0;
             P.afac_c[qi] = pow(rho / den, ha);
-            P.gpow_o[__float_as_uint(P.cand4[qi].w)] = pow(rho, ha);
+            const float4 c = P.cand4[qi];
+            P.rec_o[__float_as_uint(c.w)] = NbrRec{c, pow(rho, ha), 0.0};
         }
         if (lane == 0) { P.leaf_rho_med[t] = med; P.leaf_r2cut[t] = cut; }
     }
@@ -365,8 +367,7 @@ void launch_leaf_select(const Plan& P, const Params& prm, hipStream_t st) {
 // gets the Gaussian factor 1 (also when r_K,i = 0). The k terms are summed by
 // a fixed pairwise tree (lane r holds term r), not left to right.
 
-__global__ __launch_bounds__(256) void score_kernel(Plan P, const float* __restrict__ xyz, int kk, double sigma,
-                                                    double eps, double gamma) {
+__global__ __launch_bounds__(256) void score_kernel(Plan P, int kk, double sigma, double eps, double gamma) {
     const uint32_t np1 = P.ctr->n_p1;
     const uint32_t k = (uint32_t)kk, kp = pow2_at_least(k), qpw = 64u / kp;
     const uint32_t lane = threadIdx.x & 63u, seg = lane / kp, r = lane % kp;
@@ -378,13 +379,16 @@ __global__ __launch_bounds__(256) void score_kernel(Plan P, const float* __restr
         if (live && r < k) {
             const uint32_t j = P.nbr[(size_t)qi * k + r];
             if (j < P.n) {
-                const uint32_t i = __float_as_uint(P.cand4[qi].w);
+                // the query from its sorted copy, the neighbour from its record
+                // (both bit copies of the input coordinates)
+                const float4 a = P.cand4[qi];
+                const NbrRec R = P.rec_o[j];
                 const double sr = sigma * P.r64_c[qi];
-                const double dx = (double)xyz[3 * (size_t)j] - (double)xyz[3 * (size_t)i];
-                const double dy = (double)xyz[3 * (size_t)j + 1] - (double)xyz[3 * (size_t)i + 1];
-                const double dz = (double)xyz[3 * (size_t)j + 2] - (double)xyz[3 * (size_t)i + 2];
+                const double dx = (double)R.p.x - (double)a.x;
+                const double dy = (double)R.p.y - (double)a.y;
+                const double dz = (double)R.p.z - (double)a.z;
                 const double d2 = dx * dx + dy * dy + dz * dz;
-                const double w_den = P.afac_c[qi] * P.gpow_o[j];
+                const double w_den = P.afac_c[qi] * R.gpow;
                 const double w_dis = (d2 == 0.0) ? 1.0 : exp(-d2 / (2.0 * sr * sr));
                 const double kern = gamma == 2.0 ? 1.0 / (d2 + eps) : pow(d2 + eps, -gamma / 2.0);
                 term = w_den * w_dis * kern;
@@ -395,14 +399,14 @@ __global__ __launch_bounds__(256) void score_kernel(Plan P, const float* __restr
     }
 }
 
-void launch_score(const Plan& P, const Params& prm, const float* xyz, hipStream_t st) {
+void launch_score(const Plan& P, const Params& prm, hipStream_t st) {
     uint32_t kp = 1;
     while (kp < (uint32_t)prm.k) kp <<= 1;
     const uint64_t waves = ((uint64_t)P.n * kp + 63) / 64;
     unsigned blocks = (unsigned)((waves + 3) / 4);
     if (blocks > 8192) blocks = 8192;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(score_kernel, dim3(blocks), dim3(256), 0, st, P, xyz, prm.k, prm.sigma, prm.eps, prm.gamma);
+    hipLaunchKernelGGL(score_kernel, dim3(blocks), dim3(256), 0, st, P, prm.k, prm.sigma, prm.eps, prm.gamma);
 }
 
 // ---------------------------------------------------------------- top-lambda
