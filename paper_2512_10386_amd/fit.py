@@ -10,6 +10,8 @@ recall and F1 of noise removal (Eq. 26-28).
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 
 from . import binding as B
@@ -51,6 +53,7 @@ class ScoreFit:
         return self.out
 
 
+@functools.lru_cache(maxsize=None)
 def _loss_fn():
     import torch
 
@@ -73,14 +76,9 @@ def _loss_fn():
     return ScoreLoss
 
 
-ScoreLoss = None
-
-
 def score_loss(theta, fit: ScoreFit):
-    global ScoreLoss
-    if ScoreLoss is None:
-        ScoreLoss = _loss_fn()
-    return ScoreLoss.apply(theta, fit)
+    """Differentiable loss of ``fit`` at theta = (alpha, sigma, gamma, tau)."""
+    return _loss_fn().apply(theta, fit)
 
 
 def fit_params(fit: ScoreFit, theta0, steps: int = 100, lr: float = 0.05, min_sigma: float = 1e-3):
