@@ -249,12 +249,14 @@ def test_empty_batch(bden):
     assert out.n_kept.cpu().tolist() == [0, 0, 0]
 
 
-def test_large_batch_paths_equal_plain(bden, den):
+@pytest.mark.parametrize("k", [16, 48])
+def test_large_batch_paths_equal_plain(bden, den, k):
     # over 1M points: 16-key radix tiles, 16-item scans, the parallel kNN plan,
-    # the folded frame boxes and the one-wave selects for leaves <= 256 P1
-    # points all run here, and every frame must still equal its plain run
-    # (which, under 1M points, takes the other paths)
-    params = dict(k=16, leaf_cap=256)
+    # the folded frame boxes, the one-wave selects for leaves <= 256 P1 points
+    # and the kNN's position buffers all run here (k = 16: half-wave merges,
+    # k = 48: whole-wave merges), and every frame must still equal its plain
+    # run (which, under 1M points, takes the other paths)
+    params = dict(k=k, leaf_cap=256)
     frames = [synth.lidar_frame(seed=60 + i, n_az=int(n))[0] for i, n in enumerate([1500, 1700, 1300, 1900, 1600,
                                                                                     1800, 1400, 1750, 1650, 1550,
                                                                                     1450, 1850])]
