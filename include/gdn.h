@@ -272,7 +272,10 @@ enum {
     GDN_DUMP_STATUS = 0,     /* uint32 device status word (GDN_DEV_*) */
     GDN_DUMP_COUNTS = 1,     /* int64[4]: n_leaves, |P1|, kNN pair count W, n_kept */
     GDN_DUMP_KEYS = 2,       /* uint64[n] Morton keys */
-    GDN_DUMP_ORDER = 3,      /* uint32[n] original index at each sorted position */
+    GDN_DUMP_ORDER = 3,      /* uint32[n] original index at each sorted position: leaves in
+                                Morton order, each over its [begin, end); inside a leaf the
+                                order is unspecified (keys are sorted only as deep as the
+                                octree reaches) */
     GDN_DUMP_LEAF_OF = 4,    /* uint32[n] leaf id of each point */
     GDN_DUMP_LEAF_TABLE = 5, /* uint32[n_leaves][4]: begin, end, level, fp32 bits of h */
     GDN_DUMP_OCC = 6,        /* uint32[n] voxel occupancy n(voxel(p)) of Eq. 12 */

@@ -72,6 +72,9 @@ gdn::Plan make_plan(uint32_t n, uint32_t nf, int k, char* base) {
     P.sort_hist = (uint32_t*)take(sizeof(uint32_t) * SORT_PASSES_MAX * 256);
     P.sort_status = (uint32_t*)take(sizeof(uint32_t) * (size_t)P.sort_passes * P.sort_tiles * 256);
     P.scan_status = (uint32_t*)take(sizeof(uint32_t) * SCAN_SLOTS * (size_t)P.scan_tiles);
+    P.deep_bits = DEEP_HASH_MIN_BITS;
+    while (P.deep_bits < DEEP_HASH_MAX_BITS && (1ull << P.deep_bits) < N) ++P.deep_bits;
+    P.deep_hash = (uint32_t*)take(sizeof(uint32_t) << P.deep_bits);
     P.zero_begin = base ? base + z0 : nullptr;
     P.zero_bytes = off - z0;
 

@@ -260,7 +260,12 @@ __global__ __launch_bounds__(256) void frame_const_kernel(Plan P, double min_lea
 // Keys (quantised with the point's own frame constants), the identity
 // payload and the digit histograms of the sort: 8 key digits, then the frame
 // id digits of a batch. A single frame computes its constants per block.
-__global__ __launch_bounds__(256) void morton_kernel(const float* __restrict__ xyz, Plan P, double min_leaf_side) {
+// Each point also counts its level-10 cell (frame, 30-bit prefix) in a
+// hashed table; a counter passing `cap` (a cell, or cells sharing a
+// counter, above the leaf capacity) asks for the full sort. Cells at or
+// below the depth limit never split and are not counted.
+__global__ __launch_bounds__(256) void morton_kernel(const float* __restrict__ xyz, Plan P, double min_leaf_side,
+                                                     uint32_t cap) {
     __shared__ FrameConst s_fc;
     __shared__ uint32_t s_hist[SORT_PASSES_MAX][256];
     const uint32_t n = P.n, nf = P.nf, nh = P.sort_passes;
@@ -279,6 +284,11 @@ __global__ __launch_bounds__(256) void morton_kernel(const float* __restrict__ x
         const uint64_t key = morton3(qx, qy, qz);
         P.keys_src[i] = key;
         P.idx_src[i] = i;
+        if (SORT_SHORT_LEVEL < fc.dmax) {
+            const uint64_t cell = (key >> (3 * (MORTON_BITS - SORT_SHORT_LEVEL))) | ((uint64_t)f << 32);
+            const uint32_t h = (uint32_t)((cell * 0x9E3779B97F4A7C15ull) >> (64u - P.deep_bits));
+            if (atomicAdd(&P.deep_hash[h], 1u) == cap) atomicOr(&P.ctr->sort_deep, 1u);
+        }
 #pragma unroll
         for (int p = 0; p < SORT_PASSES; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
         for (uint32_t p = SORT_PASSES; p < nh; ++p) atomicAdd(&s_hist[p][(f >> (8 * (p - SORT_PASSES))) & 255u], 1u);
@@ -294,7 +304,8 @@ void launch_morton(const Plan& P, const Params& prm, const float* xyz, hipStream
     if (P.nf > 1) hipLaunchKernelGGL(frame_const_kernel, dim3(1), dim3(256), 0, st, P, prm.min_leaf_side);
     unsigned blocks = (P.n + 2047) / 2048;
     if (blocks > 512) blocks = 512;
-    hipLaunchKernelGGL(morton_kernel, dim3(blocks), dim3(256), 0, st, xyz, P, prm.min_leaf_side);
+    hipLaunchKernelGGL(morton_kernel, dim3(blocks), dim3(256), 0, st, xyz, P, prm.min_leaf_side,
+                       (uint32_t)prm.leaf_cap);
 }
 
 // ---------------------------------------------------------------- radix sort
@@ -304,6 +315,9 @@ void launch_morton(const Plan& P, const Params& prm, const float* xyz, hipStream
 // decoupled look-back (bounded waits), global digit bases from the histogram.
 // Passes past the key's 8 take the digit from the frame id of the payload
 // (the original index), so a batch ends sorted by (frame, key, index).
+// Key passes below SORT_SHORT_FIRST return at once unless the Morton kernel
+// asked for the full sort (the order is then by (frame, key bits 32..62,
+// index), which resolves every cell of the octree).
 template <int ITEMS>
 __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* __restrict__ kin,
                                                                 const uint32_t* __restrict__ vin,
@@ -311,7 +325,9 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
                                                                 uint32_t* __restrict__ vout, uint32_t n,
                                                                 int pass, const uint32_t* __restrict__ hist,
                                                                 uint32_t* status, uint32_t* tile_ctr,
-                                                                uint32_t* dev_status, const uint32_t* __restrict__ fid) {
+                                                                uint32_t* dev_status, const uint32_t* __restrict__ fid,
+                                                                const uint32_t* __restrict__ deep) {
+    if (pass < SORT_SHORT_FIRST && *deep == 0u) return;
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_w[SORT_BLOCK / 64][256];
     __shared__ uint32_t s_base[256];
@@ -476,7 +492,7 @@ void launch_sort(const Plan& P, hipStream_t st) {
         hipLaunchKernelGGL(kern, dim3(P.sort_tiles), dim3(SORT_BLOCK), 0, st, kin, vin, kout, vout,
                            P.n, (int)pass, P.sort_hist + 256 * pass,
                            P.sort_status + (size_t)pass * P.sort_tiles * 256, &P.ctr->sort_tile_ctr[pass],
-                           &P.ctr->status, (const uint32_t*)P.fid);
+                           &P.ctr->status, (const uint32_t*)P.fid, (const uint32_t*)&P.ctr->sort_deep);
         const uint64_t* tk = kout;
         const uint32_t* tv = vout;
         kout = (uint64_t*)kin;

@@ -44,6 +44,38 @@ def run_gpu(den, xyz):
     return out
 
 
+SHORT_SORT_LEVEL = 10  # octrees no deeper than this: keys sorted on bits 32..62 only
+
+
+def short_order(ref):
+    """Order of the short sort: (key bits 32..62, original index)."""
+    n = len(ref["keep"])
+    return np.lexsort((np.arange(n), ref["key"] >> np.uint64(32))).astype(np.uint32)
+
+
+def check_order(order, ref, expect=None):
+    """The sorted order is the oracle's full (key, index) order, or, when no
+    leaf lies below level 10, possibly the short sort's (key bits 32..62,
+    index) order; the kernels take the short one unless a hashed count of the
+    level-10 cells passes leaf_cap. Either way every leaf's points fill its
+    range [begin, end) in leaf order. expect = "full" / "short" pins the path."""
+    n = len(ref["keep"])
+    assert np.array_equal(np.sort(order), np.arange(n, dtype=order.dtype)), "order is not a permutation"
+    sizes = (ref["leaf_end"] - ref["leaf_begin"]).astype(np.int64)
+    want = np.repeat(np.arange(ref["n_leaves"], dtype=np.uint32), sizes)
+    assert np.array_equal(ref["leaf_of"][order], want), "order: a point outside its leaf's range"
+    full = np.array_equal(order, ref["order"])
+    short = np.array_equal(order, short_order(ref))
+    if ref["n_leaves"] and int(ref["leaf_level"].max()) > SHORT_SORT_LEVEL:
+        expect = "full"
+    if expect == "full":
+        assert full, "order: expected the full key order"
+    elif expect == "short":
+        assert short, "order: expected the short-sort order"
+    else:
+        assert full or short, "order: neither the full nor the short-sort order"
+
+
 def leaf_thresholds(ref):
     """theta_t: the smallest oracle score kept in each leaf (inf if none)."""
     th = np.full(ref["n_leaves"], np.inf)
@@ -53,7 +85,7 @@ def leaf_thresholds(ref):
     return th
 
 
-def compare(g, ref, exact_rho=False, log_threshold=None):
+def compare(g, ref, exact_rho=False, log_threshold=None, order=None):
     """Assert GPU results match the oracle to the parity bar; return stats.
     With log_threshold (threshold keep mode) the cut is e^threshold in every leaf."""
     n = len(ref["keep"])
@@ -63,10 +95,11 @@ def compare(g, ref, exact_rho=False, log_threshold=None):
         return stats
     assert g["status"] == 0, f"device status {g['status']}"
     assert g["n_leaves"] == ref["n_leaves"]
-    for f in ["key", "order", "leaf_of", "occ", "p1"]:
+    for f in ["key", "leaf_of", "occ", "p1"]:
         assert np.array_equal(g[f], ref[f]), f
     for f in ["leaf_begin", "leaf_end", "leaf_level", "leaf_ncand"]:
         assert np.array_equal(g[f], ref[f]), f
+    check_order(g["order"], ref, order)
     assert np.array_equal(g["leaf_h"].view(np.uint32), ref["leaf_h"].view(np.uint32)), "leaf_h"
     assert g["n_p1"] == int(ref["p1"].sum())
     assert g["pairs"] == ref["pairs"]

@@ -95,13 +95,17 @@ def check_frames_equal_plain(den, frames, off, o, dumps, params):
             continue
         B = {w: v[a:b] for w, v in dumps.items() if w in PER_POINT}
         assert np.array_equal(B["KEYS"].view(np.uint64), g["key"]), tag
-        assert np.array_equal(B["ORDER"].view(np.uint32) - a, g["order"]), tag
         lof = B["LEAF_OF"].view(np.uint32)
         assert np.array_equal(lof - lof.min(), g["leaf_of"]), tag
         lt = dumps["LEAF_TABLE"]
         mine = lt[(lt[:, 0] >= a) & (lt[:, 0] < b)]
         assert len(mine) == g["n_leaves"], tag
         assert np.array_equal(mine[:, 0] - a, g["leaf_begin"]) and np.array_equal(mine[:, 1] - a, g["leaf_end"]), tag
+        # the same points in every leaf range (the order inside a leaf is free)
+        bo = B["ORDER"].view(np.uint32) - a
+        want = np.repeat(np.arange(g["n_leaves"], dtype=np.uint32), (g["leaf_end"] - g["leaf_begin"]).astype(np.int64))
+        assert np.array_equal(np.sort(bo), np.arange(n, dtype=np.uint32)), tag
+        assert np.array_equal(g["leaf_of"][bo], want) and np.array_equal(g["leaf_of"][g["order"]], want), tag
         assert np.array_equal(mine[:, 2], g["leaf_level"]), tag
         assert np.array_equal(mine[:, 3], g["leaf_h"].view(np.uint32)), tag
         for w, key in (("OCC", "occ"), ("P1", "p1"), ("P2", "p2")):

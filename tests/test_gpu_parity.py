@@ -1,7 +1,9 @@
 """HIP path vs the CPU oracle, element by element, through the C ABI.
 
-Keys, order, leaves, voxel sizes, occupancy, P1, kNN index sets and squared
-distances, r^2_K and P2 must be bit-exact; densities and medians agree to FP64
+Keys, leaves, voxel sizes, occupancy, P1, kNN index sets and squared
+distances, r^2_K and P2 must be bit-exact; the sorted order is the oracle's
+(key, index) order, or (key bits 32..62, index) where no leaf lies below
+level 10; densities and medians agree to FP64
 rounding; scores to 1e-5 relative; keep labels may differ only for points whose
 score is within 1e-5 of their leaf's cut.
 """
@@ -22,12 +24,12 @@ def den():
     d.close()
 
 
-def check(den, oracle, xyz, **params):
+def check(den, oracle, xyz, order=None, **params):
     print(f"[parity] n={len(xyz)} params={params}", flush=True)
     den.set_params(**params)
     g = run_gpu(den, xyz)
     ref = oracle.denoise(xyz, **params)
-    st = compare(g, ref)
+    st = compare(g, ref, order=order)
     print(f"[parity] ok n={len(xyz)} leaves={ref['n_leaves']} pairs={ref['pairs']} {st}", flush=True)
     return g, ref
 
@@ -39,7 +41,7 @@ def test_sphere_plane_20k_k16(den, oracle):
 
 def test_lidar_120k_k32_full_size(den, oracle):
     xyz, _, p = synth.make("lidar_120k")
-    g, ref = check(den, oracle, xyz, **p)
+    g, ref = check(den, oracle, xyz, order="short", **p)
     assert ref["n_leaves"] > 100 and ref["pairs"] > 1e8
 
 
@@ -88,7 +90,28 @@ def test_cap_one_and_depth_limit(den, oracle):
     xyz, _ = synth.uniform_cube(8, 600)
     check(den, oracle, xyz, k=4, leaf_cap=1, min_vox_count=1)
     S = float((xyz.max(0).astype(np.float64) - xyz.min(0)).max())
-    check(den, oracle, xyz, k=4, leaf_cap=4, min_vox_count=1, min_leaf_side=S / 16.0)
+    check(den, oracle, xyz, order="short", k=4, leaf_cap=4, min_vox_count=1, min_leaf_side=S / 16.0)
+    # depth limit 2: over-full leaves at level 2, no level-10 cell can split
+    g, ref = check(den, oracle, xyz, order="short", k=4, leaf_cap=4, min_vox_count=1, min_leaf_side=S / 4.0)
+    assert ref["leaf_level"].max() == 2 and (ref["leaf_end"] - ref["leaf_begin"]).max() > 4
+
+
+def test_dense_cluster_needs_full_sort(den, oracle):
+    """A tight cluster inside a unit cube: leaves below level 10, so the
+    level-10 count must ask for every key digit (the order is the full one)."""
+    xyz, _ = synth.uniform_cube(11, 3000)
+    rng = np.random.default_rng(11)
+    blob = (np.float32(0.3) + rng.uniform(0, 2e-5, (4000, 3))).astype(np.float32)
+    g, ref = check(den, oracle, np.concatenate([xyz, blob]), order="full", k=8, leaf_cap=64, min_vox_count=2)
+    assert ref["leaf_level"].max() > 10
+
+
+def test_short_sort_on_sphere_plane(den, oracle):
+    """Leaves no deeper than level 3, cap 512: the short sort, whose order
+    differs from the full key order inside leaves."""
+    xyz, _, p = synth.make("sphere_plane_20k")
+    g, ref = check(den, oracle, xyz, order="short", **p)
+    assert not np.array_equal(g["order"], ref["order"])
 
 
 def test_parameter_variety(den, oracle):
