@@ -79,20 +79,34 @@ __device__ __forceinline__ unsigned long long shfl64(unsigned long long v, int s
 
 constexpr int BOUND_MARGIN = 64;   // window reaches this far on each side of a query
 constexpr int BOUND_LEVELS = 10;   // thresholds tau * 2^(-m/2), m = 1..10
+constexpr int BOUND_SPLIT = 4;     // adjacent lanes sharing one query's distances
+constexpr int BOUND_Q = 256;       // queries per block (BOUND_Q * BOUND_SPLIT threads)
 
 // tau: the largest d2 to the k points next to the query in Morton order inside
 // [qb, qe), a run of candidates holding the query; then, over the run's points
 // within BOUND_MARGIN positions, count those under tau * 2^(-m/2) and keep the
 // smallest threshold still holding k. -1 when the run has <= k points.
+// The BOUND_SPLIT lanes of a query each take every BOUND_SPLIT-th point and
+// combine their maxima and counts (exact, so tau does not depend on the
+// split); every lane of the wave calls this, `run` false for idle ones.
 template <class Pts>
-__device__ float query_bound(Pts cand4, uint32_t qb, uint32_t qe, uint32_t qi, int k) {
-    if (qe - qb <= (uint32_t)k) return -1.0f;
-    const float4 q = cand4[qi];
-    uint32_t s0 = (qi - qb > (uint32_t)(k / 2)) ? qi - (uint32_t)(k / 2) : qb;
-    if (s0 + (uint32_t)k + 1u > qe) s0 = qe - (uint32_t)k - 1u;
+__device__ float query_bound(Pts cand4, uint32_t qb, uint32_t qe, uint32_t qi, int k, uint32_t sub, bool live) {
+    const bool run = live && qe - qb > (uint32_t)k;
+    float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint32_t s0 = 0, s1 = 0, wlo = 0, whi = 0;
+    if (run) {
+        q = cand4[qi];
+        s0 = (qi - qb > (uint32_t)(k / 2)) ? qi - (uint32_t)(k / 2) : qb;
+        if (s0 + (uint32_t)k + 1u > qe) s0 = qe - (uint32_t)k - 1u;
+        s1 = s0 + (uint32_t)k + 1u;
+        wlo = (qi - qb > (uint32_t)BOUND_MARGIN) ? qi - (uint32_t)BOUND_MARGIN : qb;
+        whi = min(qe, qi + (uint32_t)BOUND_MARGIN + 1u);
+    }
     float tau = 0.0f;
-    for (uint32_t j = s0; j <= s0 + (uint32_t)k; ++j)
+    for (uint32_t j = s0 + sub; j < s1; j += BOUND_SPLIT)
         if (j != qi) tau = fmaxf(tau, dist2(q, cand4[j]));
+#pragma unroll
+    for (int o = 1; o < BOUND_SPLIT; o <<= 1) tau = fmaxf(tau, __shfl_xor(tau, o, 64));
     float th[BOUND_LEVELS];
     uint32_t cnt[BOUND_LEVELS];
     float f = tau;
@@ -102,9 +116,7 @@ __device__ float query_bound(Pts cand4, uint32_t qb, uint32_t qe, uint32_t qi, i
         th[m] = f;
         cnt[m] = 0;
     }
-    const uint32_t wlo = (qi - qb > (uint32_t)BOUND_MARGIN) ? qi - (uint32_t)BOUND_MARGIN : qb;
-    const uint32_t whi = min(qe, qi + (uint32_t)BOUND_MARGIN + 1u);
-    for (uint32_t j = wlo; j < whi; ++j) {
+    for (uint32_t j = wlo + sub; j < whi; j += BOUND_SPLIT) {
         const float d = dist2(q, cand4[j]);
         const uint32_t notself = (j != qi) ? 1u : 0u;
 #pragma unroll
@@ -112,9 +124,12 @@ __device__ float query_bound(Pts cand4, uint32_t qb, uint32_t qe, uint32_t qi, i
     }
     float best = tau;
 #pragma unroll
-    for (int m = 0; m < BOUND_LEVELS; ++m)
+    for (int m = 0; m < BOUND_LEVELS; ++m) {
+#pragma unroll
+        for (int o = 1; o < BOUND_SPLIT; o <<= 1) cnt[m] += (uint32_t)__shfl_xor((int)cnt[m], o, 64);
         if (cnt[m] >= (uint32_t)k) best = th[m];
-    return best;
+    }
+    return run ? best : -1.0f;
 }
 
 // Points [lo, lo + count) of the P1 order, staged in LDS.
@@ -124,25 +139,32 @@ struct StagedPts {
     __device__ float4 operator[](uint32_t j) const { return s[j - lo]; }
 };
 
-// One thread per P1 point: its bound, and, for the first query of each tile,
-// the tile's work items (one per candidate chunk) at the queue position the
-// plan gave the leaf. A block takes 256 consecutive queries; every window
-// lies within BOUND_MARGIN of its query, so the block stages those points.
-__global__ __launch_bounds__(256) void knn_bound_kernel(Plan P, const float4* __restrict__ cand4, int k) {
-    __shared__ float4 s_pts[256 + 2 * BOUND_MARGIN + 1];
+// BOUND_SPLIT lanes per P1 point: its bound, and, for the first query of each
+// tile, the tile's work items (one per candidate chunk) at the queue position
+// the plan gave the leaf. A block takes BOUND_Q consecutive queries; every
+// window lies within BOUND_MARGIN of its query, so the block stages those
+// points.
+__global__ __launch_bounds__(BOUND_Q * BOUND_SPLIT) void knn_bound_kernel(Plan P, const float4* __restrict__ cand4,
+                                                                         int k) {
+    __shared__ float4 s_pts[BOUND_Q + 2 * BOUND_MARGIN + 1];
     const uint32_t np1 = P.ctr->n_p1;
-    for (uint32_t q_first = blockIdx.x * 256u; q_first < np1; q_first += gridDim.x * 256u) {
+    const uint32_t sub = threadIdx.x % BOUND_SPLIT, ql = threadIdx.x / BOUND_SPLIT;
+    for (uint32_t q_first = blockIdx.x * BOUND_Q; q_first < np1; q_first += gridDim.x * BOUND_Q) {
         const uint32_t lo = q_first > (uint32_t)BOUND_MARGIN ? q_first - (uint32_t)BOUND_MARGIN : 0u;
-        const uint32_t hi = min(np1, q_first + 256u + (uint32_t)BOUND_MARGIN + 1u);
-        for (uint32_t j = lo + threadIdx.x; j < hi; j += 256u) s_pts[j - lo] = cand4[j];
+        const uint32_t hi = min(np1, q_first + BOUND_Q + (uint32_t)BOUND_MARGIN + 1u);
+        for (uint32_t j = lo + threadIdx.x; j < hi; j += blockDim.x) s_pts[j - lo] = cand4[j];
         __syncthreads();
-        const uint32_t qi = q_first + threadIdx.x;
-        if (qi < np1) {
-            const uint32_t t = P.cand_leaf[qi];
-            const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
+        const uint32_t qi = q_first + ql;
+        const bool live = qi < np1;
+        uint32_t t = 0, qb = 0, qe = 0, rb = 0, re = 0;
+        if (live) {
+            t = P.cand_leaf[qi];
+            qb = P.p1pos[P.leaf_begin[t]];
+            qe = P.p1pos[P.leaf_begin[t + 1]];
             // the window lives in the merged candidate range holding the query,
             // which may reach past a small leaf (every point of it is a candidate)
-            uint32_t rb = qb, re = qe;
+            rb = qb;
+            re = qe;
             const uint32_t nr = P.leaf_nr[t];
             for (uint32_t r = 0; r < nr; ++r) {
                 const uint2 R = P.leaf_ranges[(size_t)t * HALO + r];
@@ -152,7 +174,10 @@ __global__ __launch_bounds__(256) void knn_bound_kernel(Plan P, const float4* __
                     break;
                 }
             }
-            P.tau_c[qi] = query_bound(StagedPts{s_pts, lo}, rb, re, qi, k);
+        }
+        const float b = query_bound(StagedPts{s_pts, lo}, rb, re, qi, k, sub, live);
+        if (live && sub == 0u) {
+            P.tau_c[qi] = b;
             if ((qi - qb) % (uint32_t)KNN_TQ == 0u) {
                 const uint32_t nch = P.leaf_nch[t];
                 const uint32_t grp = P.leaf_item[t] + ((qi - qb) / (uint32_t)KNN_TQ) * nch;
@@ -663,9 +688,11 @@ __global__ __launch_bounds__(64) void knn_merge_kernel(Plan P, int kk) {
 
 void launch_knn_bound(const Plan& P, int k, int num_cus, hipStream_t st) {
     (void)num_cus;
-    unsigned blocks = (P.n + 255) / 256;
+    unsigned blocks = (P.n + BOUND_Q - 1) / BOUND_Q;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(knn_bound_kernel, dim3(blocks), dim3(256), 0, st, P, (const float4*)P.cand4, k);
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(knn_bound_kernel, dim3(blocks), dim3(BOUND_Q * BOUND_SPLIT), 0, st, P,
+                       (const float4*)P.cand4, k);
 }
 
 size_t knn_lds_bytes(int k, bool pos) {
