@@ -188,6 +188,8 @@ struct Plan {
     uint32_t* nbr;            // [n][k] original indices
     float* nbr_d2;            // [n][k]
     float* r2k;               // [n]
+    float* r2k1;              // [n] d2 of the (k-1)-th neighbour (k >= 2)
+    uint32_t* kidx;           // [n] original index of the k-th neighbour (none: 0xFFFFFFFF)
     float* tau_c;             // [n] per-query upper bound of r^2_K (-1: none)
     double* rho_c;            // [n]
     double* r64_c;            // [n]

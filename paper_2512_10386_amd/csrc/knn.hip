@@ -79,8 +79,8 @@ __device__ __forceinline__ unsigned long long shfl64(unsigned long long v, int s
 
 constexpr int BOUND_MARGIN = 64;   // window reaches this far on each side of a query
 constexpr int BOUND_LEVELS = 10;   // thresholds tau * 2^(-m/2), m = 1..10
-constexpr int BOUND_SPLIT = 4;     // adjacent lanes sharing one query's distances
-constexpr int BOUND_Q = 256;       // queries per block (BOUND_Q * BOUND_SPLIT threads)
+constexpr int BOUND_SPLIT = 8;     // adjacent lanes sharing one query's distances
+constexpr int BOUND_Q = 128;       // queries per block (BOUND_Q * BOUND_SPLIT threads)
 
 // tau: the largest d2 to the k points next to the query in Morton order inside
 // [qb, qe), a run of candidates holding the query; then, over the run's points
@@ -198,7 +198,12 @@ __device__ __forceinline__ void write_final(const Plan& P, uint32_t qi, uint32_t
         const float d = ok ? __uint_as_float((uint32_t)(v >> 32)) : INFINITY;
         P.nbr[(size_t)qi * k + lane] = ok ? (uint32_t)v : NONE32;
         P.nbr_d2[(size_t)qi * k + lane] = d;
-        if (lane == k - 1) P.r2k[qi] = d;
+        // the last two entries again, densely, for the density
+        if (lane == k - 1) {
+            P.r2k[qi] = d;
+            P.kidx[qi] = ok ? (uint32_t)v : NONE32;
+        }
+        if (lane + 2u == k) P.r2k1[qi] = d;
     }
 }
 

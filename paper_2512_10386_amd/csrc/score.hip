@@ -35,32 +35,43 @@ __device__ __forceinline__ double seg_sum(double v, uint32_t kp) {
 
 // One thread per query. The list is sorted by fp32 d2, and fp32 d2 is within
 // ~6e-7 relative of the exact value, so only the neighbours whose fp32 d2 is
-// within 2^-16 of the k-th can hold the FP64 maximum: walk down from the
-// k-th and stop at the first one below that (usually after one or two).
+// within 2^-16 of the k-th can hold the FP64 maximum. Usually that is the
+// k-th alone (the (k-1)-th lies below), read from the dense copies the kNN
+// writes; otherwise walk the list down from the k-th and stop at the first
+// one below.
 __global__ __launch_bounds__(256) void density_kernel(Plan P, const float* __restrict__ xyz, int kk) {
     const uint32_t np1 = P.ctr->n_p1;
     const uint32_t k = (uint32_t)kk;
     for (uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x; qi < np1; qi += gridDim.x * blockDim.x) {
-        const uint32_t* nb = P.nbr + (size_t)qi * k;
-        const float* d2 = P.nbr_d2 + (size_t)qi * k;
+        const uint32_t jk = P.kidx[qi];
         double rho, r64;
-        if (nb[k - 1] == NO_NBR) {
+        if (jk == NO_NBR) {
             rho = 0.0;
             r64 = INFINITY;
         } else {
-            const uint32_t i = __float_as_uint(P.cand4[qi].w);
-            const double xi = xyz[3 * (size_t)i], yi = xyz[3 * (size_t)i + 1], zi = xyz[3 * (size_t)i + 2];
-            const float thr = P.r2k[qi] * (1.0f - 1.0f / 65536.0f);
-            double m2 = 0.0;
-            for (int r = (int)k - 1; r >= 0; --r) {
-                if (d2[r] < thr) break;
-                const uint32_t j = nb[r];
-                if (j >= P.n) continue;
+            // the query's coordinates: cand4 holds bit copies of the input
+            const float4 cq = P.cand4[qi];
+            const double xi = cq.x, yi = cq.y, zi = cq.z;
+            auto d2_to = [&](uint32_t j) -> double {
                 const double dx = (double)xyz[3 * (size_t)j] - xi;
                 const double dy = (double)xyz[3 * (size_t)j + 1] - yi;
                 const double dz = (double)xyz[3 * (size_t)j + 2] - zi;
-                const double v = dx * dx + dy * dy + dz * dz;
-                if (v > m2) m2 = v;
+                return dx * dx + dy * dy + dz * dz;
+            };
+            const float thr = P.r2k[qi] * (1.0f - 1.0f / 65536.0f);
+            double m2 = 0.0;
+            if (k == 1u || P.r2k1[qi] < thr) {
+                if (jk < P.n) m2 = fmax(m2, d2_to(jk));
+            } else {
+                const uint32_t* nb = P.nbr + (size_t)qi * k;
+                const float* d2 = P.nbr_d2 + (size_t)qi * k;
+                for (int r = (int)k - 1; r >= 0; --r) {
+                    if (d2[r] < thr) break;
+                    const uint32_t j = nb[r];
+                    if (j >= P.n) continue;
+                    const double v = d2_to(j);
+                    if (v > m2) m2 = v;
+                }
             }
             r64 = sqrt(m2);
             rho = (double)k / ((4.0 / 3.0) * PI_D * (r64 * r64 * r64));
