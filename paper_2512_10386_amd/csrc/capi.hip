@@ -124,7 +124,7 @@ gdn::Plan make_plan(uint32_t n, uint32_t nf, int k, char* base) {
     P.tau_c = (float*)take(4 * N);
     P.rho_c = (double*)take(8 * N);
     P.r64_c = (double*)take(8 * N);
-    P.afac_c = (double*)take(8 * N);
+    P.afac_c = (double2*)take(16 * N);
     P.p2 = (uint8_t*)take(N);
     P.stage_c = (uint8_t*)take(N);
     P.score_c = (double*)take(8 * N);

@@ -193,7 +193,7 @@ struct Plan {
     float* tau_c;             // [n] per-query upper bound of r^2_K (-1: none)
     double* rho_c;            // [n]
     double* r64_c;            // [n]
-    double* afac_c;           // [n] (rho_i / (rho_med^2 + eps))^(alpha/2)
+    double2* afac_c;          // [n] (rho_i / (rho_med^2 + eps))^(alpha/2), 1 / (2 (sigma r_K,i)^2)
     uint8_t* p2;              // [n]
     uint8_t* stage_c;         // [n] 1 density-removed, 2 score-removed, 3 kept
     double* score_c;          // [n]
@@ -285,6 +285,20 @@ __device__ __forceinline__ uint32_t compact3(uint64_t x) {
 }
 __device__ __forceinline__ uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
     return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
+// Frame holding position j of a batch: frames are contiguous runs both of
+// the input and of the sorted order (the frame id is the most significant
+// sort digit), so the frame is the last f with foff[f] <= j (empty frames
+// share their end with the next start). foff is tiny and stays in cache.
+__device__ __forceinline__ uint32_t frame_of(const uint32_t* foff, uint32_t nf, uint32_t j) {
+    uint32_t lo = 0, hi = nf;
+    while (hi - lo > 1u) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (foff[mid] <= j) lo = mid;
+        else hi = mid;
+    }
+    return lo;
 }
 
 // Deepest octree level whose cell prefixes the sorted key order resolves

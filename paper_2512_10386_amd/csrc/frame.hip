@@ -83,18 +83,6 @@ void launch_frames(const Plan& P, const int64_t* frame_off, hipStream_t st) {
     hipLaunchKernelGGL(frames_kernel, dim3(1), dim3(256), 0, st, frame_off, P.nf, P.n, P.foff, P.ctr);
 }
 
-// Frame of point (original or sorted position) i: the last f with
-// foff[f] <= i, over frames [0, nf) (empty frames never match).
-__device__ __forceinline__ uint32_t frame_of(const uint32_t* foff, uint32_t nf, uint32_t i) {
-    uint32_t lo = 0, hi = nf;  // answer in [lo, hi)
-    while (hi - lo > 1u) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (foff[mid] <= i) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
 // ---------------------------------------------------------------- bbox
 
 // Waves take chunks of BBOX_CHUNK consecutive points (coalesced). A chunk
@@ -313,8 +301,9 @@ void launch_morton(const Plan& P, const Params& prm, const float* xyz, hipStream
 // One stable LSD pass over digit `pass` (8 bits) in the onesweep style: local
 // ranks by wave-level digit matching, digit offsets of earlier tiles by
 // decoupled look-back (bounded waits), global digit bases from the histogram.
-// Passes past the key's 8 take the digit from the frame id of the payload
-// (the original index), so a batch ends sorted by (frame, key, index).
+// Passes past the key's 8 take the digit from the frame of the payload (the
+// original index, found in the frame offsets), so a batch ends sorted by
+// (frame, key, index).
 // Key passes below SORT_SHORT_FIRST return at once unless the Morton kernel
 // asked for the full sort (the order is then by (frame, key bits 32..62,
 // index), which resolves every cell of the octree).
@@ -325,8 +314,8 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
                                                                 uint32_t* __restrict__ vout, uint32_t n,
                                                                 int pass, const uint32_t* __restrict__ hist,
                                                                 uint32_t* status, uint32_t* tile_ctr,
-                                                                uint32_t* dev_status, const uint32_t* __restrict__ fid,
-                                                                const uint32_t* __restrict__ deep) {
+                                                                uint32_t* dev_status, const uint32_t* __restrict__ foff,
+                                                                uint32_t nf, const uint32_t* __restrict__ deep) {
     if (pass < SORT_SHORT_FIRST && *deep == 0u) return;
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_w[SORT_BLOCK / 64][256];
@@ -349,7 +338,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
         key[i] = ok ? kin[pos] : 0ull;
         val[i] = ok ? vin[pos] : 0u;
         const uint32_t d = pass < SORT_PASSES ? (uint32_t)((key[i] >> shift) & 255u)
-                                              : (fid[ok ? val[i] : 0u] >> (8 * (pass - SORT_PASSES))) & 255u;
+                                              : (frame_of(foff, nf, ok ? val[i] : 0u) >> (8 * (pass - SORT_PASSES))) & 255u;
         dig[i] = ok ? d : 256u;
     }
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -457,7 +446,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
             const uint64_t kk = s_k[p];
             const uint32_t vv = s_v[p];
             const uint32_t d = pass < SORT_PASSES ? (uint32_t)((kk >> shift) & 255u)
-                                                  : (fid[vv] >> (8 * (pass - SORT_PASSES))) & 255u;
+                                                  : (frame_of(foff, nf, vv) >> (8 * (pass - SORT_PASSES))) & 255u;
             const uint32_t o = s_base[d] + (p - s_toff[d]);
             if (o < n) {  // always true unless a look-back wait expired
                 kout[o] = kk;
@@ -492,7 +481,7 @@ void launch_sort(const Plan& P, hipStream_t st) {
         hipLaunchKernelGGL(kern, dim3(P.sort_tiles), dim3(SORT_BLOCK), 0, st, kin, vin, kout, vout,
                            P.n, (int)pass, P.sort_hist + 256 * pass,
                            P.sort_status + (size_t)pass * P.sort_tiles * 256, &P.ctr->sort_tile_ctr[pass],
-                           &P.ctr->status, (const uint32_t*)P.fid, (const uint32_t*)&P.ctr->sort_deep);
+                           &P.ctr->status, (const uint32_t*)P.foff, P.nf, (const uint32_t*)&P.ctr->sort_deep);
         const uint64_t* tk = kout;
         const uint32_t* tv = vout;
         kout = (uint64_t*)kin;

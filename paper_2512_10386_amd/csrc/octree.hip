@@ -23,7 +23,7 @@ __device__ __forceinline__ int common_digits(uint64_t a, uint64_t b) {
 
 // Frame of sorted position j (frames keep their input ranges after the sort).
 __device__ __forceinline__ uint32_t frame_of_sorted(const Plan& P, uint32_t j) {
-    return P.nf > 1 ? P.fid[P.idx_a[j]] : 0u;
+    return P.nf > 1 ? frame_of(P.foff, P.nf, j) : 0u;
 }
 
 // Boundary test of sorted position j inside its frame [fs, fe): the frame's

@@ -278,7 +278,8 @@ __global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params p
             const uint32_t qi = qb + i;
             const bool insufficient = P.nbr[(size_t)qi * k + (k - 1)] == NO_NBR;
             P.p2[qi] = (!insufficient && P.r2k[qi] <= cut) ? 1 : 0;
-            P.afac_c[qi] = pow(P.rho_c[qi] / den, ha);
+            const double sr = prm.sigma * P.r64_c[qi];
+            P.afac_c[qi] = make_double2(pow(P.rho_c[qi] / den, ha), 1.0 / (2.0 * sr * sr));
             // rho_j^(alpha/2) of Eq. 17's factored density weight, by original index
             const float4 c = P.cand4[qi];
             P.rec_o[__float_as_uint(c.w)] = NbrRec{c, pow(P.rho_c[qi], ha), 0.0};
@@ -349,7 +350,8 @@ __global__ __launch_bounds__(256) void leaf_select_small_kernel(Plan P, Params p
             const bool insufficient = P.nbr[(size_t)qi * k + (k - 1)] == NO_NBR;
             const double rho = P.rho_c[qi];
             P.p2[qi] = (!insufficient && P.r2k[qi] <= cut) ? 1 : 0;
-            P.afac_c[qi] = pow(rho / den, ha);
+            const double sr = prm.sigma * P.r64_c[qi];
+            P.afac_c[qi] = make_double2(pow(rho / den, ha), 1.0 / (2.0 * sr * sr));
             const float4 c = P.cand4[qi];
             P.rec_o[__float_as_uint(c.w)] = NbrRec{c, pow(rho, ha), 0.0};
         }
@@ -374,11 +376,13 @@ void launch_leaf_select(const Plan& P, const Params& prm, hipStream_t st) {
 //
 // F_i = sum over N_K(i) of (rho_i rho_j / (rho_med^2 + eps))^(alpha/2)
 //       * exp(-d_ij^2 / (2 (sigma r_K,i)^2)) / (d_ij^2 + eps), in FP64, with the
-// density weight factored as afac_i * rho_j^(alpha/2). A neighbour at d = 0
-// gets the Gaussian factor 1 (also when r_K,i = 0). The k terms are summed by
-// a fixed pairwise tree (lane r holds term r), not left to right.
+// density weight factored as afac_i * rho_j^(alpha/2) and the Gaussian
+// exponent as d^2 * c_i, c_i = 1 / (2 (sigma r_K,i)^2), both per query from the
+// select kernel. A neighbour at d = 0 gets the Gaussian factor 1 (also when
+// r_K,i = 0). The k terms are summed by a fixed pairwise tree (lane r holds
+// term r), not left to right.
 
-__global__ __launch_bounds__(256) void score_kernel(Plan P, int kk, double sigma, double eps, double gamma) {
+__global__ __launch_bounds__(256) void score_kernel(Plan P, int kk, double eps, double gamma) {
     const uint32_t np1 = P.ctr->n_p1;
     const uint32_t k = (uint32_t)kk, kp = pow2_at_least(k), qpw = 64u / kp;
     const uint32_t lane = threadIdx.x & 63u, seg = lane / kp, r = lane % kp;
@@ -394,13 +398,13 @@ __global__ __launch_bounds__(256) void score_kernel(Plan P, int kk, double sigma
                 // (both bit copies of the input coordinates)
                 const float4 a = P.cand4[qi];
                 const NbrRec R = P.rec_o[j];
-                const double sr = sigma * P.r64_c[qi];
                 const double dx = (double)R.p.x - (double)a.x;
                 const double dy = (double)R.p.y - (double)a.y;
                 const double dz = (double)R.p.z - (double)a.z;
                 const double d2 = dx * dx + dy * dy + dz * dz;
-                const double w_den = P.afac_c[qi] * R.gpow;
-                const double w_dis = (d2 == 0.0) ? 1.0 : exp(-d2 / (2.0 * sr * sr));
+                const double2 af = P.afac_c[qi];
+                const double w_den = af.x * R.gpow;
+                const double w_dis = (d2 == 0.0) ? 1.0 : exp(-(d2 * af.y));
                 const double kern = gamma == 2.0 ? 1.0 / (d2 + eps) : pow(d2 + eps, -gamma / 2.0);
                 term = w_den * w_dis * kern;
             }
@@ -417,7 +421,7 @@ void launch_score(const Plan& P, const Params& prm, hipStream_t st) {
     unsigned blocks = (unsigned)((waves + 3) / 4);
     if (blocks > 8192) blocks = 8192;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(score_kernel, dim3(blocks), dim3(256), 0, st, P, prm.k, prm.sigma, prm.eps, prm.gamma);
+    hipLaunchKernelGGL(score_kernel, dim3(blocks), dim3(256), 0, st, P, prm.k, prm.eps, prm.gamma);
 }
 
 // ---------------------------------------------------------------- top-lambda
