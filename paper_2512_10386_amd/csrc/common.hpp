@@ -187,9 +187,8 @@ struct Plan {
     uint32_t* cand_leaf;      // [n]
     uint32_t* nbr;            // [n][k] original indices
     float* nbr_d2;            // [n][k]
-    float* r2k;               // [n]
-    float* r2k1;              // [n] d2 of the (k-1)-th neighbour (k >= 2)
-    uint32_t* kidx;           // [n] original index of the k-th neighbour (none: 0xFFFFFFFF)
+    float* r2k;               // [n] (written by the density kernel from krec)
+    uint4* krec;              // [n] k-th neighbour (none: 0xFFFFFFFF), fp32 bits of the (k-1)-th and k-th d2
     float* tau_c;             // [n] per-query upper bound of r^2_K (-1: none)
     double* rho_c;            // [n]
     double* r64_c;            // [n]

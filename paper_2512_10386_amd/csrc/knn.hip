@@ -193,17 +193,14 @@ __global__ __launch_bounds__(BOUND_Q * BOUND_SPLIT) void knn_bound_kernel(Plan P
 
 __device__ __forceinline__ void write_final(const Plan& P, uint32_t qi, uint32_t k, uint32_t lane,
                                             unsigned long long v) {
+    const bool ok = lane < k && real_entry(v);
+    const float d = ok ? __uint_as_float((uint32_t)(v >> 32)) : INFINITY;
+    const float d1 = __shfl(d, k >= 2u ? (int)k - 2 : 0, 64);
     if (lane < k) {
-        const bool ok = real_entry(v);
-        const float d = ok ? __uint_as_float((uint32_t)(v >> 32)) : INFINITY;
         P.nbr[(size_t)qi * k + lane] = ok ? (uint32_t)v : NONE32;
         P.nbr_d2[(size_t)qi * k + lane] = d;
-        // the last two entries again, densely, for the density
-        if (lane == k - 1) {
-            P.r2k[qi] = d;
-            P.kidx[qi] = ok ? (uint32_t)v : NONE32;
-        }
-        if (lane + 2u == k) P.r2k1[qi] = d;
+        // the k-th entry and the (k-1)-th distance again, densely, for the density
+        if (lane == k - 1) P.krec[qi] = make_uint4(ok ? (uint32_t)v : NONE32, __float_as_uint(d1), __float_as_uint(d), 0u);
     }
 }
 

@@ -36,14 +36,17 @@ __device__ __forceinline__ double seg_sum(double v, uint32_t kp) {
 // One thread per query. The list is sorted by fp32 d2, and fp32 d2 is within
 // ~6e-7 relative of the exact value, so only the neighbours whose fp32 d2 is
 // within 2^-16 of the k-th can hold the FP64 maximum. Usually that is the
-// k-th alone (the (k-1)-th lies below), read from the dense copies the kNN
+// k-th alone (the (k-1)-th lies below), read from the dense record the kNN
 // writes; otherwise walk the list down from the k-th and stop at the first
-// one below.
+// one below. Also stores r^2_K densely.
 __global__ __launch_bounds__(256) void density_kernel(Plan P, const float* __restrict__ xyz, int kk) {
     const uint32_t np1 = P.ctr->n_p1;
     const uint32_t k = (uint32_t)kk;
     for (uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x; qi < np1; qi += gridDim.x * blockDim.x) {
-        const uint32_t jk = P.kidx[qi];
+        const uint4 kr = P.krec[qi];
+        const uint32_t jk = kr.x;
+        const float r2 = __uint_as_float(kr.z);
+        P.r2k[qi] = r2;
         double rho, r64;
         if (jk == NO_NBR) {
             rho = 0.0;
@@ -58,9 +61,9 @@ __global__ __launch_bounds__(256) void density_kernel(Plan P, const float* __res
                 const double dz = (double)xyz[3 * (size_t)j + 2] - zi;
                 return dx * dx + dy * dy + dz * dz;
             };
-            const float thr = P.r2k[qi] * (1.0f - 1.0f / 65536.0f);
+            const float thr = r2 * (1.0f - 1.0f / 65536.0f);
             double m2 = 0.0;
-            if (k == 1u || P.r2k1[qi] < thr) {
+            if (k == 1u || __uint_as_float(kr.y) < thr) {
                 if (jk < P.n) m2 = fmax(m2, d2_to(jk));
             } else {
                 const uint32_t* nb = P.nbr + (size_t)qi * k;
