@@ -141,12 +141,124 @@ __device__ __forceinline__ uint64_t vox_key(float4 p, float mx_, float my_, floa
     return k;
 }
 
+// Leaf voxel size (Eq. 10, 11) from its fp32 bbox: h = beta * cbrt(V / nt)
+// rounded to fp32, 0 for a flat or degenerate leaf.
+__device__ __forceinline__ float leaf_voxel_size(const float* lo, const float* hi, uint32_t nt, double beta) {
+    double H[3];
+    for (int a = 0; a < 3; ++a) H[a] = (double)hi[a] - (double)lo[a];
+    const double V = (H[0] * H[1]) * H[2];
+    float h32 = (float)(beta * cbrt(V / (double)nt));
+    if (!(h32 > 0.0f) || !isfinite(h32)) h32 = 0.0f;
+    return h32;
+}
+
+// Small leaves (at most VOX_WAVE_MAX points) of large batches: one wave per
+// leaf with its own LDS table, no block barriers; every lane computes the
+// leaf's h (uniform) instead of one thread behind two barriers. Same
+// expressions and hash as voxel_kernel, so the counts are identical.
+constexpr uint32_t VOX_WAVE_MAX = 256;
+constexpr uint32_t VOX_WAVE_SLOTS = 2 * VOX_WAVE_MAX;
+constexpr uint32_t VOX_WAVE_MIN_N = 1u << 20;
+
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(256) void voxel_wave_kernel(Plan P, double beta, uint32_t nv) {
+    __shared__ unsigned long long s_key[4][VOX_WAVE_SLOTS];
+    __shared__ uint32_t s_cnt[4][VOX_WAVE_SLOTS];
+    constexpr unsigned long long EMPTY = ~0ull;
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t nl = P.ctr->n_leaves;
+    unsigned long long* tk = s_key[w];
+    uint32_t* tc = s_cnt[w];
+    for (uint32_t t = wid; t < nl; t += nw) {
+        const uint32_t b = P.leaf_begin[t], e = P.leaf_begin[t + 1], nt = e - b;
+        if (nt > VOX_WAVE_MAX) continue;
+        float4 p[VOX_WAVE_MAX / 64];
+        float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+        for (uint32_t r = 0; r < VOX_WAVE_MAX / 64; ++r) {
+            const uint32_t s = b + r * 64u + lane;
+            if (s < e) {
+                p[r] = P.pos4[s];
+                mn[0] = fminf(mn[0], p[r].x); mx[0] = fmaxf(mx[0], p[r].x);
+                mn[1] = fminf(mn[1], p[r].y); mx[1] = fmaxf(mx[1], p[r].y);
+                mn[2] = fminf(mn[2], p[r].z); mx[2] = fmaxf(mx[2], p[r].z);
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                mn[a] = fminf(mn[a], __shfl_xor(mn[a], o, 64));
+                mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], o, 64));
+            }
+        const float h32 = leaf_voxel_size(mn, mx, nt, beta);
+        if (lane == 0u) P.leaf_h[t] = h32;
+        if (h32 == 0.0f) {
+            for (uint32_t s = b + lane; s < e; s += 64u) {
+                P.occ[s] = nt;
+                P.p1[s] = nt >= nv;
+            }
+            continue;
+        }
+        const double h = (double)h32;
+        uint32_t slots = 64u;
+        while (slots < 2u * nt) slots <<= 1;
+        for (uint32_t i = lane; i < slots; i += 64u) {
+            tk[i] = EMPTY;
+            tc[i] = 0u;
+        }
+        wave_lds_fence();
+        unsigned long long key[VOX_WAVE_MAX / 64];
+#pragma unroll
+        for (uint32_t r = 0; r < VOX_WAVE_MAX / 64; ++r) {
+            const uint32_t s = b + r * 64u + lane;
+            if (s < e) {
+                key[r] = vox_key(p[r], mn[0], mn[1], mn[2], h);
+                uint32_t slot = vox_hash(key[r]) & (slots - 1u);
+                for (uint32_t probe = 0; probe < slots; ++probe) {
+                    const unsigned long long prev = atomicCAS(&tk[slot], EMPTY, key[r]);
+                    if (prev == EMPTY || prev == key[r]) {
+                        atomicAdd(&tc[slot], 1u);
+                        break;
+                    }
+                    slot = (slot + 1 == slots) ? 0u : slot + 1;
+                }
+            }
+        }
+        wave_lds_fence();
+#pragma unroll
+        for (uint32_t r = 0; r < VOX_WAVE_MAX / 64; ++r) {
+            const uint32_t s = b + r * 64u + lane;
+            if (s < e) {
+                uint32_t slot = vox_hash(key[r]) & (slots - 1u);
+                uint32_t c = 0;
+                for (uint32_t probe = 0; probe < slots; ++probe) {
+                    if (tk[slot] == key[r]) {
+                        c = tc[slot];
+                        break;
+                    }
+                    slot = (slot + 1 == slots) ? 0u : slot + 1;
+                }
+                P.occ[s] = c;
+                P.p1[s] = c >= nv;
+            }
+        }
+        wave_lds_fence();
+    }
+}
+
 // SLOTS: LDS hash capacity, picked from the leaf cap so that small-leaf
 // octrees keep many workgroups per CU; leaves above SLOTS/2 points (only
 // over-full leaves at the depth limit, or caps above 2048) use the global
 // per-leaf region.
 template <int SLOTS>
-__global__ __launch_bounds__(VOX_BLOCK) void voxel_kernel(Plan P, double beta, uint32_t nv) {
+__global__ __launch_bounds__(VOX_BLOCK) void voxel_kernel(Plan P, double beta, uint32_t nv, bool skip_small) {
     __shared__ unsigned long long s_key[SLOTS];
     __shared__ uint32_t s_cnt[SLOTS];
     __shared__ float s_red[6][VOX_BLOCK / 64];
@@ -157,6 +269,7 @@ __global__ __launch_bounds__(VOX_BLOCK) void voxel_kernel(Plan P, double beta, u
     constexpr unsigned long long EMPTY = ~0ull;
     for (uint32_t t = blockIdx.x; t < nl; t += gridDim.x) {
         const uint32_t b = P.leaf_begin[t], e = P.leaf_begin[t + 1], nt = e - b;
+        if (skip_small && nt <= VOX_WAVE_MAX) continue;  // voxel_wave_kernel
         float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
         for (uint32_t s = b + tid; s < e; s += VOX_BLOCK) {
             float4 p = P.pos4[s];
@@ -175,16 +288,17 @@ __global__ __launch_bounds__(VOX_BLOCK) void voxel_kernel(Plan P, double beta, u
             for (int a = 0; a < 3; ++a) { s_red[a][wave] = mn[a]; s_red[3 + a][wave] = mx[a]; }
         __syncthreads();
         if (tid == 0) {
-            double H[3];
+            float lo[3], hi[3];
             for (int a = 0; a < 3; ++a) {
-                float lo = s_red[a][0], hi = s_red[3 + a][0];
-                for (int w = 1; w < VOX_BLOCK / 64; ++w) { lo = fminf(lo, s_red[a][w]); hi = fmaxf(hi, s_red[3 + a][w]); }
-                s_mn[a] = lo;
-                H[a] = (double)hi - (double)lo;
+                lo[a] = s_red[a][0];
+                hi[a] = s_red[3 + a][0];
+                for (int w = 1; w < VOX_BLOCK / 64; ++w) {
+                    lo[a] = fminf(lo[a], s_red[a][w]);
+                    hi[a] = fmaxf(hi[a], s_red[3 + a][w]);
+                }
+                s_mn[a] = lo[a];
             }
-            double V = (H[0] * H[1]) * H[2];
-            float h32 = (float)(beta * cbrt(V / (double)nt));
-            if (!(h32 > 0.0f) || !isfinite(h32)) h32 = 0.0f;
+            const float h32 = leaf_voxel_size(lo, hi, nt, beta);
             s_h = h32;
             P.leaf_h[t] = h32;
         }
@@ -240,15 +354,22 @@ __global__ __launch_bounds__(VOX_BLOCK) void voxel_kernel(Plan P, double beta, u
 }
 
 void launch_voxel(const Plan& P, const Params& prm, hipStream_t st) {
+    // the wave path pays off for the many small leaves of large batches
+    const bool small = P.n > VOX_WAVE_MIN_N;
+    if (small) {
+        unsigned wb = (P.n / 128 + 3) / 4;
+        if (wb > 8192) wb = 8192;
+        hipLaunchKernelGGL(voxel_wave_kernel, dim3(wb), dim3(256), 0, st, P, prm.beta, (uint32_t)prm.min_vox_count);
+    }
     unsigned blocks = P.n / 128;
-    if (blocks > 16384) blocks = 16384;
+    if (blocks > (small ? 2048u : 16384u)) blocks = small ? 2048u : 16384u;  // small: only the big leaves remain
     if (blocks == 0) blocks = 1;
     if (prm.leaf_cap <= 256)
         hipLaunchKernelGGL(voxel_kernel<512>, dim3(blocks), dim3(VOX_BLOCK), 0, st, P, prm.beta,
-                           (uint32_t)prm.min_vox_count);
+                           (uint32_t)prm.min_vox_count, small);
     else
         hipLaunchKernelGGL(voxel_kernel<VOX_LDS_SLOTS>, dim3(blocks), dim3(VOX_BLOCK), 0, st, P, prm.beta,
-                           (uint32_t)prm.min_vox_count);
+                           (uint32_t)prm.min_vox_count, small);
 }
 
 // ---------------------------------------------------------------- P1 compaction
