@@ -3,6 +3,7 @@
 // kNN work plan.
 #include "kernels.hpp"
 #include "scan.hpp"
+#include "wave.hpp"
 
 namespace gdn {
 
@@ -159,12 +160,6 @@ __device__ __forceinline__ float leaf_voxel_size(const float* lo, const float* h
 constexpr uint32_t VOX_WAVE_MAX = 256;
 constexpr uint32_t VOX_WAVE_SLOTS = 2 * VOX_WAVE_MAX;
 constexpr uint32_t VOX_WAVE_MIN_N = 1u << 20;
-
-__device__ __forceinline__ void wave_lds_fence() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __global__ __launch_bounds__(256) void voxel_wave_kernel(Plan P, double beta, uint32_t nv) {
     __shared__ unsigned long long s_key[4][VOX_WAVE_SLOTS];

@@ -293,15 +293,17 @@ __global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params p
 }
 
 // Leaves with at most SMALL_LEAF (= 256) P1 points: one wave each, no block
-// barriers. The values (point i of the leaf in register i / 64 of lane
-// i % 64; padding ~0) are sorted descending across the wave by a bitonic
-// network (DPP exchanges; 64 values need one register, up to 256 four), and
-// ranks are read from the sorted order.
+// barriers. The values sit as point i of the leaf in register i / 64 of lane
+// i % 64 (padding ~0). Up to 64 values are sorted descending across the wave
+// by a bitonic network (DPP exchanges) and ranks read from the sorted order;
+// larger leaves use the wave radix select (fewer instructions than a
+// 256-value network).
 struct WaveVals {
     unsigned long long v[4];
 };
 
-__device__ __forceinline__ unsigned long long wave_rank_value(WaveVals w, uint32_t n1, uint32_t lane, uint32_t r) {
+__device__ __forceinline__ unsigned long long wave_rank_value(WaveVals w, uint32_t n1, uint32_t lane, uint32_t r,
+                                                              uint32_t* hist) {
     // ascending rank r (0-based, r < n1) of the n1 values; the padding sorts first
     if (n1 <= 64u) {
         const unsigned long long s = sort64_desc(w.v[0], lane);
@@ -309,11 +311,32 @@ __device__ __forceinline__ unsigned long long wave_rank_value(WaveVals w, uint32
         const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(s >> 32), 63 - (int)r);
         return ((unsigned long long)hi << 32) | lo;
     }
-    sort256_desc(w.v, lane);
-    return read_elem256(w.v, 255u - r);
+    return wave_select(w.v, n1, r, lane, hist);
+}
+
+// Given a = the value of ascending rank r, the value of rank r + 1: a again
+// if more than r + 1 values are <= a, else the smallest value above a.
+__device__ __forceinline__ unsigned long long wave_next_rank(const WaveVals& w, uint32_t n1, uint32_t lane, uint32_t r,
+                                                             unsigned long long a) {
+    uint32_t le = 0;
+    unsigned long long mn = ~0ull;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const bool in = (uint32_t)j * 64u + lane < n1;
+        le += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in && w.v[j] <= a));
+        if (in && w.v[j] > a && w.v[j] < mn) mn = w.v[j];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long x = (unsigned long long)__shfl_xor((long long)mn, off, 64);
+        mn = x < mn ? x : mn;
+    }
+    return le > r + 1u ? a : mn;
 }
 
 __global__ __launch_bounds__(256) void leaf_select_small_kernel(Plan P, Params prm) {
+    __shared__ uint32_t s_hist[4][256];
+    uint32_t* const hist = s_hist[threadIdx.x >> 6];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
     const uint32_t nl = P.ctr->n_leaves;
@@ -338,14 +361,14 @@ __global__ __launch_bounds__(256) void leaf_select_small_kernel(Plan P, Params p
         if (cd < 1.0) cd = 1.0;
         if (cd > (double)n1) cd = (double)n1;
         const uint32_t c = (uint32_t)cd;
-        const float cut = __uint_as_float((uint32_t)wave_rank_value(r2v, n1, lane, n1 - c));
+        const float cut = __uint_as_float((uint32_t)wave_rank_value(r2v, n1, lane, n1 - c, hist));
         double med;
         if (n1 & 1u) {
-            med = __longlong_as_double((long long)wave_rank_value(rhov, n1, lane, (n1 - 1) / 2));
+            med = __longlong_as_double((long long)wave_rank_value(rhov, n1, lane, (n1 - 1) / 2, hist));
         } else {
-            const double a = __longlong_as_double((long long)wave_rank_value(rhov, n1, lane, n1 / 2 - 1));
-            const double b = __longlong_as_double((long long)wave_rank_value(rhov, n1, lane, n1 / 2));
-            med = (a + b) / 2.0;
+            const unsigned long long ab = wave_rank_value(rhov, n1, lane, n1 / 2 - 1, hist);
+            const unsigned long long bb = wave_next_rank(rhov, n1, lane, n1 / 2 - 1, ab);
+            med = (__longlong_as_double((long long)ab) + __longlong_as_double((long long)bb)) / 2.0;
         }
         const double den = med * med + prm.eps;
         for (uint32_t i = lane; i < n1; i += 64u) {
@@ -530,6 +553,8 @@ __global__ __launch_bounds__(SEL_BLOCK) void topl_kernel(Plan P, double lambda, 
 // Small leaves: theta = the m-th largest key from a wave sort; keys above it
 // are kept, and among the keys equal to it the `need` smallest indices.
 __global__ __launch_bounds__(256) void topl_small_kernel(Plan P, double lambda) {
+    __shared__ uint32_t s_hist[4][256];
+    uint32_t* const hist = s_hist[threadIdx.x >> 6];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
     const uint32_t nl = P.ctr->n_leaves;
@@ -565,8 +590,7 @@ __global__ __launch_bounds__(256) void topl_small_kernel(Plan P, double lambda) 
                 const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(srt.v[0] >> 32), (int)m - 1);
                 theta = ((unsigned long long)hi << 32) | lo;
             } else {
-                sort256_desc(srt.v, lane);
-                theta = read_elem256(srt.v, m - 1);
+                theta = wave_select(kv.v, n1, n1 - m, lane, hist);  // the m-th largest
             }
             uint32_t greater = 0, equal = 0;
 #pragma unroll

@@ -192,6 +192,94 @@ __device__ __forceinline__ void sort256_desc(unsigned long long (&v)[4], uint32_
     sort256_stage<512>(v, lane);  // final merge: every block descending
 }
 
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Value of ascending rank r (r < n) among the n <= 256 keys v[j] of elements
+// j * 64 + lane < n (the rest are ignored). Radix select: the bits common to
+// all keys are fixed first (a wave AND / OR), then MSD digits of up to 8 bits
+// are counted in `hist` (this wave's 256 LDS words) from the highest
+// differing bit down; once the chosen bin holds one key, that key is the
+// answer. Whole wave, uniform arguments.
+__device__ __forceinline__ unsigned long long wave_select(const unsigned long long (&v)[4], uint32_t n, uint32_t r,
+                                                          uint32_t lane, uint32_t* hist) {
+    unsigned long long a = ~0ull, o = 0ull;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if ((uint32_t)j * 64u + lane < n) {
+            a &= v[j];
+            o |= v[j];
+        }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a &= (unsigned long long)__shfl_xor((long long)a, off, 64);
+        o |= (unsigned long long)__shfl_xor((long long)o, off, 64);
+    }
+    if (a == o) return a;
+    int top = 63 - __builtin_clzll(a ^ o);
+    unsigned long long mask = top >= 63 ? 0ull : (~0ull << (top + 1));
+    unsigned long long prefix = a & mask;
+    while (true) {
+        const int lo = top >= 7 ? top - 7 : 0;
+        const uint32_t dm = (2u << (top - lo)) - 1u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) hist[(uint32_t)q * 64u + lane] = 0u;
+        wave_lds_fence();
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if ((uint32_t)j * 64u + lane < n && (v[j] & mask) == prefix)
+                atomicAdd(&hist[(uint32_t)(v[j] >> lo) & dm], 1u);
+        wave_lds_fence();
+        const uint32_t h0 = hist[4u * lane], h1 = hist[4u * lane + 1u], h2 = hist[4u * lane + 2u],
+                       h3 = hist[4u * lane + 3u];
+        const uint32_t s = h0 + h1 + h2 + h3;
+        const uint32_t inc = wave_incl_scan(s);
+        const uint32_t ex = inc - s;
+        uint32_t acc = ex, b = 4u * lane, cnt = h0;
+        if (r >= acc + h0) {
+            acc += h0;
+            ++b;
+            cnt = h1;
+            if (r >= acc + h1) {
+                acc += h1;
+                ++b;
+                cnt = h2;
+                if (r >= acc + h2) {
+                    acc += h2;
+                    ++b;
+                    cnt = h3;
+                }
+            }
+        }
+        const int L = __ffsll((long long)__builtin_amdgcn_ballot_w64(ex <= r && r < inc)) - 1;
+        b = (uint32_t)__builtin_amdgcn_readlane((int)b, L);
+        acc = (uint32_t)__builtin_amdgcn_readlane((int)acc, L);
+        cnt = (uint32_t)__builtin_amdgcn_readlane((int)cnt, L);
+        wave_lds_fence();  // every lane has read hist before the next pass clears it
+        r -= acc;
+        prefix |= (unsigned long long)b << lo;
+        mask |= (unsigned long long)dm << lo;
+        if (lo == 0) return prefix;
+        if (cnt == 1u) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const unsigned long long m =
+                    __builtin_amdgcn_ballot_w64((uint32_t)j * 64u + lane < n && (v[j] & mask) == prefix);
+                if (m) {
+                    const int l = __ffsll((long long)m) - 1;
+                    const uint32_t x = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v[j], l);
+                    const uint32_t y = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v[j] >> 32), l);
+                    return ((unsigned long long)y << 32) | x;
+                }
+            }
+        }
+        top = lo - 1;
+    }
+}
+
 // Element e of a four-per-lane array (e uniform).
 __device__ __forceinline__ unsigned long long read_elem256(const unsigned long long (&v)[4], uint32_t e) {
     const uint32_t j = e >> 6;
