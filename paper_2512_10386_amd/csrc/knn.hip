@@ -204,12 +204,6 @@ __device__ __forceinline__ void write_final(const Plan& P, uint32_t qi, uint32_t
     }
 }
 
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Distance bound of a list whose k-th key is v: +inf while the list holds
 // fewer than k keys.
 __device__ __forceinline__ float bound_of(uint32_t hi) {
@@ -256,14 +250,14 @@ __device__ __forceinline__ float flush(unsigned long long* __restrict__ lst,
                                        const typename Pending<POS>::T* __restrict__ pend, uint32_t cnt,
                                        uint32_t lane, uint32_t k, unsigned long long selfkey,
                                        const float4* __restrict__ cand4, float4 q) {
-    wave_lds_sync();
+    wave_lds_fence();
     unsigned long long v = lane < cnt ? pending_key<POS>(cand4, pend, lane, q) : KEY_EMPTY;
     if (v == selfkey) v = KEY_EMPTY;
     const unsigned long long L = lane < k ? lst[lane] : KEY_EMPTY;
     v = sort64_desc(v, lane);
     v = merge64_asc(L < v ? L : v, lane);
     if (lane < k) lst[lane] = v;
-    wave_lds_sync();
+    wave_lds_fence();
     return bound_of((uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)k - 1));
 }
 
@@ -279,7 +273,7 @@ __device__ __forceinline__ void flush_half(unsigned long long* __restrict__ lst0
                                            uint32_t cnt1, unsigned long long self1, float4 q1, bool two,
                                            uint32_t lane, uint32_t k, const float4* __restrict__ cand4, float* b0,
                                            float* b1) {
-    wave_lds_sync();
+    wave_lds_fence();
     const bool up = lane >= 32u;
     const uint32_t h = lane & 31u;
     const bool act = !up || two;
@@ -292,7 +286,7 @@ __device__ __forceinline__ void flush_half(unsigned long long* __restrict__ lst0
     v = sort32x2_desc(v, lane);
     v = merge32x2_asc(L < v ? L : v, lane);
     if (act && h < k) lst[h] = v;
-    wave_lds_sync();
+    wave_lds_fence();
     const uint32_t hi = (uint32_t)(v >> 32);
     *b0 = bound_of((uint32_t)__builtin_amdgcn_readlane((int)hi, (int)k - 1));
     *b1 = bound_of((uint32_t)__builtin_amdgcn_readlane((int)hi, 32 + (int)k - 1));
@@ -368,7 +362,7 @@ __global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restric
             const float tb = P.tau_c[w.q0 + j];
             if (lane < k) s_list[j * k + lane] = tb >= 0.0f ? make_key(tb, NONE32) : KEY_EMPTY;
         }
-        wave_lds_sync();
+        wave_lds_fence();
 
         const uint32_t c_lo = w.chunk * cc;
         const uint32_t c_hi = min(ncand, c_lo + cc);
@@ -579,7 +573,7 @@ __global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restric
                 write_final(P, w.q0 + j, k, lane, v);
             }
         }
-        wave_lds_sync();
+        wave_lds_fence();
         it = n_items;  // claim the next one
     }
 }
@@ -631,7 +625,7 @@ __global__ __launch_bounds__(64) void knn_merge_kernel(Plan P, int kk) {
             }
         }
         for (uint32_t j = 0; j < qn; ++j) s_lst[j * 64u + lane] = KEY_EMPTY;
-        wave_lds_sync();
+        wave_lds_fence();
         uint32_t cm = 0;  // lane j: contributing chunks of query j
         if (lane < qn) {
             unsigned long long B = KEY_EMPTY;
@@ -677,14 +671,14 @@ __global__ __launch_bounds__(64) void knn_merge_kernel(Plan P, int kk) {
                 const unsigned long long rv = shfl64(pv[b], 63 - (int)lane);  // descending
                 const unsigned long long v = merge64_asc(L < rv ? L : rv, lane);
                 if (lane < k) lst[lane] = v;
-                wave_lds_sync();
+                wave_lds_fence();
             }
         }
         for (uint32_t j = 0; j < qn; ++j) {
             const unsigned long long v = lane < k ? s_lst[j * 64u + lane] : KEY_EMPTY;
             write_final(P, w.q0 + j, k, lane, v);
         }
-        wave_lds_sync();
+        wave_lds_fence();
     }
 }
 

@@ -1,6 +1,6 @@
-// Wave-level (64-lane) exchange helpers for gfx950: lane ^ M exchanges
-// without LDS, bitonic sorts and merges of one 64-bit key per lane, and
-// min / max reductions.
+// Wave-level (64-lane) helpers for gfx950: lane ^ M exchanges without LDS,
+// bitonic sorts and merges of one 64-bit key per lane, min / max reductions
+// and a radix select of up to 256 keys.
 #pragma once
 
 #include "common.hpp"
@@ -143,55 +143,7 @@ __device__ __forceinline__ unsigned long long merge32x2_asc(unsigned long long v
     return v;
 }
 
-// Bitonic sort of 256 keys held four per lane (element e = 64 j + lane in
-// register j), descending over e. Strides below 64 exchange across lanes,
-// strides 64 and 128 between registers of a lane.
-template <int SIZE, int M>
-__device__ __forceinline__ void sort256_step(unsigned long long (&v)[4], uint32_t lane) {
-    if constexpr (M < 64) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t e = (uint32_t)j * 64u + lane;
-            v[j] = cx<M>(v[j], lane, ((e & (uint32_t)M) == 0u) == ((e & (uint32_t)SIZE) != 0u));
-        }
-    } else {
-        constexpr int J = M / 64;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if ((j & J) != 0) continue;
-            const uint32_t e = (uint32_t)j * 64u + lane;
-            const bool asc = (e & (uint32_t)SIZE) != 0u;  // the block's direction (same for both)
-            const unsigned long long a = v[j], b = v[j | J];
-            const unsigned long long mn = a < b ? a : b, mx = a < b ? b : a;
-            v[j] = asc ? mn : mx;
-            v[j | J] = asc ? mx : mn;
-        }
-    }
-}
-
-template <int SIZE>
-__device__ __forceinline__ void sort256_stage(unsigned long long (&v)[4], uint32_t lane) {
-    if constexpr (SIZE >= 256) sort256_step<SIZE, 128>(v, lane);
-    if constexpr (SIZE >= 128) sort256_step<SIZE, 64>(v, lane);
-    if constexpr (SIZE >= 64) sort256_step<SIZE, 32>(v, lane);
-    if constexpr (SIZE >= 32) sort256_step<SIZE, 16>(v, lane);
-    if constexpr (SIZE >= 16) sort256_step<SIZE, 8>(v, lane);
-    if constexpr (SIZE >= 8) sort256_step<SIZE, 4>(v, lane);
-    if constexpr (SIZE >= 4) sort256_step<SIZE, 2>(v, lane);
-    sort256_step<SIZE, 1>(v, lane);
-}
-
-__device__ __forceinline__ void sort256_desc(unsigned long long (&v)[4], uint32_t lane) {
-    sort256_stage<2>(v, lane);
-    sort256_stage<4>(v, lane);
-    sort256_stage<8>(v, lane);
-    sort256_stage<16>(v, lane);
-    sort256_stage<32>(v, lane);
-    sort256_stage<64>(v, lane);
-    sort256_stage<128>(v, lane);
-    sort256_stage<512>(v, lane);  // final merge: every block descending
-}
-
+// Orders this wave's LDS writes before its later LDS reads (no block barrier).
 __device__ __forceinline__ void wave_lds_fence() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -278,16 +230,6 @@ __device__ __forceinline__ unsigned long long wave_select(const unsigned long lo
         }
         top = lo - 1;
     }
-}
-
-// Element e of a four-per-lane array (e uniform).
-__device__ __forceinline__ unsigned long long read_elem256(const unsigned long long (&v)[4], uint32_t e) {
-    const uint32_t j = e >> 6;
-    const int l = (int)(e & 63u);
-    const unsigned long long x = j == 0 ? v[0] : (j == 1 ? v[1] : (j == 2 ? v[2] : v[3]));
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
-    return ((unsigned long long)hi << 32) | lo;
 }
 
 }  // namespace gdn
