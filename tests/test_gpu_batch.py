@@ -274,6 +274,33 @@ def test_large_batch_paths_equal_plain(bden, den, k):
     check_frames_equal_plain(den, frames, off, o, dumps, params)
 
 
+def test_large_batch_ties_equal_plain(bden, den):
+    """Over 1M points with exact duplicates: equal r^2_K, densities and scores
+    inside small leaves (the wave radix select and the one-wave voxel filter
+    of large batches, against the block paths of the plain runs), clusters of
+    more than k identical points (r_K = 0, infinite density) and leaves too
+    small to have k candidates (zero density)."""
+    params = dict(k=16, leaf_cap=128)
+    rng = np.random.default_rng(77)
+    frames = []
+    for i, n in enumerate([1500, 1700, 1300, 1900, 1600, 1800, 1400, 1750, 1650, 1550, 1450, 1850]):
+        fr = synth.lidar_frame(seed=90 + i, n_az=int(n))[0]
+        dup = rng.choice(len(fr), len(fr) // 5, replace=False)
+        fr[dup] = fr[rng.choice(len(fr), len(dup))]  # a fifth of the points copy others
+        fr[:40] = fr[40]  # 41 identical points: r_K = 0 for them
+        frames.append(fr)
+    xyz, offd, off = to_dev(frames)
+    assert xyz.shape[0] > (1 << 20)
+    print(f"[batch] ties: {len(frames)} frames, n={xyz.shape[0]}", flush=True)
+    bden.set_params(**params)
+    o = outputs(bden(xyz, offd), xyz.shape[0], len(frames))
+    dumps = batch_dumps(bden, xyz.shape[0], len(frames))
+    assert dumps["status"] == 0
+    rho = dumps["RHO"]
+    assert np.isinf(rho).any() and (rho == 0).any()
+    check_frames_equal_plain(den, frames, off, o, dumps, params)
+
+
 def test_bench_batch_configuration_sampled_frames_vs_oracle(bden, oracle):
     """The 64-frame LiDAR batch (6.2M points) in the configuration the
     benchmark times after autotuning (leaf cap 256, candidate chunks of
