@@ -72,9 +72,7 @@ gdn::Plan make_plan(uint32_t n, uint32_t nf, int k, char* base) {
     P.sort_hist = (uint32_t*)take(sizeof(uint32_t) * SORT_PASSES_MAX * 256);
     P.sort_status = (uint32_t*)take(sizeof(uint32_t) * (size_t)P.sort_passes * P.sort_tiles * 256);
     P.scan_status = (uint32_t*)take(sizeof(uint32_t) * SCAN_SLOTS * (size_t)P.scan_tiles);
-    P.deep_bits = DEEP_HASH_MIN_BITS;
-    while (P.deep_bits < DEEP_HASH_MAX_BITS && (1ull << P.deep_bits) < N) ++P.deep_bits;
-    P.deep_hash = (uint32_t*)take(sizeof(uint32_t) << P.deep_bits);
+    P.deepf = (uint8_t*)take(N);
     P.zero_begin = base ? base + z0 : nullptr;
     P.zero_bytes = off - z0;
 
@@ -85,6 +83,7 @@ gdn::Plan make_plan(uint32_t n, uint32_t nf, int k, char* base) {
         P.fid = (uint32_t*)take(4 * N);
         P.keep_ex = (uint32_t*)take(4 * (N + 1));
     }
+    P.deep_seg = (uint2*)take(sizeof(uint2) * (N / 2 + 1));
     P.keys_a = (uint64_t*)take(8 * N);
     P.keys_b = (uint64_t*)take(8 * N);
     P.idx_a = (uint32_t*)take(4 * N);
@@ -338,7 +337,7 @@ static gdn_status run(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int64
     if (frame_off) gdn::launch_frames(P, frame_off, st);
     gdn::launch_bbox(P, xyz, st);
     gdn::launch_morton(P, prm, xyz, st);
-    gdn::launch_sort(P, st);
+    gdn::launch_sort(P, prm, st);
     gdn::launch_permute(P, xyz, st);
     gdn::launch_leaves(P, prm, st);
     gdn::launch_voxel(P, prm, st);

@@ -15,16 +15,17 @@ constexpr uint32_t SORT_BIG_N = 1u << 20;     // above: 16 keys per thread, else
 constexpr int SORT_PASSES = 8;                // 8-bit digits over the 63-bit key
 constexpr int SORT_FRAME_PASSES_MAX = 2;      // 8-bit digits of the frame id (batches)
 constexpr int SORT_PASSES_MAX = SORT_PASSES + SORT_FRAME_PASSES_MAX;
-// Short sort: when no level-10 cell can split, every leaf and halo cell is a
-// prefix of at most 30 key bits, so the passes over digits 4..7 (key bits
-// 32..62) alone order the points by cell; digits 0..3 are sorted only when a
-// hashed count of the level-10 cells says one may hold more than leaf_cap.
+// Short sort: the radix passes cover only digits 4..7 (key bits 32..62),
+// which hold every level-10 cell prefix (bits 33..62); the points end in
+// (frame, bits 32..62, original index) order. A level-10 cell that holds
+// more than leaf_cap points (and lies above the depth limit) splits further:
+// such "deep" cells are found after the sort and each is sorted on its whole
+// key by one workgroup, so the octree sees full key order wherever it goes
+// below level 10.
 constexpr int SORT_SHORT_LEVEL = 10;
 constexpr int SORT_SHORT_FIRST = 4;
 static_assert(3 * (MORTON_BITS - SORT_SHORT_LEVEL) >= 8 * SORT_SHORT_FIRST, "short sort must hold the cell prefix");
 static_assert(SORT_SHORT_FIRST % 2 == 0, "skipped passes keep the ping-pong parity");
-constexpr uint32_t DEEP_HASH_MIN_BITS = 12;   // level-10 cell counters: 2^12 .. 2^20 words
-constexpr uint32_t DEEP_HASH_MAX_BITS = 20;
 constexpr uint32_t MAX_FRAMES = 4096;         // frames per batched call (frame table staged in LDS)
 constexpr int SCAN_BLOCK = 256;
 constexpr int SCAN_ITEMS = 16;
@@ -70,7 +71,7 @@ struct Counters {
     unsigned long long pairs;
     uint32_t n_chunked_items; // kNN items of chunked leaves (they come first)
     uint32_t plan_cc;         // chosen kNN chunk length (parallel plan)
-    uint32_t sort_deep;       // nonzero: a level-10 cell may split, sort all key digits
+    uint32_t n_deep;          // deep level-10 cells (re-sorted on the whole key)
     uint32_t pad;
     unsigned long long plan_acc[PLAN_LEVELS][3];  // per candidate chunk length: lists, items, chunked items
     unsigned long long plan_pairs;
@@ -144,8 +145,8 @@ struct Plan {
     uint32_t* scan_status;    // [SCAN_SLOTS][scan_tiles]
     uint32_t sort_tiles, scan_tiles;
     uint32_t sort_items;      // keys per thread of the radix passes (4 or 16)
-    uint32_t* deep_hash;      // [1 << deep_bits] hashed level-10 cell counts (zeroed block)
-    uint32_t deep_bits;
+    uint8_t* deepf;           // [n] 1 at sorted positions inside deep level-10 cells (zeroed block)
+    uint2* deep_seg;          // [n / 2 + 1] sorted ranges of the deep cells
     // frames
     uint32_t* foff;           // [nf+1] frame offsets (checked copy of the caller's)
     uint32_t* fid;            // [n] frame of each point (original order; nf > 1 only)
@@ -298,13 +299,6 @@ __device__ __forceinline__ uint32_t frame_of(const uint32_t* foff, uint32_t nf, 
         else hi = mid;
     }
     return lo;
-}
-
-// Deepest octree level whose cell prefixes the sorted key order resolves
-// (points of one such cell sit together, in original-index order when the
-// cell is finer than the sorted digits).
-__device__ __forceinline__ int sorted_level(const Counters* c) {
-    return c->sort_deep ? MORTON_BITS : SORT_SHORT_LEVEL;
 }
 
 }  // namespace gdn

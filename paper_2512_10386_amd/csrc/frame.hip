@@ -246,14 +246,9 @@ __global__ __launch_bounds__(256) void frame_const_kernel(Plan P, double min_lea
 }
 
 // Keys (quantised with the point's own frame constants), the identity
-// payload and the digit histograms of the sort: 8 key digits, then the frame
-// id digits of a batch. A single frame computes its constants per block.
-// Each point also counts its level-10 cell (frame, 30-bit prefix) in a
-// hashed table; a counter passing `cap` (a cell, or cells sharing a
-// counter, above the leaf capacity) asks for the full sort. Cells at or
-// below the depth limit never split and are not counted.
-__global__ __launch_bounds__(256) void morton_kernel(const float* __restrict__ xyz, Plan P, double min_leaf_side,
-                                                     uint32_t cap) {
+// payload and the digit histograms of the sort: key digits 4..7, then the
+// frame id digits of a batch. A single frame computes its constants per block.
+__global__ __launch_bounds__(256) void morton_kernel(const float* __restrict__ xyz, Plan P, double min_leaf_side) {
     __shared__ FrameConst s_fc;
     __shared__ uint32_t s_hist[SORT_PASSES_MAX][256];
     const uint32_t n = P.n, nf = P.nf, nh = P.sort_passes;
@@ -272,13 +267,8 @@ __global__ __launch_bounds__(256) void morton_kernel(const float* __restrict__ x
         const uint64_t key = morton3(qx, qy, qz);
         P.keys_src[i] = key;
         P.idx_src[i] = i;
-        if (SORT_SHORT_LEVEL < fc.dmax) {
-            const uint64_t cell = (key >> (3 * (MORTON_BITS - SORT_SHORT_LEVEL))) | ((uint64_t)f << 32);
-            const uint32_t h = (uint32_t)((cell * 0x9E3779B97F4A7C15ull) >> (64u - P.deep_bits));
-            if (atomicAdd(&P.deep_hash[h], 1u) == cap) atomicOr(&P.ctr->sort_deep, 1u);
-        }
 #pragma unroll
-        for (int p = 0; p < SORT_PASSES; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
+        for (int p = SORT_SHORT_FIRST; p < SORT_PASSES; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
         for (uint32_t p = SORT_PASSES; p < nh; ++p) atomicAdd(&s_hist[p][(f >> (8 * (p - SORT_PASSES))) & 255u], 1u);
     }
     __syncthreads();
@@ -292,8 +282,7 @@ void launch_morton(const Plan& P, const Params& prm, const float* xyz, hipStream
     if (P.nf > 1) hipLaunchKernelGGL(frame_const_kernel, dim3(1), dim3(256), 0, st, P, prm.min_leaf_side);
     unsigned blocks = (P.n + 2047) / 2048;
     if (blocks > 512) blocks = 512;
-    hipLaunchKernelGGL(morton_kernel, dim3(blocks), dim3(256), 0, st, xyz, P, prm.min_leaf_side,
-                       (uint32_t)prm.leaf_cap);
+    hipLaunchKernelGGL(morton_kernel, dim3(blocks), dim3(256), 0, st, xyz, P, prm.min_leaf_side);
 }
 
 // ---------------------------------------------------------------- radix sort
@@ -303,10 +292,8 @@ void launch_morton(const Plan& P, const Params& prm, const float* xyz, hipStream
 // decoupled look-back (bounded waits), global digit bases from the histogram.
 // Passes past the key's 8 take the digit from the frame of the payload (the
 // original index, found in the frame offsets), so a batch ends sorted by
-// (frame, key, index).
-// Key passes below SORT_SHORT_FIRST return at once unless the Morton kernel
-// asked for the full sort (the order is then by (frame, key bits 32..62,
-// index), which resolves every cell of the octree).
+// (frame, key bits 32..62, index); only passes from SORT_SHORT_FIRST on are
+// launched.
 template <int ITEMS>
 __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* __restrict__ kin,
                                                                 const uint32_t* __restrict__ vin,
@@ -315,8 +302,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
                                                                 int pass, const uint32_t* __restrict__ hist,
                                                                 uint32_t* status, uint32_t* tile_ctr,
                                                                 uint32_t* dev_status, const uint32_t* __restrict__ foff,
-                                                                uint32_t nf, const uint32_t* __restrict__ deep) {
-    if (pass < SORT_SHORT_FIRST && *deep == 0u) return;
+                                                                uint32_t nf) {
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_w[SORT_BLOCK / 64][256];
     __shared__ uint32_t s_base[256];
@@ -469,19 +455,118 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
     }
 }
 
-void launch_sort(const Plan& P, hipStream_t st) {
-    // the keys start where an even/odd number of passes leaves them in keys_a
+// ---------------------------------------------------------------- deep cells
+
+constexpr int CELL_SHIFT = 3 * (MORTON_BITS - SORT_SHORT_LEVEL);  // level-10 prefix = key >> 33
+constexpr int SEG_BLOCK = 256;
+constexpr int SEG_PASSES = 6;  // key bits 0..47; bits 33..62 are the cell's own, and 6 passes end in keys_a
+
+// A level-10 cell splits when it holds more than `cap` points and lies above
+// its frame's depth limit. One thread per sorted position: a position that
+// starts such a cell finds the cell's end (the keys are in cell order) and
+// appends the range.
+__global__ __launch_bounds__(256) void deep_mark_kernel(Plan P, uint32_t cap) {
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < P.n; s += gridDim.x * blockDim.x) {
+        const uint32_t f = P.nf > 1 ? frame_of(P.foff, P.nf, s) : 0u;
+        if (P.fc[f].dmax <= SORT_SHORT_LEVEL) continue;
+        const uint32_t fs = P.foff[f], fe = P.foff[f + 1];
+        const uint64_t c = P.keys_a[s] >> CELL_SHIFT;
+        if (s > fs && (P.keys_a[s - 1] >> CELL_SHIFT) == c) continue;  // not the cell's first point
+        if ((uint64_t)s + cap >= fe || (P.keys_a[s + cap] >> CELL_SHIFT) != c) continue;  // <= cap points
+        uint32_t lo = s + cap + 1u, hi = fe;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if ((P.keys_a[mid] >> CELL_SHIFT) == c) lo = mid + 1u;
+            else hi = mid;
+        }
+        P.deep_seg[atomicAdd(&P.ctr->n_deep, 1u)] = make_uint2(s, lo);
+    }
+}
+
+// One workgroup per deep cell [a, b): a stable LSD radix sort of its keys and
+// payloads over key bits 0..47 (the cell's points share bits 33..62), tile by
+// tile in order through keys_b / idx_b (scratch after the main sort), which
+// turns the cell's (original index) order into (key, index) order. The
+// cell's positions are then flagged for the boundary test.
+__global__ __launch_bounds__(SEG_BLOCK) void seg_sort_kernel(Plan P) {
+    __shared__ uint32_t s_base[256];
+    __shared__ uint32_t s_w[SEG_BLOCK / 64][256];
+    __shared__ uint32_t s_scan[SEG_BLOCK / 64 + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t nseg = P.ctr->n_deep;
+    for (uint32_t g = blockIdx.x; g < nseg; g += gridDim.x) {
+        const uint2 sg = P.deep_seg[g];
+        const uint32_t a = sg.x, b = sg.y;
+        for (int pass = 0; pass < SEG_PASSES; ++pass) {
+            const int shift = 8 * pass;
+            const uint64_t* ks = (pass & 1) ? P.keys_b : P.keys_a;
+            const uint32_t* vs = (pass & 1) ? P.idx_b : P.idx_a;
+            uint64_t* kd = (pass & 1) ? P.keys_a : P.keys_b;
+            uint32_t* vd = (pass & 1) ? P.idx_a : P.idx_b;
+            s_base[tid] = 0u;
+            __syncthreads();
+            for (uint32_t i = a + tid; i < b; i += SEG_BLOCK) atomicAdd(&s_base[(uint32_t)(ks[i] >> shift) & 255u], 1u);
+            __syncthreads();
+            uint32_t tot;
+            const uint32_t ex = block_excl_scan(s_base[tid], s_scan, &tot);
+            s_base[tid] = a + ex;
+            for (uint32_t t0 = a; t0 < b; t0 += SEG_BLOCK) {
+                for (int w = 0; w < SEG_BLOCK / 64; ++w) s_w[w][tid] = 0u;
+                __syncthreads();
+                const uint32_t i = t0 + tid;
+                const bool ok = i < b;
+                const uint64_t k = ok ? ks[i] : 0ull;
+                const uint32_t v = ok ? vs[i] : 0u;
+                const uint32_t d = ok ? (uint32_t)(k >> shift) & 255u : 256u;
+                // lanes of this wave with the same digit
+                uint64_t m = __ballot(ok);
+#pragma unroll
+                for (int bt = 0; bt < 8; ++bt) {
+                    const bool bit = (d >> bt) & 1u;
+                    const uint64_t bb = __ballot(bit);
+                    m &= bit ? bb : ~bb;
+                }
+                const uint32_t before = (uint32_t)__popcll(m & lt_mask);
+                if (ok && (m >> lane) == 1ull) s_w[wave][d] = (uint32_t)__popcll(m);
+                __syncthreads();
+                uint32_t run = 0;
+                for (int w = 0; w < SEG_BLOCK / 64; ++w) {
+                    const uint32_t c = s_w[w][tid];
+                    s_w[w][tid] = run;
+                    run += c;
+                }
+                __syncthreads();
+                if (ok) {
+                    const uint32_t o = s_base[d] + s_w[wave][d] + before;
+                    if (o < b) {  // always true
+                        kd[o] = k;
+                        vd[o] = v;
+                    }
+                }
+                __syncthreads();
+                s_base[tid] += run;
+            }
+            __syncthreads();  // the pass's writes are complete before the next reads them
+        }
+        for (uint32_t i = a + tid; i < b; i += SEG_BLOCK) P.deepf[i] = 1u;
+        __syncthreads();
+    }
+}
+
+void launch_sort(const Plan& P, const Params& prm, hipStream_t st) {
+    // the keys start where the launched passes leave them in keys_a
     const uint64_t* kin = P.keys_src;
     const uint32_t* vin = P.idx_src;
     uint64_t* kout = P.keys_src == P.keys_a ? P.keys_b : P.keys_a;
     uint32_t* vout = P.idx_src == P.idx_a ? P.idx_b : P.idx_a;
-    for (uint32_t pass = 0; pass < P.sort_passes; ++pass) {
+    for (uint32_t pass = SORT_SHORT_FIRST; pass < P.sort_passes; ++pass) {
         // small inputs: many small tiles (latency); large: fewer, fuller tiles
         auto kern = P.sort_items == 4 ? radix_pass_kernel<4> : radix_pass_kernel<16>;
         hipLaunchKernelGGL(kern, dim3(P.sort_tiles), dim3(SORT_BLOCK), 0, st, kin, vin, kout, vout,
                            P.n, (int)pass, P.sort_hist + 256 * pass,
                            P.sort_status + (size_t)pass * P.sort_tiles * 256, &P.ctr->sort_tile_ctr[pass],
-                           &P.ctr->status, (const uint32_t*)P.foff, P.nf, (const uint32_t*)&P.ctr->sort_deep);
+                           &P.ctr->status, (const uint32_t*)P.foff, P.nf);
         const uint64_t* tk = kout;
         const uint32_t* tv = vout;
         kout = (uint64_t*)kin;
@@ -489,6 +574,11 @@ void launch_sort(const Plan& P, hipStream_t st) {
         kin = tk;
         vin = tv;
     }
+    unsigned blocks = (P.n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(deep_mark_kernel, dim3(blocks), dim3(256), 0, st, P, (uint32_t)prm.leaf_cap);
+    hipLaunchKernelGGL(seg_sort_kernel, dim3(256), dim3(SEG_BLOCK), 0, st, P);
 }
 
 // ---------------------------------------------------------------- permute

@@ -30,14 +30,15 @@ __device__ __forceinline__ uint32_t frame_of_sorted(const Plan& P, uint32_t j) {
 // Boundary test of sorted position j inside its frame [fs, fe): the frame's
 // first point starts a leaf; otherwise the rule above with the frame's depth
 // limit and the search window clipped to the frame.
-// Positions that share a cell of level lres (the deepest the sort resolves)
-// never straddle a boundary: no such cell splits.
-__device__ uint32_t leaf_boundary(const uint64_t* keys, uint32_t j, uint32_t fs, uint32_t fe, int dmax, int lres,
+// Positions that share a level-10 cell lie in one leaf unless the cell is
+// deep (more than leaf_cap points: it was re-sorted on the whole key, and the
+// test below applies inside it).
+__device__ uint32_t leaf_boundary(const uint64_t* keys, uint32_t j, uint32_t fs, uint32_t fe, int dmax, bool deep,
                                   uint32_t cap) {
     if (j == fs) return 1u;
     const uint64_t a = keys[j - 1], b = keys[j];
     const int l = common_digits(a, b);
-    if (l >= dmax || l >= lres) return 0u;
+    if (l >= dmax || (l >= SORT_SHORT_LEVEL && !deep)) return 0u;
     const int sh = 3 * (MORTON_BITS - l);
     const uint64_t P = b >> sh;
     uint32_t lo = (j - 1 - fs > cap) ? j - 1 - cap : fs;
@@ -93,10 +94,10 @@ __global__ __launch_bounds__(256) void leaf_table_kernel(Plan P, uint32_t cap) {
 // The boundary tests run one thread per position (each is a chain of
 // dependent loads); the scan then only reads the flags.
 __global__ __launch_bounds__(256) void boundary_flag_kernel(Plan P, uint32_t cap) {
-    const int lres = sorted_level(P.ctr);
     for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < P.n; j += gridDim.x * blockDim.x) {
         const uint32_t f = frame_of_sorted(P, j);
-        P.bflag[j] = (uint8_t)leaf_boundary(P.keys_a, j, P.foff[f], P.foff[f + 1], P.fc[f].dmax, lres, cap);
+        P.bflag[j] = (uint8_t)leaf_boundary(P.keys_a, j, P.foff[f], P.foff[f + 1], P.fc[f].dmax, P.deepf[j] != 0u,
+                                            cap);
     }
 }
 

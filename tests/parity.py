@@ -44,36 +44,42 @@ def run_gpu(den, xyz):
     return out
 
 
-SHORT_SORT_LEVEL = 10  # octrees no deeper than this: keys sorted on bits 32..62 only
+SHORT_SORT_LEVEL = 10  # the radix passes cover key bits 32..62 (every level-10 prefix)
 
 
-def short_order(ref):
-    """Order of the short sort: (key bits 32..62, original index)."""
+def expected_order(ref):
+    """The kernels' sorted order: (key bits 32..62, original index), except
+    inside "deep" level-10 cells (more than leaf_cap points, split further by
+    the octree), which are re-sorted on the whole key: there the order is the
+    oracle's (key, index). Deep cells exist exactly when a leaf lies below
+    level 10."""
     n = len(ref["keep"])
-    return np.lexsort((np.arange(n), ref["key"] >> np.uint64(32))).astype(np.uint32)
+    key = ref["key"].astype(np.uint64)
+    masked = key & ~np.uint64(0xFFFFFFFF)
+    if ref["n_leaves"] and int(ref["leaf_level"].max()) > SHORT_SORT_LEVEL:
+        cell = key >> np.uint64(3 * (21 - SHORT_SORT_LEVEL))
+        _, inv, cnt = np.unique(cell, return_inverse=True, return_counts=True)
+        deep = cnt[inv] > int(ref["params"]["leaf_cap"])
+        masked = np.where(deep, key, masked)
+    return np.lexsort((np.arange(n), masked)).astype(np.uint32)
 
 
 def check_order(order, ref, expect=None):
-    """The sorted order is the oracle's full (key, index) order, or, when no
-    leaf lies below level 10, possibly the short sort's (key bits 32..62,
-    index) order; the kernels take the short one unless a hashed count of the
-    level-10 cells passes leaf_cap. Either way every leaf's points fill its
-    range [begin, end) in leaf order. expect = "full" / "short" pins the path."""
+    """The sorted order is exactly the one above; every leaf's points fill its
+    range [begin, end) in leaf order. expect = "full" additionally requires the
+    oracle's whole-key order (every point in a deep cell or alone in its
+    level-10 cell), "short" that no cell was re-sorted."""
     n = len(ref["keep"])
     assert np.array_equal(np.sort(order), np.arange(n, dtype=order.dtype)), "order is not a permutation"
     sizes = (ref["leaf_end"] - ref["leaf_begin"]).astype(np.int64)
     want = np.repeat(np.arange(ref["n_leaves"], dtype=np.uint32), sizes)
     assert np.array_equal(ref["leaf_of"][order], want), "order: a point outside its leaf's range"
-    full = np.array_equal(order, ref["order"])
-    short = np.array_equal(order, short_order(ref))
-    if ref["n_leaves"] and int(ref["leaf_level"].max()) > SHORT_SORT_LEVEL:
-        expect = "full"
+    exp = expected_order(ref)
+    assert np.array_equal(order, exp), "order: not (key bits 32..62, index) with deep cells in key order"
     if expect == "full":
-        assert full, "order: expected the full key order"
+        assert np.array_equal(order, ref["order"]), "order: expected the full key order"
     elif expect == "short":
-        assert short, "order: expected the short-sort order"
-    else:
-        assert full or short, "order: neither the full nor the short-sort order"
+        assert int(ref["leaf_level"].max()) <= SHORT_SORT_LEVEL, "order: a deep cell where none was expected"
 
 
 def leaf_thresholds(ref):

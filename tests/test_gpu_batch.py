@@ -279,7 +279,9 @@ def test_large_batch_ties_equal_plain(bden, den):
     inside small leaves (the wave radix select and the one-wave voxel filter
     of large batches, against the block paths of the plain runs), clusters of
     more than k identical points (r_K = 0, infinite density) and leaves too
-    small to have k candidates (zero density)."""
+    small to have k candidates (zero density). One frame also holds a tight
+    blob whose level-10 cell exceeds the leaf cap (re-sorted on the whole key
+    and split below level 10)."""
     params = dict(k=16, leaf_cap=128)
     rng = np.random.default_rng(77)
     frames = []
@@ -288,6 +290,8 @@ def test_large_batch_ties_equal_plain(bden, den):
         dup = rng.choice(len(fr), len(fr) // 5, replace=False)
         fr[dup] = fr[rng.choice(len(fr), len(dup))]  # a fifth of the points copy others
         fr[:40] = fr[40]  # 41 identical points: r_K = 0 for them
+        if i == 3:
+            fr[100:2100] = fr[100] + rng.uniform(0, 1e-3, (2000, 3)).astype(np.float32)
         frames.append(fr)
     xyz, offd, off = to_dev(frames)
     assert xyz.shape[0] > (1 << 20)
@@ -298,6 +302,7 @@ def test_large_batch_ties_equal_plain(bden, den):
     assert dumps["status"] == 0
     rho = dumps["RHO"]
     assert np.isinf(rho).any() and (rho == 0).any()
+    assert dumps["LEAF_TABLE"][:, 2].max() > 10  # the blob's leaves lie below level 10
     check_frames_equal_plain(den, frames, off, o, dumps, params)
 
 

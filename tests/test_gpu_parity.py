@@ -1,9 +1,9 @@
 """HIP path vs the CPU oracle, element by element, through the C ABI.
 
 Keys, leaves, voxel sizes, occupancy, P1, kNN index sets and squared
-distances, r^2_K and P2 must be bit-exact; the sorted order is the oracle's
-(key, index) order, or (key bits 32..62, index) where no leaf lies below
-level 10; densities and medians agree to FP64
+distances, r^2_K and P2 must be bit-exact; the sorted order is (key bits
+32..62, index), with the oracle's (key, index) order inside level-10 cells
+that hold more than leaf_cap points; densities and medians agree to FP64
 rounding; scores to 1e-5 relative; keep labels may differ only for points whose
 score is within 1e-5 of their leaf's cut.
 """
@@ -97,8 +97,10 @@ def test_cap_one_and_depth_limit(den, oracle):
 
 
 def test_dense_cluster_needs_full_sort(den, oracle):
-    """A tight cluster inside a unit cube: leaves below level 10, so the
-    level-10 count must ask for every key digit (the order is the full one)."""
+    """A tight cluster inside a unit cube: its level-10 cell holds more than
+    leaf_cap points, so it is re-sorted on the whole key and split below
+    level 10 (the other points are alone in their level-10 cells, so the
+    whole order equals the oracle's)."""
     xyz, _ = synth.uniform_cube(11, 3000)
     rng = np.random.default_rng(11)
     blob = (np.float32(0.3) + rng.uniform(0, 2e-5, (4000, 3))).astype(np.float32)
