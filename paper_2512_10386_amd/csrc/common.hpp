@@ -218,7 +218,7 @@ __device__ __forceinline__ float f32_from_ordered(uint32_t o) {
 
 // Look-back status words carry their whole payload (flag + count), so relaxed
 // device-scope atomics suffice: no other data is published through them.
-constexpr int LB_WINDOW = 8;                  // predecessors fetched per look-back round trip
+constexpr int LB_WINDOW = 4;                  // predecessors fetched per look-back round trip
 
 __device__ __forceinline__ uint32_t ld_relaxed_agent(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
