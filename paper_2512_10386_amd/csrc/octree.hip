@@ -763,13 +763,17 @@ void launch_knn_plan(const Plan& P, const Params& prm, hipStream_t st) {
     if (blocks > 512) blocks = 512;
     hipLaunchKernelGGL(plan_count_kernel, dim3(blocks), dim3(256), 0, st, P, (uint32_t)chunk0);
     hipLaunchKernelGGL(plan_pick_kernel, dim3(1), dim3(64), 0, st, P, (uint32_t)chunk0);
+    // scans over the leaves (far fewer than the points that bound them): a
+    // small grid that loops over the tiles, not one workgroup per possible tile
     const uint32_t* nl = &P.ctr->n_leaves;
+    constexpr uint32_t LEAF_SCAN_BLOCKS = 64;
     launch_scan(ListsGet{P}, ListsEmit{P}, NoFin{}, nl, P.n, P.scan_status + 3 * (size_t)P.scan_tiles,
-                &P.ctr->scan_tile_ctr[3], &P.ctr->status, st);
+                &P.ctr->scan_tile_ctr[3], &P.ctr->status, st, LEAF_SCAN_BLOCKS);
     launch_scan(ItemsGet<true>{P}, ItemsEmit<true>{P}, NoFin{}, nl, P.n, P.scan_status + 4 * (size_t)P.scan_tiles,
-                &P.ctr->scan_tile_ctr[4], &P.ctr->status, st);
+                &P.ctr->scan_tile_ctr[4], &P.ctr->status, st, LEAF_SCAN_BLOCKS);
     launch_scan(ItemsGet<false>{P}, ItemsEmit<false>{P}, ItemsFin{P.ctr}, nl, P.n,
-                P.scan_status + 5 * (size_t)P.scan_tiles, &P.ctr->scan_tile_ctr[5], &P.ctr->status, st);
+                P.scan_status + 5 * (size_t)P.scan_tiles, &P.ctr->scan_tile_ctr[5], &P.ctr->status, st,
+                LEAF_SCAN_BLOCKS);
 }
 
 }  // namespace gdn

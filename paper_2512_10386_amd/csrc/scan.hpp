@@ -1,8 +1,9 @@
 // Single-pass exclusive scan with decoupled look-back.
 //
-// Every workgroup takes the next tile id from an atomic counter, so a tile
-// only ever waits on tiles that were handed out earlier and are already
-// resident; each wait is additionally bounded by SPIN_LIMIT (on expiry the
+// Workgroups take tile ids from an atomic counter, one after another until
+// the tiles run out (a grid smaller than the tile count loops), so a tile
+// only ever waits on tiles that were handed out earlier to running
+// workgroups; each wait is additionally bounded by SPIN_LIMIT (on expiry the
 // device status word records DEV_WAIT_LIMIT and the scan carries on), so no
 // launch can hang. The status words must be zero before the launch.
 #pragma once
@@ -31,10 +32,11 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(Get get, Emit emit, Fi
     __shared__ uint32_t s_val[TILE + TILE / 32];
     __shared__ uint32_t s_pre[TILE + TILE / 32];
     const uint32_t n = n_dev ? *n_dev : n_host;
+    const uint32_t ntiles = (n + TILE - 1) / TILE;
+    for (;;) {
     if (threadIdx.x == 0) s_tile = atomicAdd(tile_ctr, 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
-    const uint32_t ntiles = (n + TILE - 1) / TILE;
     if (tile >= ntiles) {
         if (n == 0 && tile == 0 && threadIdx.x == 0) fin(0u);
         return;
@@ -113,6 +115,8 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(Get get, Emit emit, Fi
         if (idx < n) emit(idx, s_pre[scan_lds_at(e)], s_val[scan_lds_at(e)]);
     }
     if (tile == ntiles - 1 && threadIdx.x == 0) fin(s_excl + agg);
+    __syncthreads();  // s_tile, s_excl and the LDS tile are reused by the next tile
+    }
 }
 
 // Items per thread for a scan over at most n_max elements: small scans use
@@ -125,10 +129,14 @@ inline uint32_t scan_tiles_for(uint32_t n_max) {
     return t ? t : 1u;
 }
 
+// max_blocks > 0 caps the grid (workgroups then take several tiles): for
+// scans whose device count is usually far below the host bound n_max.
 template <class Get, class Emit, class Fin>
 inline void launch_scan(Get get, Emit emit, Fin fin, const uint32_t* n_dev, uint32_t n_max,
-                        uint32_t* status, uint32_t* tile_ctr, uint32_t* dev_status, hipStream_t st) {
-    const uint32_t tiles = scan_tiles_for(n_max);
+                        uint32_t* status, uint32_t* tile_ctr, uint32_t* dev_status, hipStream_t st,
+                        uint32_t max_blocks = 0) {
+    uint32_t tiles = scan_tiles_for(n_max);
+    if (max_blocks > 0 && tiles > max_blocks) tiles = max_blocks;
     if (scan_items_for(n_max) == 4u)
         scan_kernel<4, Get, Emit, Fin><<<dim3(tiles), dim3(SCAN_BLOCK), 0, st>>>(get, emit, fin, n_dev, n_max,
                                                                                  status, tile_ctr, dev_status);
