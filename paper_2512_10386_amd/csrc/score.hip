@@ -221,6 +221,24 @@ struct RhoBits {
     }
 };
 
+// A block's leaves are t = blockIdx.x (mod gridDim.x). They are examined
+// SEL_BLOCK at a time, one per thread (one round of loads instead of a chain
+// of them), and those the block must handle (with `small`, the ones above
+// SMALL_LEAF P1 points; otherwise all) are listed in order in s_list.
+// Returns the count; whole block.
+__device__ uint32_t block_leaf_round(const Plan& P, uint32_t base, uint32_t nl, bool small, uint32_t* s_list,
+                                     uint32_t* s_scan) {
+    const uint32_t ti = base + threadIdx.x * gridDim.x;
+    uint32_t take = 0;
+    if (ti < nl)
+        take = small ? (P.p1pos[P.leaf_begin[ti + 1]] - P.p1pos[P.leaf_begin[ti]] > SMALL_LEAF ? 1u : 0u) : 1u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(take, s_scan, &tot);
+    if (take) s_list[ex] = ti;
+    __syncthreads();
+    return tot;
+}
+
 // ---------------------------------------------------------------- percentile + median
 //
 // Per leaf over Q_t = P1 of the leaf (n1 points): MATLAB prctile keeps the
@@ -251,9 +269,14 @@ __global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params p
     __shared__ uint32_t s_sel[SEL_SCRATCH];
     __shared__ uint32_t s_r2[SEL_LDS_MAX];
     __shared__ unsigned long long s_rho[SEL_LDS_MAX];
+    __shared__ uint32_t s_list[SEL_BLOCK];
+    __shared__ uint32_t s_lscan[SEL_BLOCK / 64 + 1];
     const uint32_t nl = P.ctr->n_leaves;
     const int k = prm.k;
-    for (uint32_t t = blockIdx.x; t < nl; t += gridDim.x) {
+    for (uint32_t base = blockIdx.x; base < nl; base += gridDim.x * SEL_BLOCK) {
+    const uint32_t nlist = block_leaf_round(P, base, nl, small, s_list, s_lscan);
+    for (uint32_t li = 0; li < nlist; ++li) {
+        const uint32_t t = s_list[li];
         const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
         const uint32_t n1 = qe - qb;
         if (small && n1 <= SMALL_LEAF) continue;  // leaf_select_small_kernel
@@ -289,6 +312,8 @@ __global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params p
         }
         if (threadIdx.x == 0) { P.leaf_rho_med[t] = med; P.leaf_r2cut[t] = cut; }
         __syncthreads();
+    }
+    __syncthreads();  // s_list is refilled by the next round
     }
 }
 
@@ -500,8 +525,13 @@ __global__ __launch_bounds__(SEL_BLOCK) void topl_kernel(Plan P, double lambda, 
     __shared__ uint32_t s_cnt;
     __shared__ unsigned long long s_key[SEL_LDS_MAX];
     __shared__ uint32_t s_idx[SEL_LDS_MAX];
+    __shared__ uint32_t s_list[SEL_BLOCK];
+    __shared__ uint32_t s_lscan[SEL_BLOCK / 64 + 1];
     const uint32_t nl = P.ctr->n_leaves;
-    for (uint32_t t = blockIdx.x; t < nl; t += gridDim.x) {
+    for (uint32_t base = blockIdx.x; base < nl; base += gridDim.x * SEL_BLOCK) {
+    const uint32_t nlist = block_leaf_round(P, base, nl, small, s_list, s_lscan);
+    for (uint32_t li = 0; li < nlist; ++li) {
+        const uint32_t t = s_list[li];
         const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
         const uint32_t n1 = qe - qb;
         if (small && n1 <= SMALL_LEAF) continue;  // topl_small_kernel
@@ -547,6 +577,8 @@ __global__ __launch_bounds__(SEL_BLOCK) void topl_kernel(Plan P, double lambda, 
         }
         if (threadIdx.x == 0) P.leaf_m[t] = m;
         __syncthreads();
+    }
+    __syncthreads();  // s_list is refilled by the next round
     }
 }
 
