@@ -349,8 +349,7 @@ static gdn_status run(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int64
     gdn::launch_knn(P, prm.k, ctx->num_cus, st);
     if (ce) (void)hipEventRecord(ce->ev[2], st);
     gdn::launch_knn_merge(P, prm.k, ctx->num_cus, st);
-    gdn::launch_density(P, prm, xyz, st);
-    gdn::launch_leaf_select(P, prm, st);
+    gdn::launch_leaf_select(P, prm, xyz, st);
     if (prm.stages & GDN_STAGE_SCORE) {
         gdn::launch_score(P, prm, st);
         gdn::launch_topl(P, prm, st);

@@ -28,9 +28,8 @@ void launch_knn_bound(const Plan& P, int k, int num_cus, hipStream_t st);
 void launch_knn(const Plan& P, int k, int num_cus, hipStream_t st);
 void launch_knn_merge(const Plan& P, int k, int num_cus, hipStream_t st);
 
-// score.hip: density, percentile/median, score, top-lambda, outputs
-void launch_density(const Plan& P, const Params& prm, const float* xyz, hipStream_t st);
-void launch_leaf_select(const Plan& P, const Params& prm, hipStream_t st);
+// score.hip: density with percentile/median, score, top-lambda, outputs
+void launch_leaf_select(const Plan& P, const Params& prm, const float* xyz, hipStream_t st);
 void launch_score(const Plan& P, const Params& prm, hipStream_t st);
 void launch_topl(const Plan& P, const Params& prm, hipStream_t st);
 void launch_keep_p2(const Plan& P, hipStream_t st);

@@ -33,62 +33,60 @@ __device__ __forceinline__ double seg_sum(double v, uint32_t kp) {
     return v;
 }
 
-// One thread per query. The list is sorted by fp32 d2, and fp32 d2 is within
-// ~6e-7 relative of the exact value, so only the neighbours whose fp32 d2 is
-// within 2^-16 of the k-th can hold the FP64 maximum. Usually that is the
-// k-th alone (the (k-1)-th lies below), read from the dense record the kNN
-// writes; otherwise walk the list down from the k-th and stop at the first
-// one below. Also stores r^2_K densely.
-__global__ __launch_bounds__(256) void density_kernel(Plan P, const float* __restrict__ xyz, int kk) {
-    const uint32_t np1 = P.ctr->n_p1;
-    const uint32_t k = (uint32_t)kk;
-    for (uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x; qi < np1; qi += gridDim.x * blockDim.x) {
-        const uint4 kr = P.krec[qi];
-        const uint32_t jk = kr.x;
-        const float r2 = __uint_as_float(kr.z);
-        P.r2k[qi] = r2;
-        double rho, r64;
-        if (jk == NO_NBR) {
-            rho = 0.0;
-            r64 = INFINITY;
-        } else {
-            // the query's coordinates: cand4 holds bit copies of the input
-            const float4 cq = P.cand4[qi];
-            const double xi = cq.x, yi = cq.y, zi = cq.z;
-            auto d2_to = [&](uint32_t j) -> double {
-                const double dx = (double)xyz[3 * (size_t)j] - xi;
-                const double dy = (double)xyz[3 * (size_t)j + 1] - yi;
-                const double dz = (double)xyz[3 * (size_t)j + 2] - zi;
-                return dx * dx + dy * dy + dz * dz;
-            };
-            const float thr = r2 * (1.0f - 1.0f / 65536.0f);
-            double m2 = 0.0;
-            if (k == 1u || __uint_as_float(kr.y) < thr) {
-                if (jk < P.n) m2 = fmax(m2, d2_to(jk));
-            } else {
-                const uint32_t* nb = P.nbr + (size_t)qi * k;
-                const float* d2 = P.nbr_d2 + (size_t)qi * k;
-                for (int r = (int)k - 1; r >= 0; --r) {
-                    if (d2[r] < thr) break;
-                    const uint32_t j = nb[r];
-                    if (j >= P.n) continue;
-                    const double v = d2_to(j);
-                    if (v > m2) m2 = v;
-                }
-            }
-            r64 = sqrt(m2);
-            rho = (double)k / ((4.0 / 3.0) * PI_D * (r64 * r64 * r64));
-        }
-        P.rho_c[qi] = rho;
-        P.r64_c[qi] = r64;
-    }
-}
+// Density of P1 query qi. The list is sorted by fp32 d2, and fp32 d2 is
+// within ~6e-7 relative of the exact value, so only the neighbours whose fp32
+// d2 is within 2^-16 of the k-th can hold the FP64 maximum. Usually that is
+// the k-th alone (the (k-1)-th lies below), read from the dense record the
+// kNN writes; otherwise walk the list down from the k-th and stop at the
+// first one below. Stores r^2_K, rho and r densely (the selects run it for
+// their leaf's points, so the density needs no launch of its own).
+struct Dens {
+    float r2;
+    double rho, r64;
+    bool short_list;  // fewer than k candidates
+};
 
-void launch_density(const Plan& P, const Params& prm, const float* xyz, hipStream_t st) {
-    unsigned blocks = (P.n + 255) / 256;
-    if (blocks > 16384) blocks = 16384;
-    if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(density_kernel, dim3(blocks), dim3(256), 0, st, P, xyz, prm.k);
+__device__ __forceinline__ Dens density_at(const Plan& P, const float* __restrict__ xyz, uint32_t k, uint32_t qi) {
+    const uint4 kr = P.krec[qi];
+    const uint32_t jk = kr.x;
+    Dens out;
+    out.r2 = __uint_as_float(kr.z);
+    out.short_list = jk == NO_NBR;
+    if (out.short_list) {
+        out.rho = 0.0;
+        out.r64 = INFINITY;
+    } else {
+        // the query's coordinates: cand4 holds bit copies of the input
+        const float4 cq = P.cand4[qi];
+        const double xi = cq.x, yi = cq.y, zi = cq.z;
+        auto d2_to = [&](uint32_t j) -> double {
+            const double dx = (double)xyz[3 * (size_t)j] - xi;
+            const double dy = (double)xyz[3 * (size_t)j + 1] - yi;
+            const double dz = (double)xyz[3 * (size_t)j + 2] - zi;
+            return dx * dx + dy * dy + dz * dz;
+        };
+        const float thr = out.r2 * (1.0f - 1.0f / 65536.0f);
+        double m2 = 0.0;
+        if (k == 1u || __uint_as_float(kr.y) < thr) {
+            if (jk < P.n) m2 = fmax(m2, d2_to(jk));
+        } else {
+            const uint32_t* nb = P.nbr + (size_t)qi * k;
+            const float* d2 = P.nbr_d2 + (size_t)qi * k;
+            for (int r = (int)k - 1; r >= 0; --r) {
+                if (d2[r] < thr) break;
+                const uint32_t j = nb[r];
+                if (j >= P.n) continue;
+                const double v = d2_to(j);
+                if (v > m2) m2 = v;
+            }
+        }
+        out.r64 = sqrt(m2);
+        out.rho = (double)k / ((4.0 / 3.0) * PI_D * (out.r64 * out.r64 * out.r64));
+    }
+    P.r2k[qi] = out.r2;
+    P.rho_c[qi] = out.rho;
+    P.r64_c[qi] = out.r64;
+    return out;
 }
 
 // ---------------------------------------------------------------- block radix select
@@ -264,7 +262,8 @@ __device__ void leaf_cut_and_median(RG r2, HG rho, uint32_t n1, double q, float*
     }
 }
 
-__global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params prm, bool small) {
+__global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params prm, bool small,
+                                                               const float* __restrict__ xyz) {
     __shared__ uint32_t s_hist[256];
     __shared__ uint32_t s_sel[SEL_SCRATCH];
     __shared__ uint32_t s_r2[SEL_LDS_MAX];
@@ -288,21 +287,25 @@ __global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params p
         double med;
         if (n1 <= SEL_LDS_MAX) {
             for (uint32_t i = threadIdx.x; i < n1; i += blockDim.x) {
-                s_r2[i] = __float_as_uint(P.r2k[qb + i]);
-                s_rho[i] = (unsigned long long)__double_as_longlong(P.rho_c[qb + i]);
+                const Dens dn = density_at(P, xyz, (uint32_t)k, qb + i);
+                s_r2[i] = __float_as_uint(dn.r2);
+                s_rho[i] = (unsigned long long)__double_as_longlong(dn.rho);
             }
             __syncthreads();
             leaf_cut_and_median(LdsBits<uint32_t>{s_r2}, LdsBits<unsigned long long>{s_rho}, n1, prm.rho_percentile,
                                 &cut, &med, s_hist, s_sel);
         } else {
+            for (uint32_t i = threadIdx.x; i < n1; i += blockDim.x) (void)density_at(P, xyz, (uint32_t)k, qb + i);
+            __syncthreads();
             leaf_cut_and_median(R2Bits{P.r2k, qb}, RhoBits{P.rho_c, qb}, n1, prm.rho_percentile, &cut, &med, s_hist,
                                 s_sel);
         }
         const double den = med * med + prm.eps;
         const double ha = prm.alpha / 2.0;
+        // same thread-to-point mapping as the density loop: each thread reads back its own stores
         for (uint32_t i = threadIdx.x; i < n1; i += blockDim.x) {
             const uint32_t qi = qb + i;
-            const bool insufficient = P.nbr[(size_t)qi * k + (k - 1)] == NO_NBR;
+            const bool insufficient = P.krec[qi].x == NO_NBR;
             P.p2[qi] = (!insufficient && P.r2k[qi] <= cut) ? 1 : 0;
             const double sr = prm.sigma * P.r64_c[qi];
             P.afac_c[qi] = make_double2(pow(P.rho_c[qi] / den, ha), 1.0 / (2.0 * sr * sr));
@@ -359,7 +362,7 @@ __device__ __forceinline__ unsigned long long wave_next_rank(const WaveVals& w, 
     return le > r + 1u ? a : mn;
 }
 
-__global__ __launch_bounds__(256) void leaf_select_small_kernel(Plan P, Params prm) {
+__global__ __launch_bounds__(256) void leaf_select_small_kernel(Plan P, Params prm, const float* __restrict__ xyz) {
     __shared__ uint32_t s_hist[4][256];
     uint32_t* const hist = s_hist[threadIdx.x >> 6];
     const uint32_t lane = threadIdx.x & 63u;
@@ -376,11 +379,22 @@ __global__ __launch_bounds__(256) void leaf_select_small_kernel(Plan P, Params p
             continue;
         }
         WaveVals r2v, rhov;
+        double r64v[4];
+        bool shortv[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t i = (uint32_t)j * 64u + lane;
-            r2v.v[j] = i < n1 ? (unsigned long long)__float_as_uint(P.r2k[qb + i]) : ~0ull;
-            rhov.v[j] = i < n1 ? (unsigned long long)__double_as_longlong(P.rho_c[qb + i]) : ~0ull;
+            r2v.v[j] = ~0ull;
+            rhov.v[j] = ~0ull;
+            r64v[j] = 0.0;
+            shortv[j] = true;
+            if (i < n1) {
+                const Dens dn = density_at(P, xyz, (uint32_t)k, qb + i);
+                r2v.v[j] = (unsigned long long)__float_as_uint(dn.r2);
+                rhov.v[j] = (unsigned long long)__double_as_longlong(dn.rho);
+                r64v[j] = dn.r64;
+                shortv[j] = dn.short_list;
+            }
         }
         double cd = ceil((double)n1 * prm.rho_percentile / 100.0 + 0.5);
         if (cd < 1.0) cd = 1.0;
@@ -396,12 +410,14 @@ __global__ __launch_bounds__(256) void leaf_select_small_kernel(Plan P, Params p
             med = (__longlong_as_double((long long)ab) + __longlong_as_double((long long)bb)) / 2.0;
         }
         const double den = med * med + prm.eps;
-        for (uint32_t i = lane; i < n1; i += 64u) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t i = (uint32_t)j * 64u + lane;
+            if (i >= n1) continue;
             const uint32_t qi = qb + i;
-            const bool insufficient = P.nbr[(size_t)qi * k + (k - 1)] == NO_NBR;
-            const double rho = P.rho_c[qi];
-            P.p2[qi] = (!insufficient && P.r2k[qi] <= cut) ? 1 : 0;
-            const double sr = prm.sigma * P.r64_c[qi];
+            const double rho = __longlong_as_double((long long)rhov.v[j]);
+            P.p2[qi] = (!shortv[j] && __uint_as_float((uint32_t)r2v.v[j]) <= cut) ? 1 : 0;
+            const double sr = prm.sigma * r64v[j];
             P.afac_c[qi] = make_double2(pow(rho / den, ha), 1.0 / (2.0 * sr * sr));
             const float4 c = P.cand4[qi];
             P.rec_o[__float_as_uint(c.w)] = NbrRec{c, pow(rho, ha), 0.0};
@@ -410,17 +426,17 @@ __global__ __launch_bounds__(256) void leaf_select_small_kernel(Plan P, Params p
     }
 }
 
-void launch_leaf_select(const Plan& P, const Params& prm, hipStream_t st) {
+void launch_leaf_select(const Plan& P, const Params& prm, const float* xyz, hipStream_t st) {
     // the wave path pays off for the many small leaves of large batches
     const bool small = P.n > SMALL_PATH_MIN_N;
     if (small) {
         unsigned wb = (P.n / 128 + 3) / 4;
         if (wb > 8192) wb = 8192;
-        hipLaunchKernelGGL(leaf_select_small_kernel, dim3(wb), dim3(256), 0, st, P, prm);
+        hipLaunchKernelGGL(leaf_select_small_kernel, dim3(wb), dim3(256), 0, st, P, prm, xyz);
     }
     unsigned blocks = P.n < 2048 ? P.n : 2048;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(leaf_select_kernel, dim3(blocks), dim3(SEL_BLOCK), 0, st, P, prm, small);
+    hipLaunchKernelGGL(leaf_select_kernel, dim3(blocks), dim3(SEL_BLOCK), 0, st, P, prm, small, xyz);
 }
 
 // ---------------------------------------------------------------- score
