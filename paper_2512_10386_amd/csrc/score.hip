@@ -33,6 +33,16 @@ __device__ __forceinline__ double seg_sum(double v, uint32_t kp) {
     return v;
 }
 
+// x^(alpha/2) of the density weight (Eq. 17): the square root for the
+// default alpha = 1 (a few instructions instead of a general FP64 power; the
+// two agree to an ulp), pow otherwise. The select kernels are instantiated
+// for either, so each holds only the code it runs.
+template <bool SQRT>
+__device__ __forceinline__ double pow_ha(double x, double ha) {
+    if constexpr (SQRT) return sqrt(x);
+    else return pow(x, ha);
+}
+
 // Density of P1 query qi. The list is sorted by fp32 d2, and fp32 d2 is
 // within ~6e-7 relative of the exact value, so only the neighbours whose fp32
 // d2 is within 2^-16 of the k-th can hold the FP64 maximum. Usually that is
@@ -262,6 +272,7 @@ __device__ void leaf_cut_and_median(RG r2, HG rho, uint32_t n1, double q, float*
     }
 }
 
+template <bool SQRT>
 __global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params prm, bool small,
                                                                const float* __restrict__ xyz) {
     __shared__ uint32_t s_hist[256];
@@ -308,10 +319,10 @@ __global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params p
             const bool insufficient = P.krec[qi].x == NO_NBR;
             P.p2[qi] = (!insufficient && P.r2k[qi] <= cut) ? 1 : 0;
             const double sr = prm.sigma * P.r64_c[qi];
-            P.afac_c[qi] = make_double2(pow(P.rho_c[qi] / den, ha), 1.0 / (2.0 * sr * sr));
+            P.afac_c[qi] = make_double2(pow_ha<SQRT>(P.rho_c[qi] / den, ha), 1.0 / (2.0 * sr * sr));
             // rho_j^(alpha/2) of Eq. 17's factored density weight, by original index
             const float4 c = P.cand4[qi];
-            P.rec_o[__float_as_uint(c.w)] = NbrRec{c, pow(P.rho_c[qi], ha), 0.0};
+            P.rec_o[__float_as_uint(c.w)] = NbrRec{c, pow_ha<SQRT>(P.rho_c[qi], ha), 0.0};
         }
         if (threadIdx.x == 0) { P.leaf_rho_med[t] = med; P.leaf_r2cut[t] = cut; }
         __syncthreads();
@@ -362,6 +373,7 @@ __device__ __forceinline__ unsigned long long wave_next_rank(const WaveVals& w, 
     return le > r + 1u ? a : mn;
 }
 
+template <bool SQRT>
 __global__ __launch_bounds__(256) void leaf_select_small_kernel(Plan P, Params prm, const float* __restrict__ xyz) {
     __shared__ uint32_t s_hist[4][256];
     uint32_t* const hist = s_hist[threadIdx.x >> 6];
@@ -418,9 +430,9 @@ __global__ __launch_bounds__(256) void leaf_select_small_kernel(Plan P, Params p
             const double rho = __longlong_as_double((long long)rhov.v[j]);
             P.p2[qi] = (!shortv[j] && __uint_as_float((uint32_t)r2v.v[j]) <= cut) ? 1 : 0;
             const double sr = prm.sigma * r64v[j];
-            P.afac_c[qi] = make_double2(pow(rho / den, ha), 1.0 / (2.0 * sr * sr));
+            P.afac_c[qi] = make_double2(pow_ha<SQRT>(rho / den, ha), 1.0 / (2.0 * sr * sr));
             const float4 c = P.cand4[qi];
-            P.rec_o[__float_as_uint(c.w)] = NbrRec{c, pow(rho, ha), 0.0};
+            P.rec_o[__float_as_uint(c.w)] = NbrRec{c, pow_ha<SQRT>(rho, ha), 0.0};
         }
         if (lane == 0) { P.leaf_rho_med[t] = med; P.leaf_r2cut[t] = cut; }
     }
@@ -429,14 +441,17 @@ __global__ __launch_bounds__(256) void leaf_select_small_kernel(Plan P, Params p
 void launch_leaf_select(const Plan& P, const Params& prm, const float* xyz, hipStream_t st) {
     // the wave path pays off for the many small leaves of large batches
     const bool small = P.n > SMALL_PATH_MIN_N;
+    const bool sq = prm.alpha == 1.0;
     if (small) {
         unsigned wb = (P.n / 128 + 3) / 4;
         if (wb > 8192) wb = 8192;
-        hipLaunchKernelGGL(leaf_select_small_kernel, dim3(wb), dim3(256), 0, st, P, prm, xyz);
+        hipLaunchKernelGGL(sq ? leaf_select_small_kernel<true> : leaf_select_small_kernel<false>, dim3(wb), dim3(256),
+                           0, st, P, prm, xyz);
     }
     unsigned blocks = P.n < 2048 ? P.n : 2048;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(leaf_select_kernel, dim3(blocks), dim3(SEL_BLOCK), 0, st, P, prm, small, xyz);
+    hipLaunchKernelGGL(sq ? leaf_select_kernel<true> : leaf_select_kernel<false>, dim3(blocks), dim3(SEL_BLOCK), 0, st,
+                       P, prm, small, xyz);
 }
 
 // ---------------------------------------------------------------- score
