@@ -464,6 +464,10 @@ void launch_leaf_select(const Plan& P, const Params& prm, const float* xyz, hipS
 // r_K,i = 0). The k terms are summed by a fixed pairwise tree (lane r holds
 // term r), not left to right.
 
+// Instantiated for the plain kernel exponent gamma = 2 (Eq. 20, one
+// division) and the general power: a kernel holding both paths needs more
+// registers and runs slower even when the power is never taken.
+template <bool G2>
 __global__ __launch_bounds__(256) void score_kernel(Plan P, int kk, double eps, double gamma) {
     const uint32_t np1 = P.ctr->n_p1;
     const uint32_t k = (uint32_t)kk, kp = pow2_at_least(k), qpw = 64u / kp;
@@ -487,7 +491,9 @@ __global__ __launch_bounds__(256) void score_kernel(Plan P, int kk, double eps, 
                 const double2 af = P.afac_c[qi];
                 const double w_den = af.x * R.gpow;
                 const double w_dis = (d2 == 0.0) ? 1.0 : exp(-(d2 * af.y));
-                const double kern = gamma == 2.0 ? 1.0 / (d2 + eps) : pow(d2 + eps, -gamma / 2.0);
+                double kern;
+                if constexpr (G2) kern = 1.0 / (d2 + eps);
+                else kern = pow(d2 + eps, -gamma / 2.0);
                 term = w_den * w_dis * kern;
             }
         }
@@ -503,7 +509,7 @@ void launch_score(const Plan& P, const Params& prm, hipStream_t st) {
     unsigned blocks = (unsigned)((waves + 3) / 4);
     if (blocks > 8192) blocks = 8192;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(score_kernel, dim3(blocks), dim3(256), 0, st, P, prm.k, prm.eps, prm.gamma);
+    hipLaunchKernelGGL(prm.gamma == 2.0 ? score_kernel<true> : score_kernel<false>, dim3(blocks), dim3(256), 0, st, P, prm.k, prm.eps, prm.gamma);
 }
 
 // ---------------------------------------------------------------- top-lambda
