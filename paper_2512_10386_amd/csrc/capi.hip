@@ -119,6 +119,7 @@ gdn::Plan make_plan(uint32_t n, uint32_t nf, int k, char* base) {
     P.nbr_d2 = (float*)take(4 * N * k);
     P.r2k = (float*)take(4 * N);
     P.krec = (uint4*)take(16 * N);
+    P.outrec = (uint2*)take(8 * N);
     P.tau_c = (float*)take(4 * N);
     P.rho_c = (double*)take(8 * N);
     P.r64_c = (double*)take(8 * N);

@@ -190,6 +190,7 @@ struct Plan {
     float* nbr_d2;            // [n][k]
     float* r2k;               // [n] (written by the density kernel from krec)
     uint4* krec;              // [n] k-th neighbour (none: 0xFFFFFFFF), fp32 bits of the (k-1)-th and k-th d2
+    uint2* outrec;            // [n] by original index: fp32 score bits, stage (large inputs' outputs)
     float* tau_c;             // [n] per-query upper bound of r^2_K (-1: none)
     double* rho_c;            // [n]
     double* r64_c;            // [n]

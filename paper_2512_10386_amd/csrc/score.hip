@@ -760,6 +760,41 @@ struct KeepGet {
     const uint8_t* keep;
     __device__ uint32_t operator()(uint32_t i) const { return keep[i]; }
 };
+
+// Large inputs: the outputs go out in two steps. outputs_pack_kernel
+// scatters one 8-byte record per point to its original index (one random
+// line per point instead of one per output array), and the keep scan, which
+// reads every point in input order anyway, writes the three output arrays
+// from the records as it loads them (coalesced).
+constexpr uint32_t PACKED_OUT_MIN_N = 1u << 20;
+
+__global__ __launch_bounds__(256) void outputs_pack_kernel(Plan P) {
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < P.n; s += gridDim.x * blockDim.x) {
+        uint32_t st = 0;
+        float sc = -1.0f;
+        if (P.p1[s]) {
+            const uint32_t qi = P.p1pos[s];
+            st = P.stage_c[qi];
+            if (st >= 2) sc = (float)P.score_c[qi];
+        }
+        P.outrec[P.idx_a[s]] = make_uint2(__float_as_uint(sc), st);
+    }
+}
+
+struct PackedKeepGet {
+    const uint2* rec;
+    uint8_t* keep;
+    float* score;
+    uint8_t* stage;
+    __device__ uint32_t operator()(uint32_t i) const {
+        const uint2 r = rec[i];
+        const uint32_t k = r.y == 3u ? 1u : 0u;
+        keep[i] = (uint8_t)k;
+        score[i] = __uint_as_float(r.x);
+        if (stage) stage[i] = (uint8_t)r.y;
+        return k;
+    }
+};
 struct KeepEmit {
     uint32_t* kept_idx;
     __device__ void operator()(uint32_t i, uint32_t ex, uint32_t f) const {
@@ -808,15 +843,26 @@ void launch_outputs(const Plan& P, uint8_t* keep, float* score, uint8_t* stage, 
                     int64_t* n_kept, hipStream_t st) {
     unsigned blocks = (P.n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(outputs_kernel, dim3(blocks), dim3(256), 0, st, P, keep, score, stage);
-    if (P.nf == 1) {
-        launch_scan(KeepGet{keep}, KeepEmit{kept_idx}, KeepFin{P.ctr, n_kept}, nullptr, P.n,
-                    P.scan_status + 2 * (size_t)P.scan_tiles, &P.ctr->scan_tile_ctr[2], &P.ctr->status, st);
+    uint32_t* const sstat = P.scan_status + 2 * (size_t)P.scan_tiles;
+    uint32_t* const sctr = &P.ctr->scan_tile_ctr[2];
+    if (P.n > PACKED_OUT_MIN_N) {
+        hipLaunchKernelGGL(outputs_pack_kernel, dim3(blocks), dim3(256), 0, st, P);
+        const PackedKeepGet get{P.outrec, keep, score, stage};
+        if (P.nf == 1)
+            launch_scan(get, KeepEmit{kept_idx}, KeepFin{P.ctr, n_kept}, nullptr, P.n, sstat, sctr, &P.ctr->status, st);
+        else
+            launch_scan(get, BatchKeepEmit{P.keep_ex}, BatchKeepFin{P.ctr, P.keep_ex, P.n}, nullptr, P.n, sstat, sctr,
+                        &P.ctr->status, st);
     } else {
-        launch_scan(KeepGet{keep}, BatchKeepEmit{P.keep_ex}, BatchKeepFin{P.ctr, P.keep_ex, P.n}, nullptr, P.n,
-                    P.scan_status + 2 * (size_t)P.scan_tiles, &P.ctr->scan_tile_ctr[2], &P.ctr->status, st);
-        hipLaunchKernelGGL(kept_frames_kernel, dim3(blocks), dim3(256), 0, st, P, keep, kept_idx, n_kept);
+        hipLaunchKernelGGL(outputs_kernel, dim3(blocks), dim3(256), 0, st, P, keep, score, stage);
+        if (P.nf == 1)
+            launch_scan(KeepGet{keep}, KeepEmit{kept_idx}, KeepFin{P.ctr, n_kept}, nullptr, P.n, sstat, sctr,
+                        &P.ctr->status, st);
+        else
+            launch_scan(KeepGet{keep}, BatchKeepEmit{P.keep_ex}, BatchKeepFin{P.ctr, P.keep_ex, P.n}, nullptr, P.n,
+                        sstat, sctr, &P.ctr->status, st);
     }
+    if (P.nf > 1) hipLaunchKernelGGL(kept_frames_kernel, dim3(blocks), dim3(256), 0, st, P, keep, kept_idx, n_kept);
 }
 
 __global__ void write_zero_counts_kernel(int64_t* n_kept, uint32_t nf) {
