@@ -78,19 +78,25 @@ __device__ __forceinline__ unsigned long long shfl64(unsigned long long v, int s
 // ---------------------------------------------------------------- bound
 
 constexpr int BOUND_MARGIN = 64;   // window reaches this far on each side of a query
-constexpr int BOUND_LEVELS = 10;   // thresholds tau * 2^(-m/2), m = 1..10
 constexpr int BOUND_SPLIT = 8;     // adjacent lanes sharing one query's distances
+// Threshold ladders: tau * 2^(-m/2), m = 1..10, for single frames; tau * 2^-m,
+// m = 1..5, above 1M points (small leaves: the coarser ladder costs the bound
+// less than it costs the kNN there).
+constexpr uint32_t BOUND_COARSE_MIN_N = 1u << 20;
 constexpr int BOUND_Q = 128;       // queries per block (BOUND_Q * BOUND_SPLIT threads)
 
 // tau: the largest d2 to the k points next to the query in Morton order inside
 // [qb, qe), a run of candidates holding the query; then, over the run's points
-// within BOUND_MARGIN positions, count those under tau * 2^(-m/2) and keep the
-// smallest threshold still holding k. -1 when the run has <= k points.
+// within BOUND_MARGIN positions, count those under each rung of the ladder
+// (LEVELS rungs, each the previous times STEP) and keep the smallest threshold
+// still holding k. -1 when the run has <= k points.
 // The BOUND_SPLIT lanes of a query each take every BOUND_SPLIT-th point and
 // combine their maxima and counts (exact, so tau does not depend on the
 // split); every lane of the wave calls this, `run` false for idle ones.
-template <class Pts>
+template <int LEVELS, class Pts>
 __device__ float query_bound(Pts cand4, uint32_t qb, uint32_t qe, uint32_t qi, int k, uint32_t sub, bool live) {
+    constexpr float STEP = LEVELS == 10 ? 0.70710678f : 0.5f;
+    static_assert(LEVELS == 10 || LEVELS == 5, "ladder");
     const bool run = live && qe - qb > (uint32_t)k;
     float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
     uint32_t s0 = 0, s1 = 0, wlo = 0, whi = 0;
@@ -107,12 +113,12 @@ __device__ float query_bound(Pts cand4, uint32_t qb, uint32_t qe, uint32_t qi, i
         if (j != qi) tau = fmaxf(tau, dist2(q, cand4[j]));
 #pragma unroll
     for (int o = 1; o < BOUND_SPLIT; o <<= 1) tau = fmaxf(tau, __shfl_xor(tau, o, 64));
-    float th[BOUND_LEVELS];
-    uint32_t cnt[BOUND_LEVELS];
+    float th[LEVELS];
+    uint32_t cnt[LEVELS];
     float f = tau;
 #pragma unroll
-    for (int m = 0; m < BOUND_LEVELS; ++m) {
-        f = f * 0.70710678f;
+    for (int m = 0; m < LEVELS; ++m) {
+        f = f * STEP;
         th[m] = f;
         cnt[m] = 0;
     }
@@ -120,11 +126,11 @@ __device__ float query_bound(Pts cand4, uint32_t qb, uint32_t qe, uint32_t qi, i
         const float d = dist2(q, cand4[j]);
         const uint32_t notself = (j != qi) ? 1u : 0u;
 #pragma unroll
-        for (int m = 0; m < BOUND_LEVELS; ++m) cnt[m] += (d <= th[m]) ? notself : 0u;
+        for (int m = 0; m < LEVELS; ++m) cnt[m] += (d <= th[m]) ? notself : 0u;
     }
     float best = tau;
 #pragma unroll
-    for (int m = 0; m < BOUND_LEVELS; ++m) {
+    for (int m = 0; m < LEVELS; ++m) {
 #pragma unroll
         for (int o = 1; o < BOUND_SPLIT; o <<= 1) cnt[m] += (uint32_t)__shfl_xor((int)cnt[m], o, 64);
         if (cnt[m] >= (uint32_t)k) best = th[m];
@@ -144,6 +150,7 @@ struct StagedPts {
 // the plan gave the leaf. A block takes BOUND_Q consecutive queries; every
 // window lies within BOUND_MARGIN of its query, so the block stages those
 // points.
+template <int LEVELS>
 __global__ __launch_bounds__(BOUND_Q * BOUND_SPLIT) void knn_bound_kernel(Plan P, const float4* __restrict__ cand4,
                                                                          int k) {
     __shared__ float4 s_pts[BOUND_Q + 2 * BOUND_MARGIN + 1];
@@ -175,7 +182,7 @@ __global__ __launch_bounds__(BOUND_Q * BOUND_SPLIT) void knn_bound_kernel(Plan P
                 }
             }
         }
-        const float b = query_bound(StagedPts{s_pts, lo}, rb, re, qi, k, sub, live);
+        const float b = query_bound<LEVELS>(StagedPts{s_pts, lo}, rb, re, qi, k, sub, live);
         if (live && sub == 0u) {
             P.tau_c[qi] = b;
             if ((qi - qb) % (uint32_t)KNN_TQ == 0u) {
@@ -687,8 +694,8 @@ void launch_knn_bound(const Plan& P, int k, int num_cus, hipStream_t st) {
     unsigned blocks = (P.n + BOUND_Q - 1) / BOUND_Q;
     if (blocks > 4096) blocks = 4096;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(knn_bound_kernel, dim3(blocks), dim3(BOUND_Q * BOUND_SPLIT), 0, st, P,
-                       (const float4*)P.cand4, k);
+    hipLaunchKernelGGL(P.n > BOUND_COARSE_MIN_N ? knn_bound_kernel<5> : knn_bound_kernel<10>, dim3(blocks),
+                       dim3(BOUND_Q * BOUND_SPLIT), 0, st, P, (const float4*)P.cand4, k);
 }
 
 size_t knn_lds_bytes(int k, bool pos) {
