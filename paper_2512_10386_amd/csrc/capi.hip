@@ -83,7 +83,6 @@ gdn::Plan make_plan(uint32_t n, uint32_t nf, int k, char* base) {
         P.fid = (uint32_t*)take(4 * N);
         P.keep_ex = (uint32_t*)take(4 * (N + 1));
     }
-    P.deep_seg = (uint2*)take(sizeof(uint2) * (N / 2 + 1));
     P.keys_a = (uint64_t*)take(8 * N);
     P.keys_b = (uint64_t*)take(8 * N);
     P.idx_a = (uint32_t*)take(4 * N);

@@ -71,8 +71,7 @@ struct Counters {
     unsigned long long pairs;
     uint32_t n_chunked_items; // kNN items of chunked leaves (they come first)
     uint32_t plan_cc;         // chosen kNN chunk length (parallel plan)
-    uint32_t n_deep;          // deep level-10 cells (re-sorted on the whole key)
-    uint32_t pad;
+    uint32_t pad[2];
     unsigned long long plan_acc[PLAN_LEVELS][3];  // per candidate chunk length: lists, items, chunked items
     unsigned long long plan_pairs;
     // kNN work queue: item i belongs to stream i % KNN_STREAMS; one cursor
@@ -146,7 +145,6 @@ struct Plan {
     uint32_t sort_tiles, scan_tiles;
     uint32_t sort_items;      // keys per thread of the radix passes (4 or 16)
     uint8_t* deepf;           // [n] 1 at sorted positions inside deep level-10 cells (zeroed block)
-    uint2* deep_seg;          // [n / 2 + 1] sorted ranges of the deep cells
     // frames
     uint32_t* foff;           // [nf+1] frame offsets (checked copy of the caller's)
     uint32_t* fid;            // [n] frame of each point (original order; nf > 1 only)

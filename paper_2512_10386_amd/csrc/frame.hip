@@ -461,95 +461,105 @@ constexpr int CELL_SHIFT = 3 * (MORTON_BITS - SORT_SHORT_LEVEL);  // level-10 pr
 constexpr int SEG_BLOCK = 256;
 constexpr int SEG_PASSES = 6;  // key bits 0..47; bits 33..62 are the cell's own, and 6 passes end in keys_a
 
-// A level-10 cell splits when it holds more than `cap` points and lies above
-// its frame's depth limit. One thread per sorted position: a position that
-// starts such a cell finds the cell's end (the keys are in cell order) and
-// appends the range.
-__global__ __launch_bounds__(256) void deep_mark_kernel(Plan P, uint32_t cap) {
-    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < P.n; s += gridDim.x * blockDim.x) {
-        const uint32_t f = P.nf > 1 ? frame_of(P.foff, P.nf, s) : 0u;
-        if (P.fc[f].dmax <= SORT_SHORT_LEVEL) continue;
-        const uint32_t fs = P.foff[f], fe = P.foff[f + 1];
-        const uint64_t c = P.keys_a[s] >> CELL_SHIFT;
-        if (s > fs && (P.keys_a[s - 1] >> CELL_SHIFT) == c) continue;  // not the cell's first point
-        if ((uint64_t)s + cap >= fe || (P.keys_a[s + cap] >> CELL_SHIFT) != c) continue;  // <= cap points
-        uint32_t lo = s + cap + 1u, hi = fe;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if ((P.keys_a[mid] >> CELL_SHIFT) == c) lo = mid + 1u;
-            else hi = mid;
+// Stable LSD radix sort of the keys and payloads of one deep cell [a, b) over
+// key bits 0..47 (the cell's points share bits 33..62), by the whole block,
+// tile by tile in order through keys_b / idx_b (scratch after the main sort):
+// the cell's (original index) order becomes (key, index) order. Its
+// positions are then flagged for the boundary test.
+__device__ void sort_deep_cell(const Plan& P, uint32_t a, uint32_t b, uint32_t* s_base,
+                               uint32_t (*s_w)[256], uint32_t* s_scan) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int pass = 0; pass < SEG_PASSES; ++pass) {
+        const int shift = 8 * pass;
+        const uint64_t* ks = (pass & 1) ? P.keys_b : P.keys_a;
+        const uint32_t* vs = (pass & 1) ? P.idx_b : P.idx_a;
+        uint64_t* kd = (pass & 1) ? P.keys_a : P.keys_b;
+        uint32_t* vd = (pass & 1) ? P.idx_a : P.idx_b;
+        s_base[tid] = 0u;
+        __syncthreads();
+        for (uint32_t i = a + tid; i < b; i += SEG_BLOCK) atomicAdd(&s_base[(uint32_t)(ks[i] >> shift) & 255u], 1u);
+        __syncthreads();
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(s_base[tid], s_scan, &tot);
+        s_base[tid] = a + ex;
+        for (uint32_t t0 = a; t0 < b; t0 += SEG_BLOCK) {
+            for (int w = 0; w < SEG_BLOCK / 64; ++w) s_w[w][tid] = 0u;
+            __syncthreads();
+            const uint32_t i = t0 + tid;
+            const bool ok = i < b;
+            const uint64_t k = ok ? ks[i] : 0ull;
+            const uint32_t v = ok ? vs[i] : 0u;
+            const uint32_t d = ok ? (uint32_t)(k >> shift) & 255u : 256u;
+            // lanes of this wave with the same digit
+            uint64_t m = __ballot(ok);
+#pragma unroll
+            for (int bt = 0; bt < 8; ++bt) {
+                const bool bit = (d >> bt) & 1u;
+                const uint64_t bb = __ballot(bit);
+                m &= bit ? bb : ~bb;
+            }
+            const uint32_t before = (uint32_t)__popcll(m & lt_mask);
+            if (ok && (m >> lane) == 1ull) s_w[wave][d] = (uint32_t)__popcll(m);
+            __syncthreads();
+            uint32_t run = 0;
+            for (int w = 0; w < SEG_BLOCK / 64; ++w) {
+                const uint32_t c = s_w[w][tid];
+                s_w[w][tid] = run;
+                run += c;
+            }
+            __syncthreads();
+            if (ok) {
+                const uint32_t o = s_base[d] + s_w[wave][d] + before;
+                if (o < b) {  // always true
+                    kd[o] = k;
+                    vd[o] = v;
+                }
+            }
+            __syncthreads();
+            s_base[tid] += run;
         }
-        P.deep_seg[atomicAdd(&P.ctr->n_deep, 1u)] = make_uint2(s, lo);
+        __syncthreads();  // the pass's writes are complete before the next reads them
     }
+    for (uint32_t i = a + tid; i < b; i += SEG_BLOCK) P.deepf[i] = 1u;
+    __syncthreads();
 }
 
-// One workgroup per deep cell [a, b): a stable LSD radix sort of its keys and
-// payloads over key bits 0..47 (the cell's points share bits 33..62), tile by
-// tile in order through keys_b / idx_b (scratch after the main sort), which
-// turns the cell's (original index) order into (key, index) order. The
-// cell's positions are then flagged for the boundary test.
-__global__ __launch_bounds__(SEG_BLOCK) void seg_sort_kernel(Plan P) {
+// A level-10 cell splits when it holds more than `cap` points and lies above
+// its frame's depth limit. One thread per sorted position: a position that
+// starts such a cell finds the cell's end (the keys are in cell order); the
+// block then sorts the cells that start among its positions. (Blocks that
+// read keys of a cell another block is sorting compare cell prefixes only,
+// which the sort does not change.)
+__global__ __launch_bounds__(SEG_BLOCK) void deep_cells_kernel(Plan P, uint32_t cap) {
     __shared__ uint32_t s_base[256];
     __shared__ uint32_t s_w[SEG_BLOCK / 64][256];
     __shared__ uint32_t s_scan[SEG_BLOCK / 64 + 1];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    const uint32_t nseg = P.ctr->n_deep;
-    for (uint32_t g = blockIdx.x; g < nseg; g += gridDim.x) {
-        const uint2 sg = P.deep_seg[g];
-        const uint32_t a = sg.x, b = sg.y;
-        for (int pass = 0; pass < SEG_PASSES; ++pass) {
-            const int shift = 8 * pass;
-            const uint64_t* ks = (pass & 1) ? P.keys_b : P.keys_a;
-            const uint32_t* vs = (pass & 1) ? P.idx_b : P.idx_a;
-            uint64_t* kd = (pass & 1) ? P.keys_a : P.keys_b;
-            uint32_t* vd = (pass & 1) ? P.idx_a : P.idx_b;
-            s_base[tid] = 0u;
-            __syncthreads();
-            for (uint32_t i = a + tid; i < b; i += SEG_BLOCK) atomicAdd(&s_base[(uint32_t)(ks[i] >> shift) & 255u], 1u);
-            __syncthreads();
-            uint32_t tot;
-            const uint32_t ex = block_excl_scan(s_base[tid], s_scan, &tot);
-            s_base[tid] = a + ex;
-            for (uint32_t t0 = a; t0 < b; t0 += SEG_BLOCK) {
-                for (int w = 0; w < SEG_BLOCK / 64; ++w) s_w[w][tid] = 0u;
-                __syncthreads();
-                const uint32_t i = t0 + tid;
-                const bool ok = i < b;
-                const uint64_t k = ok ? ks[i] : 0ull;
-                const uint32_t v = ok ? vs[i] : 0u;
-                const uint32_t d = ok ? (uint32_t)(k >> shift) & 255u : 256u;
-                // lanes of this wave with the same digit
-                uint64_t m = __ballot(ok);
-#pragma unroll
-                for (int bt = 0; bt < 8; ++bt) {
-                    const bool bit = (d >> bt) & 1u;
-                    const uint64_t bb = __ballot(bit);
-                    m &= bit ? bb : ~bb;
+    __shared__ uint2 s_seg[SEG_BLOCK / 2];  // cells are >= 2 points long, so at most half the positions start one
+    __shared__ uint32_t s_nseg;
+    for (uint32_t base = blockIdx.x * SEG_BLOCK; base < P.n; base += gridDim.x * SEG_BLOCK) {
+        if (threadIdx.x == 0) s_nseg = 0u;
+        __syncthreads();
+        const uint32_t s = base + threadIdx.x;
+        if (s < P.n) {
+            const uint32_t f = P.nf > 1 ? frame_of(P.foff, P.nf, s) : 0u;
+            const uint32_t fs = P.foff[f], fe = P.foff[f + 1];
+            const uint64_t c = P.keys_a[s] >> CELL_SHIFT;
+            const bool start = P.fc[f].dmax > SORT_SHORT_LEVEL && (s == fs || (P.keys_a[s - 1] >> CELL_SHIFT) != c) &&
+                               (uint64_t)s + cap < fe && (P.keys_a[s + cap] >> CELL_SHIFT) == c;
+            if (start) {
+                uint32_t lo = s + cap + 1u, hi = fe;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if ((P.keys_a[mid] >> CELL_SHIFT) == c) lo = mid + 1u;
+                    else hi = mid;
                 }
-                const uint32_t before = (uint32_t)__popcll(m & lt_mask);
-                if (ok && (m >> lane) == 1ull) s_w[wave][d] = (uint32_t)__popcll(m);
-                __syncthreads();
-                uint32_t run = 0;
-                for (int w = 0; w < SEG_BLOCK / 64; ++w) {
-                    const uint32_t c = s_w[w][tid];
-                    s_w[w][tid] = run;
-                    run += c;
-                }
-                __syncthreads();
-                if (ok) {
-                    const uint32_t o = s_base[d] + s_w[wave][d] + before;
-                    if (o < b) {  // always true
-                        kd[o] = k;
-                        vd[o] = v;
-                    }
-                }
-                __syncthreads();
-                s_base[tid] += run;
+                s_seg[atomicAdd(&s_nseg, 1u)] = make_uint2(s, lo);
             }
-            __syncthreads();  // the pass's writes are complete before the next reads them
         }
-        for (uint32_t i = a + tid; i < b; i += SEG_BLOCK) P.deepf[i] = 1u;
+        __syncthreads();
+        const uint32_t ns = s_nseg;
+        for (uint32_t g = 0; g < ns; ++g) sort_deep_cell(P, s_seg[g].x, s_seg[g].y, s_base, s_w, s_scan);
         __syncthreads();
     }
 }
@@ -577,8 +587,7 @@ void launch_sort(const Plan& P, const Params& prm, hipStream_t st) {
     unsigned blocks = (P.n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(deep_mark_kernel, dim3(blocks), dim3(256), 0, st, P, (uint32_t)prm.leaf_cap);
-    hipLaunchKernelGGL(seg_sort_kernel, dim3(256), dim3(SEG_BLOCK), 0, st, P);
+    hipLaunchKernelGGL(deep_cells_kernel, dim3(blocks), dim3(SEG_BLOCK), 0, st, P, (uint32_t)prm.leaf_cap);
 }
 
 // ---------------------------------------------------------------- permute
