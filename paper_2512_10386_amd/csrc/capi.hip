@@ -342,7 +342,7 @@ static gdn_status run(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int64
     gdn::launch_leaves(P, prm, st);
     gdn::launch_voxel(P, prm, st);
     gdn::launch_p1_compact(P, st);
-    gdn::launch_halo(P, st);
+    gdn::launch_halo(P, prm, st);
     gdn::launch_knn_plan(P, prm, st);
     gdn::launch_knn_bound(P, prm.k, ctx->num_cus, st);
     if (ce) (void)hipEventRecord(ce->ev[1], st);

@@ -20,7 +20,7 @@ void launch_permute(const Plan& P, const float* xyz, hipStream_t st);
 void launch_leaves(const Plan& P, const Params& prm, hipStream_t st);
 void launch_voxel(const Plan& P, const Params& prm, hipStream_t st);
 void launch_p1_compact(const Plan& P, hipStream_t st);
-void launch_halo(const Plan& P, hipStream_t st);
+void launch_halo(const Plan& P, const Params& prm, hipStream_t st);
 void launch_knn_plan(const Plan& P, const Params& prm, hipStream_t st);
 
 // knn.hip: brute-force kNN over leaf + halo candidates (chunk merge included)

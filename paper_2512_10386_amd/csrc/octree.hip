@@ -71,24 +71,17 @@ struct BoundaryFin {
     }
 };
 
-// Level and prefix of each leaf [s, e): with m = the larger of the common
-// digits across its two borders, the leaf is the level-(m+1) cell unless it
-// is an over-full cell at the depth limit.
-__global__ __launch_bounds__(256) void leaf_table_kernel(Plan P, uint32_t cap) {
-    const uint32_t nl = P.ctr->n_leaves;
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nl; t += gridDim.x * blockDim.x) {
-        const uint32_t s = P.leaf_begin[t], e = P.leaf_begin[t + 1];
-        const uint32_t f = frame_of_sorted(P, s);
-        const uint32_t fs = P.foff[f], fe = P.foff[f + 1];
-        const int dmax = P.fc[f].dmax;
-        int m = -1;
-        if (s > fs) m = common_digits(P.keys_a[s - 1], P.keys_a[s]);
-        if (e < fe) m = max(m, common_digits(P.keys_a[e - 1], P.keys_a[e]));
-        int level = (e - s <= cap) ? m + 1 : dmax;
-        level = level < 0 ? 0 : (level > MORTON_BITS ? MORTON_BITS : level);
-        P.leaf_level[t] = (uint32_t)level;
-        P.leaf_prefix[t] = P.keys_a[s] >> (3 * (MORTON_BITS - level));
-    }
+// Level and prefix of leaf t = [s, e) of frame [fs, fe): with m = the larger
+// of the common digits across its two borders, the leaf is the level-(m+1)
+// cell unless it is an over-full cell at the depth limit. (The halo kernel
+// derives them as it starts on the leaf.)
+__device__ __forceinline__ int leaf_level_of(const Plan& P, uint32_t s, uint32_t e, uint32_t fs, uint32_t fe,
+                                             int dmax, uint32_t cap) {
+    int m = -1;
+    if (s > fs) m = common_digits(P.keys_a[s - 1], P.keys_a[s]);
+    if (e < fe) m = max(m, common_digits(P.keys_a[e - 1], P.keys_a[e]));
+    int level = (e - s <= cap) ? m + 1 : dmax;
+    return level < 0 ? 0 : (level > MORTON_BITS ? MORTON_BITS : level);
 }
 
 // The boundary tests run one thread per position (each is a chain of
@@ -113,8 +106,6 @@ void launch_leaves(const Plan& P, const Params& prm, hipStream_t st) {
     BoundaryEmit e{P.leaf_of, P.leaf_begin};
     BoundaryFin f{P.ctr, P.leaf_begin, P.n};
     launch_scan(FlagGet{P.bflag}, e, f, nullptr, P.n, P.scan_status, &P.ctr->scan_tile_ctr[0], &P.ctr->status, st);
-    if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(leaf_table_kernel, dim3(blocks), dim3(256), 0, st, P, (uint32_t)prm.leaf_cap);
 }
 
 // ---------------------------------------------------------------- voxel filter
@@ -440,7 +431,7 @@ constexpr int HALO_LEAVES = 8;  // leaves per 256-thread block (32 threads each,
 // it (clipped to the grid and to the frame), then the non-empty ranges are
 // sorted by rank counting and runs of touching ranges merged with ballots;
 // the result is the leaf's candidate ranges in P1 order.
-__global__ __launch_bounds__(256) void halo_kernel(Plan P) {
+__global__ __launch_bounds__(256) void halo_kernel(Plan P, uint32_t cap) {
     __shared__ uint2 s_r[HALO_LEAVES][32];
     __shared__ uint2 s_s[HALO_LEAVES][32];
     const int tid = threadIdx.x, grp = tid >> 5, g = tid & 31;
@@ -454,10 +445,15 @@ __global__ __launch_bounds__(256) void halo_kernel(Plan P) {
         const bool live = t < nl;
         uint2 r = make_uint2(0u, 0u);
         if (live && g < HALO) {
-            const uint32_t f = frame_of_sorted(P, P.leaf_begin[t]);
+            const uint32_t lb = P.leaf_begin[t], le = P.leaf_begin[t + 1];
+            const uint32_t f = frame_of_sorted(P, lb);
             const uint32_t fs = P.foff[f], fe = P.foff[f + 1];
-            const int d = (int)P.leaf_level[t];
-            const uint64_t pre = P.leaf_prefix[t];
+            const int d = leaf_level_of(P, lb, le, fs, fe, P.fc[f].dmax, cap);
+            const uint64_t pre = P.keys_a[lb] >> (3 * (MORTON_BITS - d));
+            if (g == 0) {
+                P.leaf_level[t] = (uint32_t)d;
+                P.leaf_prefix[t] = pre;
+            }
             const int64_t cx = compact3(pre), cy = compact3(pre >> 1), cz = compact3(pre >> 2);
             const int64_t nx = cx + (g % 3) - 1, ny = cy + (g / 3) % 3 - 1, nz = cz + g / 9 - 1;
             const int64_t side = (int64_t)1 << d;
@@ -506,11 +502,11 @@ __global__ __launch_bounds__(256) void halo_kernel(Plan P) {
     }
 }
 
-void launch_halo(const Plan& P, hipStream_t st) {
+void launch_halo(const Plan& P, const Params& prm, hipStream_t st) {
     unsigned blocks = (P.n + HALO_LEAVES - 1) / HALO_LEAVES;
     if (blocks > 2048) blocks = 2048;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(halo_kernel, dim3(blocks), dim3(256), 0, st, P);
+    hipLaunchKernelGGL(halo_kernel, dim3(blocks), dim3(256), 0, st, P, (uint32_t)prm.leaf_cap);
 }
 
 // ---------------------------------------------------------------- kNN plan
