@@ -587,26 +587,34 @@ __global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restric
 
 // ---------------------------------------------------------------- chunk merge
 //
-// One wave per query tile of a chunked leaf, after the kNN kernel (the kernel
+// MERGE_SPLIT waves per query tile of a chunked leaf (each takes a share of
+// the tile's queries, which shortens the longest chain of merges), after the kNN kernel (the kernel
 // boundary makes every partial list visible). B_j, the smallest k-th key over
 // the chunks of query j, bounds its merged k-th key, so a list whose first key
 // exceeds B_j contributes nothing. The first and k-th keys of all lists of the
 // tile are fetched together and staged in LDS; the contributing lists are then
 // fetched eight at a time, over all queries of the tile, and merged into the
 // query's list with the exchange steps of the kNN kernel.
+constexpr int MERGE_SPLIT = 4;
+
 __global__ __launch_bounds__(64) void knn_merge_kernel(Plan P, int kk) {
     __shared__ unsigned long long s_fk[QPW * KNN_NCH_MAX * 2];
     __shared__ unsigned long long s_lst[QPW * 64];
     const uint32_t lane = threadIdx.x;
     const uint32_t k = (uint32_t)kk;
     const uint32_t nci = P.ctr->n_chunked_items;
-    for (uint32_t it = blockIdx.x; it < nci; it += gridDim.x) {
+    for (uint32_t u = blockIdx.x; u < nci * MERGE_SPLIT; u += gridDim.x) {
+        const uint32_t it = u / MERGE_SPLIT, part = u % MERGE_SPLIT;
         const KnnItem w = P.items[it];
         if (w.chunk != 0u) continue;
+        // this wave's share of the tile's queries
+        const uint32_t q0 = w.q0 + part * (uint32_t)(KNN_TQ / MERGE_SPLIT);
+        if (q0 >= w.q1) continue;
+        const uint32_t q1 = min(w.q1, q0 + (uint32_t)(KNN_TQ / MERGE_SPLIT));
         const uint32_t t = w.leaf;
         const uint32_t nch = P.leaf_nch[t];
         const uint32_t qb = P.p1pos[P.leaf_begin[t]];
-        const uint32_t qn = w.q1 - w.q0;
+        const uint32_t qn = q1 - q0;
         const unsigned long long* base = (const unsigned long long*)P.plist + (size_t)P.leaf_plist[t] * k;
         const uint32_t tot = qn * nch;
         for (uint32_t e0 = 0; e0 < tot; e0 += 256u) {
@@ -616,7 +624,7 @@ __global__ __launch_bounds__(64) void knn_merge_kernel(Plan P, int kk) {
                 const uint32_t e = e0 + (uint32_t)b * 64u + lane;
                 if (e < tot) {
                     const uint32_t j = e / nch, c = e - j * nch;
-                    const unsigned long long* l = base + ((size_t)(w.q0 + j - qb) * nch + c) * k;
+                    const unsigned long long* l = base + ((size_t)(q0 + j - qb) * nch + c) * k;
                     f[b] = l[0];
                     kt[b] = l[k - 1];
                 }
@@ -666,7 +674,7 @@ __global__ __launch_bounds__(64) void knn_merge_kernel(Plan P, int kk) {
                     for (uint32_t r = p - (uint32_t)__builtin_amdgcn_readlane((int)excl, (int)j); r > 0u; --r)
                         bits &= bits - 1u;
                     const uint32_t c = (uint32_t)__ffs((int)bits) - 1u;
-                    if (lane < k) pv[b] = base[((size_t)(w.q0 + j - qb) * nch + c) * k + lane];
+                    if (lane < k) pv[b] = base[((size_t)(q0 + j - qb) * nch + c) * k + lane];
                     pj[b] = j;
                 }
             }
@@ -683,7 +691,7 @@ __global__ __launch_bounds__(64) void knn_merge_kernel(Plan P, int kk) {
         }
         for (uint32_t j = 0; j < qn; ++j) {
             const unsigned long long v = lane < k ? s_lst[j * 64u + lane] : KEY_EMPTY;
-            write_final(P, w.q0 + j, k, lane, v);
+            write_final(P, q0 + j, k, lane, v);
         }
         wave_lds_fence();
     }
