@@ -161,6 +161,62 @@ __global__ __launch_bounds__(256) void bbox_kernel(const float* __restrict__ xyz
     }
 }
 
+// A single frame with few points: each wave reduces its 512-point chunks,
+// the block combines its four waves in LDS and adds one box per block with
+// atomics (a quarter of the atomics of one box per wave, all of them on the
+// same six words, which is what bounds the one-box-per-wave form).
+__global__ __launch_bounds__(256) void bbox_one_kernel(const float* __restrict__ xyz, Plan P, uint32_t chunk) {
+    __shared__ float s_mn[4][3], s_mx[4][3];
+    __shared__ uint32_t s_bad[4];
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t n = P.n, nchunks = (n + chunk - 1) / chunk;
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    uint32_t bad = 0;
+    for (uint32_t c = wid; c < nchunks; c += nw) {
+        const uint32_t end = min(n, (c + 1u) * chunk);
+        for (uint32_t i = c * chunk + lane; i < end; i += 64u) {
+            const float x = xyz[3 * (size_t)i], y = xyz[3 * (size_t)i + 1], z = xyz[3 * (size_t)i + 2];
+            if (isfinite(x) && isfinite(y) && isfinite(z)) {
+                mn[0] = fminf(mn[0], x); mx[0] = fmaxf(mx[0], x);
+                mn[1] = fminf(mn[1], y); mx[1] = fmaxf(mx[1], y);
+                mn[2] = fminf(mn[2], z); mx[2] = fmaxf(mx[2], z);
+            } else {
+                ++bad;
+            }
+        }
+    }
+    bbox_reduce_wave(mn, mx, bad);
+    if (lane == 0u) {
+        for (int a = 0; a < 3; ++a) {
+            s_mn[wave][a] = mn[a];
+            s_mx[wave][a] = mx[a];
+        }
+        s_bad[wave] = bad;
+    }
+    __syncthreads();
+    FrameStat* fs = P.fstat;
+    if (threadIdx.x < 3u) {
+        const uint32_t a = threadIdx.x;
+        float lo = s_mn[0][a], hi = s_mx[0][a];
+        for (int w = 1; w < 4; ++w) {
+            lo = fminf(lo, s_mn[w][a]);
+            hi = fmaxf(hi, s_mx[w][a]);
+        }
+        if (lo <= hi) {
+            atomicMax(&fs->bbox_nmin[a], ~f32_ordered(lo));
+            atomicMax(&fs->bbox_max[a], f32_ordered(hi));
+        }
+    }
+    if (threadIdx.x == 3u) {
+        const uint32_t b = s_bad[0] + s_bad[1] + s_bad[2] + s_bad[3];
+        if (b) {
+            atomicAdd(&fs->nonfinite, b);
+            atomicOr(&P.ctr->status, DEV_NONFINITE);
+        }
+    }
+}
+
 // One wave per frame: fold the frame's whole chunks into its accumulators.
 __global__ __launch_bounds__(256) void bbox_fold_kernel(Plan P) {
     const uint32_t lane = threadIdx.x & 63u;
@@ -202,6 +258,10 @@ void launch_bbox(const Plan& P, const float* xyz, hipStream_t st) {
     unsigned blocks = (nchunks + 3) / 4;
     if (blocks > 2048) blocks = 2048;
     if (blocks == 0) blocks = 1;
+    if (direct && P.nf == 1) {
+        hipLaunchKernelGGL(bbox_one_kernel, dim3(blocks), dim3(256), 0, st, xyz, P, chunk);
+        return;
+    }
     hipLaunchKernelGGL(bbox_kernel, dim3(blocks), dim3(256), 0, st, xyz, P, direct, chunk);
     if (direct) return;
     unsigned fb = (P.nf + 3) / 4;
