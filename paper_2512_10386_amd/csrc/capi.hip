@@ -338,8 +338,7 @@ static gdn_status run(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int64
     gdn::launch_bbox(P, xyz, st);
     gdn::launch_morton(P, prm, xyz, st);
     gdn::launch_sort(P, prm, st);
-    gdn::launch_permute(P, xyz, st);
-    gdn::launch_leaves(P, prm, st);
+    gdn::launch_leaves(P, prm, xyz, st);
     gdn::launch_voxel(P, prm, st);
     gdn::launch_p1_compact(P, st);
     gdn::launch_halo(P, prm, st);

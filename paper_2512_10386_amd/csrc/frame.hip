@@ -1,7 +1,7 @@
 // Frame-level passes: zero-fill of the workspace control block, the frame
 // bounding box (the octree root cube, Sec. 3 with Eq. 2), 63-bit Morton keys,
-// the stable LSD radix sort of (key, original index) and the gather of the
-// sorted coordinates.
+// the stable LSD radix sort of (key, original index) on the digits the octree
+// needs, and the whole-key re-sort of deep level-10 cells.
 #include "kernels.hpp"
 
 namespace gdn {
@@ -648,22 +648,6 @@ void launch_sort(const Plan& P, const Params& prm, hipStream_t st) {
     if (blocks > 4096) blocks = 4096;
     if (blocks == 0) blocks = 1;
     hipLaunchKernelGGL(deep_cells_kernel, dim3(blocks), dim3(SEG_BLOCK), 0, st, P, (uint32_t)prm.leaf_cap);
-}
-
-// ---------------------------------------------------------------- permute
-
-__global__ __launch_bounds__(256) void permute_kernel(const float* __restrict__ xyz, Plan P) {
-    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < P.n; s += gridDim.x * blockDim.x) {
-        uint32_t i = P.idx_a[s];
-        P.pos4[s] = make_float4(xyz[3 * (size_t)i], xyz[3 * (size_t)i + 1], xyz[3 * (size_t)i + 2],
-                                __uint_as_float(i));
-    }
-}
-
-void launch_permute(const Plan& P, const float* xyz, hipStream_t st) {
-    unsigned blocks = (P.n + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(permute_kernel, dim3(blocks), dim3(256), 0, st, xyz, P);
 }
 
 }  // namespace gdn

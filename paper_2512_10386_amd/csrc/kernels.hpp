@@ -8,16 +8,16 @@ struct gdn_ctx;
 namespace gdn {
 
 // frame.hip: zero-fill, frame table, frame bboxes, Morton keys, radix sort (and
-// the re-sort of deep level-10 cells), permute
+// the re-sort of deep level-10 cells)
 void launch_zero(const Plan& P, hipStream_t st);
 void launch_frames(const Plan& P, const int64_t* frame_off, hipStream_t st);
 void launch_bbox(const Plan& P, const float* xyz, hipStream_t st);
 void launch_morton(const Plan& P, const Params& prm, const float* xyz, hipStream_t st);
 void launch_sort(const Plan& P, const Params& prm, hipStream_t st);
-void launch_permute(const Plan& P, const float* xyz, hipStream_t st);
 
-// octree.hip: leaves, voxel filter, P1 compaction, halo ranges, kNN plan
-void launch_leaves(const Plan& P, const Params& prm, hipStream_t st);
+// octree.hip: sorted coordinates and leaves, voxel filter, P1 compaction, halo
+// ranges, kNN plan
+void launch_leaves(const Plan& P, const Params& prm, const float* xyz, hipStream_t st);
 void launch_voxel(const Plan& P, const Params& prm, hipStream_t st);
 void launch_p1_compact(const Plan& P, hipStream_t st);
 void launch_halo(const Plan& P, const Params& prm, hipStream_t st);

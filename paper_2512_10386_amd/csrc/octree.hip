@@ -85,9 +85,13 @@ __device__ __forceinline__ int leaf_level_of(const Plan& P, uint32_t s, uint32_t
 }
 
 // The boundary tests run one thread per position (each is a chain of
-// dependent loads); the scan then only reads the flags.
-__global__ __launch_bounds__(256) void boundary_flag_kernel(Plan P, uint32_t cap) {
+// dependent loads); the scan then only reads the flags. The same pass
+// gathers the points' coordinates into sorted order (pos4: x, y, z and the
+// original index's bits).
+__global__ __launch_bounds__(256) void boundary_flag_kernel(Plan P, uint32_t cap, const float* __restrict__ xyz) {
     for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < P.n; j += gridDim.x * blockDim.x) {
+        const uint32_t i = P.idx_a[j];
+        P.pos4[j] = make_float4(xyz[3 * (size_t)i], xyz[3 * (size_t)i + 1], xyz[3 * (size_t)i + 2], __uint_as_float(i));
         const uint32_t f = frame_of_sorted(P, j);
         P.bflag[j] = (uint8_t)leaf_boundary(P.keys_a, j, P.foff[f], P.foff[f + 1], P.fc[f].dmax, P.deepf[j] != 0u,
                                             cap);
@@ -99,10 +103,10 @@ struct FlagGet {
     __device__ uint32_t operator()(uint32_t j) const { return f[j]; }
 };
 
-void launch_leaves(const Plan& P, const Params& prm, hipStream_t st) {
+void launch_leaves(const Plan& P, const Params& prm, const float* xyz, hipStream_t st) {
     unsigned blocks = (P.n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(boundary_flag_kernel, dim3(blocks), dim3(256), 0, st, P, (uint32_t)prm.leaf_cap);
+    hipLaunchKernelGGL(boundary_flag_kernel, dim3(blocks), dim3(256), 0, st, P, (uint32_t)prm.leaf_cap, xyz);
     BoundaryEmit e{P.leaf_of, P.leaf_begin};
     BoundaryFin f{P.ctr, P.leaf_begin, P.n};
     launch_scan(FlagGet{P.bflag}, e, f, nullptr, P.n, P.scan_status, &P.ctr->scan_tile_ctr[0], &P.ctr->status, st);
