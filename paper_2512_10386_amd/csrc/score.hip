@@ -475,27 +475,34 @@ __global__ __launch_bounds__(256) void score_kernel(Plan P, int kk, double eps, 
     const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
     for (uint32_t q0 = wid * qpw; q0 < np1; q0 += nw * qpw) {
         const uint32_t qi = q0 + seg;
-        const bool live = qi < np1 && P.p2[qi];
+        uint32_t j = 0xFFFFFFFFu;
+        bool live = false;
+        float4 a;
+        double2 af;
+        if (qi < np1) {
+            // every load but the neighbour's record is issued up front, so the
+            // flag, the neighbour index and the query's values do not wait on
+            // each other; the query comes from its sorted copy and the
+            // neighbour from its record (both bit copies of the input)
+            live = P.p2[qi] != 0;
+            if (r < k) j = P.nbr[(size_t)qi * k + r];
+            a = P.cand4[qi];
+            af = P.afac_c[qi];
+        }
+        if (!live) j = 0xFFFFFFFFu;
         double term = 0.0;
-        if (live && r < k) {
-            const uint32_t j = P.nbr[(size_t)qi * k + r];
-            if (j < P.n) {
-                // the query from its sorted copy, the neighbour from its record
-                // (both bit copies of the input coordinates)
-                const float4 a = P.cand4[qi];
-                const NbrRec R = P.rec_o[j];
-                const double dx = (double)R.p.x - (double)a.x;
-                const double dy = (double)R.p.y - (double)a.y;
-                const double dz = (double)R.p.z - (double)a.z;
-                const double d2 = dx * dx + dy * dy + dz * dz;
-                const double2 af = P.afac_c[qi];
-                const double w_den = af.x * R.gpow;
-                const double w_dis = (d2 == 0.0) ? 1.0 : exp(-(d2 * af.y));
-                double kern;
-                if constexpr (G2) kern = 1.0 / (d2 + eps);
-                else kern = pow(d2 + eps, -gamma / 2.0);
-                term = w_den * w_dis * kern;
-            }
+        if (j < P.n) {
+            const NbrRec R = P.rec_o[j];
+            const double dx = (double)R.p.x - (double)a.x;
+            const double dy = (double)R.p.y - (double)a.y;
+            const double dz = (double)R.p.z - (double)a.z;
+            const double d2 = dx * dx + dy * dy + dz * dz;
+            const double w_den = af.x * R.gpow;
+            const double w_dis = (d2 == 0.0) ? 1.0 : exp(-(d2 * af.y));
+            double kern;
+            if constexpr (G2) kern = 1.0 / (d2 + eps);
+            else kern = pow(d2 + eps, -gamma / 2.0);
+            term = w_den * w_dis * kern;
         }
         const double F = seg_sum(term, kp);
         if (live && r == 0) P.score_c[qi] = F;
