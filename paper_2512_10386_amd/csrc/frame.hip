@@ -473,6 +473,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
         // scattering from registers.
         __shared__ uint64_t s_k[SORT_BLOCK * ITEMS];
         __shared__ uint32_t s_v[SORT_BLOCK * ITEMS];
+        __shared__ uint8_t s_dg[SORT_BLOCK * ITEMS];  // frame digits, found once per element
         __shared__ uint32_t s_toff[256];
         uint32_t ttot;
         const uint32_t tex = block_excl_scan(tcnt, s_scan, &ttot);
@@ -485,14 +486,14 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
                 const uint32_t lp = s_toff[d] + s_w[wave][d] + rank[i];
                 s_k[lp] = key[i];
                 s_v[lp] = val[i];
+                if (pass >= SORT_PASSES) s_dg[lp] = (uint8_t)d;
             }
         }
         __syncthreads();
         for (uint32_t p = tid; p < ttot; p += SORT_BLOCK) {
             const uint64_t kk = s_k[p];
             const uint32_t vv = s_v[p];
-            const uint32_t d = pass < SORT_PASSES ? (uint32_t)((kk >> shift) & 255u)
-                                                  : (frame_of(foff, nf, vv) >> (8 * (pass - SORT_PASSES))) & 255u;
+            const uint32_t d = pass < SORT_PASSES ? (uint32_t)((kk >> shift) & 255u) : (uint32_t)s_dg[p];
             const uint32_t o = s_base[d] + (p - s_toff[d]);
             if (o < n) {  // always true unless a look-back wait expired
                 kout[o] = kk;
