@@ -15,6 +15,7 @@ constexpr uint32_t SORT_BIG_N = 1u << 20;     // above: 16 keys per thread, else
 constexpr int SORT_PASSES = 8;                // 8-bit digits over the 63-bit key
 constexpr int SORT_FRAME_PASSES_MAX = 2;      // 8-bit digits of the frame id (batches)
 constexpr int SORT_PASSES_MAX = SORT_PASSES + SORT_FRAME_PASSES_MAX;
+constexpr uint32_t SORT_FOFF_LDS = 2048;      // frame offsets staged in LDS by frame passes (nf < this)
 // Short sort: the radix passes cover only digits 4..7 (key bits 32..62),
 // which hold every level-10 cell prefix (bits 33..62); the points end in
 // (frame, bits 32..62, original index) order. A level-10 cell that holds

@@ -367,8 +367,13 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
     __shared__ uint32_t s_w[SORT_BLOCK / 64][256];
     __shared__ uint32_t s_base[256];
     __shared__ uint32_t s_scan[SORT_BLOCK / 64 + 1];
+    __shared__ uint32_t s_foff[SORT_FOFF_LDS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int shift = 8 * pass;
+    // frame passes of batches with few frames search the offsets in LDS
+    const bool foff_lds = pass >= SORT_PASSES && nf < SORT_FOFF_LDS;
+    if (foff_lds)
+        for (uint32_t i = tid; i <= nf; i += SORT_BLOCK) s_foff[i] = foff[i];
     for (int i = tid; i < (SORT_BLOCK / 64) * 256; i += SORT_BLOCK) (&s_w[0][0])[i] = 0u;
     if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
     __syncthreads();
@@ -383,8 +388,14 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
         bool ok = pos < n;
         key[i] = ok ? kin[pos] : 0ull;
         val[i] = ok ? vin[pos] : 0u;
-        const uint32_t d = pass < SORT_PASSES ? (uint32_t)((key[i] >> shift) & 255u)
-                                              : (frame_of(foff, nf, ok ? val[i] : 0u) >> (8 * (pass - SORT_PASSES))) & 255u;
+        uint32_t d;
+        if (pass < SORT_PASSES) {
+            d = (uint32_t)((key[i] >> shift) & 255u);
+        } else {
+            const uint32_t v = ok ? val[i] : 0u;
+            const uint32_t f = foff_lds ? frame_of(s_foff, nf, v) : frame_of(foff, nf, v);
+            d = (f >> (8 * (pass - SORT_PASSES))) & 255u;
+        }
         dig[i] = ok ? d : 256u;
     }
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));

@@ -148,10 +148,12 @@ def test_batch_frame_against_oracle(bden, oracle):
         assert np.allclose(o["score"][a:b][m], F[m], rtol=1e-5, atol=0)
 
 
-def test_many_tiny_frames_two_frame_digits(bden, den):
-    # more than 256 frames: the sort takes two frame-id digits
-    rng = np.random.default_rng(8)
-    sizes = rng.integers(0, 40, 300)
+@pytest.mark.parametrize("nframes", [300, 2100])
+def test_many_tiny_frames_two_frame_digits(bden, den, nframes):
+    # more than 256 frames: the sort takes two frame-id digits; up to 2047
+    # frames its frame passes search the offsets in LDS, beyond in memory
+    rng = np.random.default_rng(8 if nframes == 300 else nframes)
+    sizes = rng.integers(0, 40, nframes)
     frames = [synth.uniform_cube(100 + i, int(s))[0] if s else np.zeros((0, 3), np.float32)
               for i, s in enumerate(sizes)]
     params = dict(k=4, leaf_cap=8, min_vox_count=1)
