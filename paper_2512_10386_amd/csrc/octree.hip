@@ -89,12 +89,27 @@ __device__ __forceinline__ int leaf_level_of(const Plan& P, uint32_t s, uint32_t
 // gathers the points' coordinates into sorted order (pos4: x, y, z and the
 // original index's bits).
 __global__ __launch_bounds__(256) void boundary_flag_kernel(Plan P, uint32_t cap, const float* __restrict__ xyz) {
+    // batches of fewer than SORT_FOFF_LDS frames search the offsets in LDS
+    __shared__ uint32_t s_foff[SORT_FOFF_LDS];
+    const bool lds = P.nf > 1u && P.nf < SORT_FOFF_LDS;
+    if (lds) {
+        for (uint32_t i = threadIdx.x; i <= P.nf; i += blockDim.x) s_foff[i] = P.foff[i];
+        __syncthreads();
+    }
     for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < P.n; j += gridDim.x * blockDim.x) {
         const uint32_t i = P.idx_a[j];
         P.pos4[j] = make_float4(xyz[3 * (size_t)i], xyz[3 * (size_t)i + 1], xyz[3 * (size_t)i + 2], __uint_as_float(i));
-        const uint32_t f = frame_of_sorted(P, j);
-        P.bflag[j] = (uint8_t)leaf_boundary(P.keys_a, j, P.foff[f], P.foff[f + 1], P.fc[f].dmax, P.deepf[j] != 0u,
-                                            cap);
+        uint32_t f, fs, fe;
+        if (lds) {
+            f = frame_of(s_foff, P.nf, j);
+            fs = s_foff[f];
+            fe = s_foff[f + 1];
+        } else {
+            f = frame_of_sorted(P, j);
+            fs = P.foff[f];
+            fe = P.foff[f + 1];
+        }
+        P.bflag[j] = (uint8_t)leaf_boundary(P.keys_a, j, fs, fe, P.fc[f].dmax, P.deepf[j] != 0u, cap);
     }
 }
 
