@@ -609,13 +609,25 @@ __global__ __launch_bounds__(SEG_BLOCK) void deep_cells_kernel(Plan P, uint32_t 
     __shared__ uint32_t s_scan[SEG_BLOCK / 64 + 1];
     __shared__ uint2 s_seg[SEG_BLOCK / 2];  // cells are >= 2 points long, so at most half the positions start one
     __shared__ uint32_t s_nseg;
+    __shared__ uint32_t s_foff[SORT_FOFF_LDS];  // batches of fewer frames search the offsets here
+    const bool lds = P.nf > 1u && P.nf < SORT_FOFF_LDS;
+    if (lds)
+        for (uint32_t i = threadIdx.x; i <= P.nf; i += blockDim.x) s_foff[i] = P.foff[i];
     for (uint32_t base = blockIdx.x * SEG_BLOCK; base < P.n; base += gridDim.x * SEG_BLOCK) {
         if (threadIdx.x == 0) s_nseg = 0u;
         __syncthreads();
         const uint32_t s = base + threadIdx.x;
         if (s < P.n) {
-            const uint32_t f = P.nf > 1 ? frame_of(P.foff, P.nf, s) : 0u;
-            const uint32_t fs = P.foff[f], fe = P.foff[f + 1];
+            uint32_t f = 0u, fs, fe;
+            if (lds) {
+                f = frame_of(s_foff, P.nf, s);
+                fs = s_foff[f];
+                fe = s_foff[f + 1];
+            } else {
+                if (P.nf > 1u) f = frame_of(P.foff, P.nf, s);
+                fs = P.foff[f];
+                fe = P.foff[f + 1];
+            }
             const uint64_t c = P.keys_a[s] >> CELL_SHIFT;
             const bool start = P.fc[f].dmax > SORT_SHORT_LEVEL && (s == fs || (P.keys_a[s - 1] >> CELL_SHIFT) != c) &&
                                (uint64_t)s + cap < fe && (P.keys_a[s + cap] >> CELL_SHIFT) == c;
