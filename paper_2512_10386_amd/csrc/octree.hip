@@ -459,14 +459,27 @@ __global__ __launch_bounds__(256) void halo_kernel(Plan P, uint32_t cap) {
     // this thread's half of the wave
     const unsigned long long half = (lane & 32u) ? 0xFFFFFFFF00000000ull : 0x00000000FFFFFFFFull;
     const unsigned long long below = lane == 0u ? 0ull : (~0ull >> (64u - lane));
+    __shared__ uint32_t s_foff[SORT_FOFF_LDS];  // batches of fewer frames search the offsets here
+    const bool lds = P.nf > 1u && P.nf < SORT_FOFF_LDS;
+    if (lds)
+        for (uint32_t i = threadIdx.x; i <= P.nf; i += blockDim.x) s_foff[i] = P.foff[i];
+    __syncthreads();
     for (uint32_t base = blockIdx.x * HALO_LEAVES; base < nl; base += gridDim.x * HALO_LEAVES) {
         const uint32_t t = base + grp;
         const bool live = t < nl;
         uint2 r = make_uint2(0u, 0u);
         if (live && g < HALO) {
             const uint32_t lb = P.leaf_begin[t], le = P.leaf_begin[t + 1];
-            const uint32_t f = frame_of_sorted(P, lb);
-            const uint32_t fs = P.foff[f], fe = P.foff[f + 1];
+            uint32_t f, fs, fe;
+            if (lds) {
+                f = frame_of(s_foff, P.nf, lb);
+                fs = s_foff[f];
+                fe = s_foff[f + 1];
+            } else {
+                f = frame_of_sorted(P, lb);
+                fs = P.foff[f];
+                fe = P.foff[f + 1];
+            }
             const int d = leaf_level_of(P, lb, le, fs, fe, P.fc[f].dmax, cap);
             const uint64_t pre = P.keys_a[lb] >> (3 * (MORTON_BITS - d));
             if (g == 0) {
