@@ -229,6 +229,17 @@ static void topk_push(float *bd, uint32_t *bi, int *cnt, int k, float d2, uint32
     bi[pos] = j;
 }
 
+/* ------------------------------------------------------------- halo block */
+
+/* Point i's cell at the level whose shift is sh lies within one cell of c on
+ * every axis. Cells outside [0, 2^d) hold no points, so the block is clipped
+ * at the grid border without a separate test. */
+static int in_block(const uint32_t *q, int64_t i, int sh, const int64_t *c)
+{
+    int64_t px = (int64_t)(q[3 * i] >> sh), py = (int64_t)(q[3 * i + 1] >> sh), pz = (int64_t)(q[3 * i + 2] >> sh);
+    return llabs(px - c[0]) <= 1 && llabs(py - c[1]) <= 1 && llabs(pz - c[2]) <= 1;
+}
+
 /* ------------------------------------------------------------ percentile */
 
 /* MATLAB prctile places the i-th smallest of n values at percentile
@@ -371,36 +382,41 @@ int orc_denoise(const float *xyz, int64_t n, const orc_params *p, orc_out *o)
     }
 
     /* Candidate set of each leaf: the P1 points whose level-d cell lies in
-     * the 3x3x3 block of cells around the leaf's cell. */
-    int64_t *cand_off = malloc(sizeof(int64_t) * (size_t)(NL + 1));
-    uint32_t *qoff_cnt = calloc((size_t)NL, sizeof(uint32_t));
-    cand_off[0] = 0;
+     * the 3x3x3 block of cells around the leaf's cell (level d = the leaf's
+     * level; cell coordinates = the 21-bit grid coordinates shifted down by
+     * 21 - d). Leaves are independent, so both passes run in parallel over
+     * leaves; the offsets between them are a plain prefix sum. */
+    int *cell_sh = malloc(sizeof(int) * (size_t)(NL > 0 ? NL : 1));
+    int64_t *cell = malloc(sizeof(int64_t) * 3 * (size_t)(NL > 0 ? NL : 1));
     for (int64_t l = 0; l < NL; ++l) {
-        int d = (int)L[l].level, sh = MORTON_BITS - d;
+        cell_sh[l] = MORTON_BITS - (int)L[l].level;
         uint32_t f = sidx[L[l].begin];
-        int64_t cx = q[3 * (size_t)f] >> sh, cy = q[3 * (size_t)f + 1] >> sh, cz = q[3 * (size_t)f + 2] >> sh;
-        int64_t cnt = 0;
-        for (int64_t i = 0; i < n; ++i) {
-            if (!p1[i]) continue;
-            int64_t px = q[3 * i] >> sh, py = q[3 * i + 1] >> sh, pz = q[3 * i + 2] >> sh;
-            if (llabs(px - cx) <= 1 && llabs(py - cy) <= 1 && llabs(pz - cz) <= 1) ++cnt;
-        }
-        cand_off[l + 1] = cand_off[l] + cnt;
+        for (int a = 0; a < 3; ++a) cell[3 * l + a] = (int64_t)(q[3 * (size_t)f + a] >> cell_sh[l]);
     }
-    uint32_t *cand = malloc(sizeof(uint32_t) * (size_t)(cand_off[NL] > 0 ? cand_off[NL] : 1));
+    int64_t *cand_off = malloc(sizeof(int64_t) * (size_t)(NL + 1));
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
     for (int64_t l = 0; l < NL; ++l) {
-        int d = (int)L[l].level, sh = MORTON_BITS - d;
-        uint32_t f = sidx[L[l].begin];
-        int64_t cx = q[3 * (size_t)f] >> sh, cy = q[3 * (size_t)f + 1] >> sh, cz = q[3 * (size_t)f + 2] >> sh;
+        int64_t cnt = 0;
+        for (int64_t i = 0; i < n; ++i)
+            if (p1[i] && in_block(q, i, cell_sh[l], cell + 3 * l)) ++cnt;
+        cand_off[l + 1] = cnt;
+    }
+    cand_off[0] = 0;
+    for (int64_t l = 0; l < NL; ++l) cand_off[l + 1] += cand_off[l];
+    uint32_t *cand = malloc(sizeof(uint32_t) * (size_t)(cand_off[NL] > 0 ? cand_off[NL] : 1));
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t l = 0; l < NL; ++l) {
         int64_t w = cand_off[l];
-        for (int64_t i = 0; i < n; ++i) {
-            if (!p1[i]) continue;
-            int64_t px = q[3 * i] >> sh, py = q[3 * i + 1] >> sh, pz = q[3 * i + 2] >> sh;
-            if (llabs(px - cx) <= 1 && llabs(py - cy) <= 1 && llabs(pz - cz) <= 1) cand[w++] = (uint32_t)i;
-        }
+        for (int64_t i = 0; i < n; ++i)
+            if (p1[i] && in_block(q, i, cell_sh[l], cell + 3 * l)) cand[w++] = (uint32_t)i;
         if (o->leaf_ncand) o->leaf_ncand[l] = (uint32_t)(cand_off[l + 1] - cand_off[l]);
     }
-    free(qoff_cnt);
+    free(cell_sh);
+    free(cell);
 
     /* Queries: the P1 points of each leaf. */
     uint32_t *queries = malloc(sizeof(uint32_t) * (size_t)n);

@@ -57,27 +57,43 @@ class Out(C.Structure):
 _lib = None
 
 
+def _configure(h: C.CDLL) -> C.CDLL:
+    h.orc_denoise.argtypes = [_P, C.c_int64, C.POINTER(Params), C.POINTER(Out)]
+    h.orc_denoise.restype = C.c_int
+    h.orc_default_params.argtypes = [C.POINTER(Params)]
+    h.orc_morton_interleave.argtypes = [C.c_uint32] * 3
+    h.orc_morton_interleave.restype = C.c_uint64
+    h.orc_percentile_rank.argtypes = [C.c_int64, C.c_double]
+    h.orc_percentile_rank.restype = C.c_int64
+    h.orc_fit_loss_grad.argtypes = [_P, C.c_int64, C.c_int, C.c_double, C.POINTER(Out), _P,
+                                    C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, _P]
+    h.orc_fit_loss_grad.restype = C.c_int
+    h.orc_nearest.argtypes = [_P, C.c_int64, _P, C.c_int64, _P, _P]
+    h.orc_nearest.restype = C.c_int
+    h.orc_eval_metrics.argtypes = [_P, C.c_int64, _P, C.c_int64, _P]
+    h.orc_eval_metrics.restype = C.c_int
+    return h
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        _lib = C.CDLL(LIB_PATH)
-        _lib.orc_denoise.argtypes = [_P, C.c_int64, C.POINTER(Params), C.POINTER(Out)]
-        _lib.orc_denoise.restype = C.c_int
-        _lib.orc_default_params.argtypes = [C.POINTER(Params)]
-        _lib.orc_morton_interleave.argtypes = [C.c_uint32] * 3
-        _lib.orc_morton_interleave.restype = C.c_uint64
-        _lib.orc_percentile_rank.argtypes = [C.c_int64, C.c_double]
-        _lib.orc_percentile_rank.restype = C.c_int64
-        _lib.orc_fit_loss_grad.argtypes = [_P, C.c_int64, C.c_int, C.c_double, C.POINTER(Out), _P,
-                                           C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, _P]
-        _lib.orc_fit_loss_grad.restype = C.c_int
-        _lib.orc_nearest.argtypes = [_P, C.c_int64, _P, C.c_int64, _P, _P]
-        _lib.orc_nearest.restype = C.c_int
-        _lib.orc_eval_metrics.argtypes = [_P, C.c_int64, _P, C.c_int64, _P]
-        _lib.orc_eval_metrics.restype = C.c_int
+        _lib = _configure(C.CDLL(LIB_PATH))
     return _lib
+
+
+def build_variant(source_text: str, out_path: str) -> C.CDLL:
+    """Compile a modified copy of the oracle source (tests that plant a
+    mistake in the oracle use this to show that a pin catches it) and load it.
+    The regular library is left untouched."""
+    src = out_path + ".c"
+    with open(src, "w") as f:
+        f.write(source_text)
+    cmd = ["gcc", *CFLAGS, "-I", HERE, src, "-o", out_path, "-lm"]
+    subprocess.run(cmd, check=True, capture_output=True)
+    return _configure(C.CDLL(out_path))
 
 
 def default_params() -> dict:
@@ -94,8 +110,11 @@ def percentile_rank(n: int, q: float) -> int:
     return int(lib().orc_percentile_rank(n, q))
 
 
-def denoise(xyz: np.ndarray, **params) -> dict:
+def denoise(xyz: np.ndarray, *, handle: C.CDLL | None = None, **params) -> dict:
     """Run the whole oracle pipeline; returns every intermediate array.
+
+    ``handle`` selects another build of the oracle (``build_variant``); by
+    default the regular library is used.
 
     Per-point arrays are in original point order. Rows of ``nbr_idx`` /
     ``nbr_d2`` / ``r2k`` / ``rho`` for points outside P1 are left at their
@@ -128,7 +147,8 @@ def denoise(xyz: np.ndarray, **params) -> dict:
         leaf_rho_med=np.zeros(m, np.float64), leaf_ncand=np.zeros(m, np.uint32),
     )
     o = Out(**{name: arr.ctypes.data for name, arr in a.items()})
-    rc = lib().orc_denoise(xyz.ctypes.data if n else None, n, C.byref(P), C.byref(o))
+    h = lib() if handle is None else handle
+    rc = h.orc_denoise(xyz.ctypes.data if n else None, n, C.byref(P), C.byref(o))
     if rc != 0:
         raise ValueError("oracle rejected the parameters")
     nl = o.n_leaves
