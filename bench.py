@@ -52,9 +52,11 @@ def knn_traffic(knn_ms_launch):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(xyz, params, budget_s=12.0):
+def cpu_baseline(xyz, params, workload, budget_s=12.0, single_budget_s=10.0):
     """The CPU oracle, as it stands, on the host cores: whole frames until the
-    time budget is used (at least one)."""
+    time budget is used (at least one); then the same with one thread, in a
+    child process started with OMP_NUM_THREADS=1."""
+    import subprocess
     from oracle import oracle as O
     O.build()
     reps, t0 = 0, time.perf_counter()
@@ -66,10 +68,32 @@ def cpu_baseline(xyz, params, budget_s=12.0):
         el = time.perf_counter() - t0
         if el >= budget_s or reps >= 30:
             break
-    return {"value": round(xyz.shape[0] * reps / el / 1e6, 4), "unit": "Mpoints/s",
-            "cores": int(threads), "kind": "oracle",
-            "sample": f"{reps} full frames of the same workload ({xyz.shape[0]} points each), "
-                      f"{el:.1f} s wall"}
+    rec = {"value": round(xyz.shape[0] * reps / el / 1e6, 4), "unit": "Mpoints/s",
+           "cores": int(threads), "kind": "oracle",
+           "sample": f"{reps} full frames of the same workload ({xyz.shape[0]} points each), "
+                     f"{el:.1f} s wall"}
+    child = (
+        "import sys, time, json\n"
+        f"sys.path.insert(0, {ROOT!r})\n"
+        "from oracle import oracle as O\n"
+        "from paper_2512_10386_amd import synth\n"
+        f"xyz, _, p = synth.make({workload!r})\n"
+        "reps, t0 = 0, time.perf_counter()\n"
+        "while True:\n"
+        "    r = O.denoise(xyz, **p); reps += 1; el = time.perf_counter() - t0\n"
+        f"    if el >= {single_budget_s} or reps >= 10: break\n"
+        "print(json.dumps(dict(reps=reps, el=el, n=int(xyz.shape[0]), threads=int(r['threads']))))\n")
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        out = subprocess.run([sys.executable, "-c", child], env=env, capture_output=True, text=True,
+                             timeout=single_budget_s * 6 + 60)
+        one = json.loads(out.stdout.strip().splitlines()[-1])
+        rec["single_thread"] = {"value": round(one["n"] * one["reps"] / one["el"] / 1e6, 4), "unit": "Mpoints/s",
+                                "cores": one["threads"],
+                                "sample": f"{one['reps']} full frames, {one['el']:.1f} s wall"}
+    except (subprocess.SubprocessError, ValueError, IndexError, KeyError) as e:
+        rec["single_thread"] = {"error": str(e)[:200]}
+    return rec
 
 
 def bench_batch(steps):
@@ -112,6 +136,7 @@ def bench_batch(steps):
     gdn_set_timing(bd.ctx, False)
     ms_eager = statistics.fmean(t for t, _ in per)
     knn_ms = statistics.fmean(k for _, k in per)
+    bd.check_status(n)
     counts = bd.dump("COUNTS", n).cpu().numpy()
     pairs = int(counts[2])
     # the same frames as plain single-frame calls, back to back
@@ -263,6 +288,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="lidar_120k")
+    ap.add_argument("--latency-frames", type=int, default=1000, help="solo frames timed for p50/p99")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched (64-frame) leg")
     ap.add_argument("--batch-steps", type=int, default=20)
@@ -330,17 +356,19 @@ def main():
         f"kNN kernel {knn_ms:.4f} ms, call {call_ms:.4f} ms")
     gdn_set_timing(den.ctx, False)
 
-    # frame latency: each frame submitted alone and waited for
+    den.check_status(n)
+
+    # frame latency: each frame submitted alone and waited for (host clock
+    # from the call to the end of a synchronize), over --latency-frames frames
     lat = []
-    for _ in range(args.steps):
+    for _ in range(args.latency_frames):
         s = time.perf_counter()
         den(x, out)
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - s) * 1e3)
-    lat.sort()
-    p50 = lat[len(lat) // 2]
-    p99 = lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]
-    log(f"[bench] latency p50 {p50:.4f} ms p99 {p99:.4f} ms")
+    lat = np.array(lat)
+    p50, p99 = float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+    log(f"[bench] latency over {len(lat)} solo frames: p50 {p50:.4f} ms p99 {p99:.4f} ms max {lat.max():.4f} ms")
 
     flops = pairs * FLOPS_PER_PAIR
     achieved = flops / (knn_ms * 1e-3) / 1e12
@@ -377,7 +405,8 @@ def main():
         "config": {"workload": args.workload, "points": n, "k": params["k"],
                    "leaf_cap": params["leaf_cap"], "frames_per_step": 1, "path": "plain single-frame",
                    "score_dtype": "f64", "leaves": n_leaves, "p1_points": n_p1, "kept": n_kept},
-        "latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4)},
+        "latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4), "frames": int(len(lat)),
+                       "how": "solo frames, host clock from the call to the end of a device synchronize"},
         "roofline": roofline,
     }
     if not args.no_batch:
@@ -389,7 +418,7 @@ def main():
         rec["fit"] = bench_fit(60)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
-        rec["cpu_baseline"] = cpu_baseline(xyz, params)
+        rec["cpu_baseline"] = cpu_baseline(xyz, params, args.workload)
         log(f"[bench] cpu baseline {rec['cpu_baseline']}")
     print(json.dumps(rec, allow_nan=False), flush=True)
 

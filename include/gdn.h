@@ -190,7 +190,10 @@ gdn_status gdn_autotune(gdn_ctx *ctx, gdn_params *p, const int32_t *caps, int nc
  *   gdn_server_poll retires finished batches, then packs waiting frames (in
  *     arrival order) into every free slot and launches them; it never waits
  *     for the GPU. It reports up to max_done finished tickets, and optionally
- *     the queue length and the number of busy slots.
+ *     (done_status, NULL ok) for each the device status word (GDN_DEV_*) of
+ *     the batch it ran in: non-zero means that batch's outputs are
+ *     unspecified; and optionally the queue length and the number of busy
+ *     slots.
  * Results of a frame equal those of gdn_denoise on it alone. Not thread-safe;
  * poll from one thread. After a GDN_EHIP from poll the server is unusable.
  * Destroy waits for running slots, drops frames still queued and frees the
@@ -203,8 +206,8 @@ gdn_status gdn_server_create(gdn_ctx *ctx, const gdn_params *p, size_t hbm_budge
 gdn_status gdn_server_info(gdn_server *s, int *n_slots, size_t *bytes_per_slot);
 gdn_status gdn_server_submit(gdn_server *s, const float *xyz, int64_t n, uint8_t *keep, float *score,
                              uint8_t *stage, uint32_t *kept_idx, int64_t *n_kept, int64_t *ticket);
-gdn_status gdn_server_poll(gdn_server *s, int64_t *done_tickets, int max_done, int *n_done,
-                           int *n_waiting, int *n_busy);
+gdn_status gdn_server_poll(gdn_server *s, int64_t *done_tickets, uint32_t *done_status, int max_done,
+                           int *n_done, int *n_waiting, int *n_busy);
 void gdn_server_destroy(gdn_server *s);
 const char *gdn_server_last_error(gdn_server *s);
 
@@ -306,6 +309,11 @@ gdn_status gdn_timing(gdn_ctx *ctx, int64_t back, float *total_ms, float *knn_ms
 const char *gdn_status_string(gdn_status s);
 /* Message of the last failed call on ctx ("" if none). */
 const char *gdn_last_error(gdn_ctx *ctx);
+
+/* Hex SHA-256 of the sources and flags this library was built from (a static
+ * string; "unknown" if the build did not set it). Loaders compare it with the
+ * sources beside the library to refuse a stale build. */
+const char *gdn_source_hash(void);
 
 #ifdef __cplusplus
 }

@@ -52,13 +52,21 @@ _lib = None
 
 
 def lib():
-    """Load libgdn.so; raise if it is missing (there is no fallback path)."""
+    """Load libgdn.so; raise if it is missing (there is no fallback path) or
+    was built from other sources than the ones beside it."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_2512_10386_amd.build`")
         L = C.CDLL(LIB_PATH)
+        L.gdn_source_hash.argtypes = []
+        L.gdn_source_hash.restype = C.c_char_p
+        from . import build as _build
+        built, now = L.gdn_source_hash().decode(), _build.source_hash()
+        if built != now:
+            raise RuntimeError(f"{LIB_PATH} is stale (built from sources {built[:12]}, the tree holds "
+                               f"{now[:12]}): rebuild it with `python -m paper_2512_10386_amd.build`")
         vp, i64, sz = C.c_void_p, C.c_int64, C.c_size_t
         L.gdn_default_params.argtypes = [C.POINTER(gdn_params)]
         L.gdn_create.argtypes = [C.POINTER(vp), C.c_int]
@@ -77,8 +85,8 @@ def lib():
         L.gdn_server_create.argtypes = [vp, C.POINTER(gdn_params), sz, C.c_int, i64, C.c_int, C.POINTER(vp)]
         L.gdn_server_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(sz)]
         L.gdn_server_submit.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, C.POINTER(i64)]
-        L.gdn_server_poll.argtypes = [vp, C.POINTER(i64), C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
-                                      C.POINTER(C.c_int)]
+        L.gdn_server_poll.argtypes = [vp, C.POINTER(i64), C.POINTER(C.c_uint32), C.c_int, C.POINTER(C.c_int),
+                                      C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.gdn_server_destroy.argtypes = [vp]
         L.gdn_server_destroy.restype = None
         L.gdn_server_last_error.argtypes = [vp]
@@ -216,11 +224,12 @@ def gdn_server_submit(srv, xyz, n, keep, score, stage, kept_idx, n_kept) -> int:
 
 
 def gdn_server_poll(srv, max_done: int = 256):
-    """(finished tickets, queue length, busy slots)"""
+    """(finished tickets, their batches' device status words, queue length, busy slots)"""
     buf = (C.c_int64 * max_done)()
+    sts = (C.c_uint32 * max_done)()
     nd, nw, nb = C.c_int(), C.c_int(), C.c_int()
-    _check_srv(srv, lib().gdn_server_poll(srv, buf, max_done, C.byref(nd), C.byref(nw), C.byref(nb)))
-    return list(buf[:nd.value]), nw.value, nb.value
+    _check_srv(srv, lib().gdn_server_poll(srv, buf, sts, max_done, C.byref(nd), C.byref(nw), C.byref(nb)))
+    return list(buf[:nd.value]), list(sts[:nd.value]), nw.value, nb.value
 
 
 def gdn_server_destroy(srv) -> None:
@@ -343,6 +352,20 @@ class Denoiser:
                     out.keep.data_ptr(), out.score.data_ptr(), out.stage.data_ptr(),
                     out.kept_idx.data_ptr(), out.n_kept.data_ptr(), stream)
         return out
+
+    def check_status(self, n: int) -> int:
+        """Wait for the last call and raise GdnError if the device flagged a
+        condition (GDN_DEV_* bits: non-finite input, an exhausted wait, a bad
+        frame table), whose outputs are unspecified. Returns the status word."""
+        if n == 0:
+            return 0
+        st = int(self.dump("STATUS", n).cpu().item())
+        if st:
+            names = [m for b, m in ((GDN_DEV_NONFINITE, "non-finite coordinates"),
+                                    (GDN_DEV_WAIT_LIMIT, "an inter-workgroup wait hit its limit"),
+                                    (GDN_DEV_BAD_FRAMES, "bad frame table")) if st & b]
+            raise GdnError(GDN_EINTERNAL, f"device status {st:#x}: {', '.join(names)}; outputs unspecified")
+        return st
 
     def dump(self, what: str, n: int):
         """Intermediates of the last frame (original point order), as a tensor."""

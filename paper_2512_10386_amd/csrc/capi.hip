@@ -67,7 +67,7 @@ gdn::Plan make_plan(uint32_t n, uint32_t nf, int k, char* base) {
     P.plist_max = (uint32_t)std::min<uint64_t>(3ull * n + 64u, (1ull << 30) - 64u);
 
     const size_t z0 = off;
-    P.ctr = (Counters*)take(sizeof(Counters));
+    P.ctr = (Counters*)take(sizeof(Counters));  // first: status_word() reads the workspace start
     P.fstat = (FrameStat*)take(sizeof(FrameStat) * (size_t)nf);
     P.sort_hist = (uint32_t*)take(sizeof(uint32_t) * SORT_PASSES_MAX * 256);
     P.sort_status = (uint32_t*)take(sizeof(uint32_t) * (size_t)P.sort_passes * P.sort_tiles * 256);
@@ -635,5 +635,10 @@ const char* gdn_status_string(gdn_status s) {
 }
 
 const char* gdn_last_error(gdn_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+#ifndef GDN_SOURCE_HASH
+#define GDN_SOURCE_HASH "unknown"
+#endif
+const char* gdn_source_hash(void) { return GDN_SOURCE_HASH; }
 
 }  // extern "C"

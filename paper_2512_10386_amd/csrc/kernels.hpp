@@ -50,6 +50,11 @@ size_t eval_workspace_bytes(uint32_t nc, uint32_t nd);
 void launch_eval(const float* clean, uint32_t nc, const float* den, uint32_t nd, void* ws, double* out,
                  hipStream_t st);
 
+// The device status word of a pass: the Counters block opens the workspace.
+inline const uint32_t* status_word(const void* workspace) {
+    return &static_cast<const Counters*>(workspace)->status;
+}
+
 // dump.hip: intermediates back in original point order
 int launch_dump(const Plan& P, int what, void* dst, size_t dst_bytes, hipStream_t st);
 

@@ -87,6 +87,7 @@ struct Slot {
     int64_t* n_kept = nullptr;
     ReqDesc* desc_dev = nullptr;
     ReqDesc* desc_host = nullptr;  // pinned
+    uint32_t* status_host = nullptr;  // pinned: the batch's device status word
     std::vector<int64_t> tickets;
     bool busy = false;
 };
@@ -103,6 +104,7 @@ struct gdn_server {
     std::vector<Slot> slots;
     std::deque<Req> waiting;
     std::vector<int64_t> done;  // finished tickets not yet reported
+    std::vector<uint32_t> done_status;  // their batches' device status words
     int64_t next_ticket = 0;
     std::string err;
 };
@@ -120,6 +122,7 @@ void free_slot(Slot& sl) {
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
     if (sl.xyz) (void)hipFree(sl.xyz);  // one allocation holds all device arrays
     if (sl.desc_host) (void)hipHostFree(sl.desc_host);
+    if (sl.status_host) (void)hipHostFree(sl.status_host);
     sl = Slot{};
 }
 
@@ -148,6 +151,9 @@ gdn_status launch_slot(gdn_server* S, Slot& sl) {
     if (st != GDN_OK) return srv_fail(S, st, gdn_last_error(S->ctx));
     hipLaunchKernelGGL(scatter_kernel, dim3(blocks), dim3(256), 0, sl.stream, sl.desc_dev, nr, total, sl.keep,
                        sl.score, sl.stage, sl.kept_idx, sl.n_kept);
+    if (hipMemcpyAsync(sl.status_host, gdn::status_word(sl.ws), sizeof(uint32_t), hipMemcpyDeviceToHost,
+                       sl.stream) != hipSuccess)
+        return srv_fail(S, GDN_EHIP, "hipMemcpyAsync of the status word failed");
     if (hipEventRecord(sl.done, sl.stream) != hipSuccess) return srv_fail(S, GDN_EHIP, "hipEventRecord failed");
     if (hipGetLastError() != hipSuccess) return srv_fail(S, GDN_EHIP, "kernel launch failed");
     sl.busy = true;
@@ -185,6 +191,7 @@ gdn_status gdn_server_create(gdn_ctx* ctx, const gdn_params* p, size_t hbm_budge
         ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess;
         ok = ok && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess;
         ok = ok && hipHostMalloc((void**)&sl.desc_host, sizeof(ReqDesc) * F) == hipSuccess;
+        ok = ok && hipHostMalloc((void**)&sl.status_host, sizeof(uint32_t)) == hipSuccess;
         if (!ok) {
             if (b) (void)hipFree(b);
             for (Slot& x : S->slots) free_slot(x);
@@ -240,8 +247,8 @@ gdn_status gdn_server_submit(gdn_server* s, const float* xyz, int64_t n, uint8_t
     return GDN_OK;
 }
 
-gdn_status gdn_server_poll(gdn_server* s, int64_t* done_tickets, int max_done, int* n_done, int* n_waiting,
-                           int* n_busy) {
+gdn_status gdn_server_poll(gdn_server* s, int64_t* done_tickets, uint32_t* done_status, int max_done, int* n_done,
+                           int* n_waiting, int* n_busy) {
     if (!s || !n_done) return GDN_EINVAL;
     gdn::CurrentDevice guard(gdn::context_device(s->ctx));
     for (Slot& sl : s->slots) {
@@ -250,6 +257,7 @@ gdn_status gdn_server_poll(gdn_server* s, int64_t* done_tickets, int max_done, i
         if (q == hipSuccess) {
             sl.busy = false;
             s->done.insert(s->done.end(), sl.tickets.begin(), sl.tickets.end());
+            s->done_status.insert(s->done_status.end(), sl.tickets.size(), *sl.status_host);
             sl.tickets.clear();
         } else if (q != hipErrorNotReady) {
             return srv_fail(s, GDN_EHIP, "hipEventQuery failed");
@@ -262,8 +270,12 @@ gdn_status gdn_server_poll(gdn_server* s, int64_t* done_tickets, int max_done, i
         if (st != GDN_OK) return st;
     }
     const int k = std::min<int>((int)s->done.size(), std::max(max_done, 0));
-    for (int i = 0; i < k; ++i) done_tickets[i] = s->done[(size_t)i];
+    for (int i = 0; i < k; ++i) {
+        done_tickets[i] = s->done[(size_t)i];
+        if (done_status) done_status[i] = s->done_status[(size_t)i];
+    }
     s->done.erase(s->done.begin(), s->done.begin() + k);
+    s->done_status.erase(s->done_status.begin(), s->done_status.begin() + k);
     *n_done = k;
     if (n_waiting) *n_waiting = (int)s->waiting.size();
     if (n_busy) {

@@ -22,6 +22,7 @@ class Server:
         self.torch = torch
         self.device = torch.device("cuda", device)
         self.srv = 0
+        self.flagged = {}
         self.ctx = B.gdn_create(device)
         self.params = B.make_params(**params)
         try:
@@ -59,7 +60,15 @@ class Server:
                                    out.stage.data_ptr(), out.kept_idx.data_ptr(), out.n_kept.data_ptr())
 
     def poll(self):
-        return B.gdn_server_poll(self.srv)
+        """(finished tickets, queue length, busy slots). Raises GdnError if a
+        finished frame's batch raised a device status bit (its outputs are
+        unspecified); the tickets of such a batch are in ``self.flagged``."""
+        done, sts, nw, nb = B.gdn_server_poll(self.srv)
+        bad = {t: s for t, s in zip(done, sts) if s}
+        if bad:
+            self.flagged.update(bad)
+            raise B.GdnError(B.GDN_EINTERNAL, f"device status {sorted(set(bad.values()))} for tickets {sorted(bad)}")
+        return done, nw, nb
 
 
 def arrivals(n_sensors: int, rate_hz: float, duration_s: float, seed: int):

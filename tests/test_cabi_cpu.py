@@ -79,3 +79,16 @@ def test_batch_workspace_size_and_validation_on_host(libgdn):
     with pytest.raises(libgdn.GdnError) as e:
         libgdn.gdn_workspace_size(0, libgdn.make_params(knn_chunk=-1), 10)
     assert e.value.status == libgdn.GDN_EINVAL
+
+
+def test_library_matches_its_sources(libgdn, monkeypatch):
+    """The loaded library carries the hash of the sources it was built from;
+    a library built from other sources is refused."""
+    from paper_2512_10386_amd import build
+    lib = C.CDLL(libgdn.LIB_PATH)
+    lib.gdn_source_hash.restype = C.c_char_p
+    assert lib.gdn_source_hash().decode() == build.source_hash()
+    monkeypatch.setattr(libgdn, "_lib", None)
+    monkeypatch.setattr(build, "source_hash", lambda: "0" * 64)
+    with pytest.raises(RuntimeError, match="stale"):
+        libgdn.lib()

@@ -78,10 +78,12 @@ def kept_lists(o, off):
     return [o["kept_idx"][int(off[f]):int(off[f]) + int(o["n_kept"][f])].tolist() for f in range(len(off) - 1)]
 
 
-def check_frames_equal_plain(den, frames, off, o, dumps, params):
-    """Every frame of the batch against a plain run of that frame."""
+def check_frames_equal_plain(den, frames, off, o, dumps, params, which=None):
+    """Every frame of the batch (or the frames listed in ``which``) against a
+    plain run of that frame."""
     den.set_params(**params)
-    for f, fr in enumerate(frames):
+    for f in (range(len(frames)) if which is None else which):
+        fr = frames[f]
         a, b = int(off[f]), int(off[f + 1])
         n = b - a
         g = run_gpu(den, fr)
@@ -166,6 +168,31 @@ def test_many_tiny_frames_two_frame_digits(bden, den, nframes):
     check_frames_equal_plain(den, frames[:40], off, o, dumps, params)
     # the rest: outputs only
     check_frames_equal_plain(den, frames, off, o, None, params)
+
+
+@pytest.mark.parametrize("nframes", [300, 2100])
+def test_many_frames_above_1m_points(bden, den, nframes):
+    """More than 256 frames (two frame-id digits) and, with 2100, more than
+    2047 (frame offsets searched in memory rather than in LDS), in a batch of
+    more than 2^20 points, so the 16-key radix tiles scatter both frame
+    digits through LDS and the other large-input kernels run. Sampled frames
+    equal their plain runs in every intermediate, the rest in their outputs."""
+    beams, az = (16, 232) if nframes == 300 else (8, 88)
+    rng = np.random.default_rng(nframes + 1)
+    frames = [synth.lidar_frame(seed=5000 + i, n_beams=beams, n_az=int(az + rng.integers(-8, 9)))[0]
+              for i in range(nframes)]
+    params = dict(k=8, leaf_cap=128)
+    xyz, offd, off = to_dev(frames)
+    assert xyz.shape[0] > (1 << 20)
+    print(f"[batch] {nframes} frames above 1M: n={xyz.shape[0]}", flush=True)
+    bden.set_params(**params)
+    o = outputs(bden(xyz, offd), xyz.shape[0], len(frames))
+    dumps = batch_dumps(bden, xyz.shape[0], len(frames))
+    assert dumps["status"] == 0
+    sample = sorted(set([0, 1, 255, 256, 257, nframes // 2, nframes - 2, nframes - 1] +
+                        list(rng.choice(nframes, 6, replace=False))))
+    check_frames_equal_plain(den, frames, off, o, dumps, params, which=sample)
+    check_frames_equal_plain(den, frames, off, o, None, params, which=range(0, nframes, 7))
 
 
 def test_one_frame_batch_equals_plain(bden, den):
