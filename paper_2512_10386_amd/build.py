@@ -38,7 +38,8 @@ def source_hash() -> str:
             h.update(fh.read())
     with open(os.path.join(ROOT, "include", "gdn.h"), "rb") as fh:
         h.update(fh.read())
-    h.update(" ".join(FLAGS).encode())
+    # flags without the include path, which depends on where the tree sits
+    h.update(" ".join(f for f in FLAGS if not f.startswith(ROOT)).encode())
     return h.hexdigest()
 
 
