@@ -145,7 +145,8 @@ struct Plan {
     uint32_t* scan_status;    // [SCAN_SLOTS][scan_tiles]
     uint32_t sort_tiles, scan_tiles;
     uint32_t sort_items;      // keys per thread of the radix passes (4 or 16)
-    uint8_t* deepf;           // [n] 1 at sorted positions inside deep level-10 cells (zeroed block)
+    uint8_t* deepf;           // [n] 1 at sorted positions inside deep level-10 cells; between the two
+                              // deep-cell kernels, 2 marks the start of a cell to re-sort (zeroed block)
     // frames
     uint32_t* foff;           // [nf+1] frame offsets (checked copy of the caller's)
     uint32_t* fid;            // [n] frame of each point (original order; nf > 1 only)

@@ -533,13 +533,14 @@ constexpr int CELL_SHIFT = 3 * (MORTON_BITS - SORT_SHORT_LEVEL);  // level-10 pr
 constexpr int SEG_BLOCK = 256;
 constexpr int SEG_PASSES = 6;  // key bits 0..47; bits 33..62 are the cell's own, and 6 passes end in keys_a
 
-// Stable LSD radix sort of the keys and payloads of one deep cell [a, b) over
-// key bits 0..47 (the cell's points share bits 33..62), by the whole block,
-// tile by tile in order through keys_b / idx_b (scratch after the main sort):
-// the cell's (original index) order becomes (key, index) order. Its
-// positions are then flagged for the boundary test.
-__device__ void sort_deep_cell(const Plan& P, uint32_t a, uint32_t b, uint32_t* s_base,
-                               uint32_t (*s_w)[256], uint32_t* s_scan) {
+// Stable LSD radix sort of the keys and payloads of one level-10 cell [a, b)
+// over key bits 0..47 (the cell's points share bits 33..62), by the whole
+// block, tile by tile in order through keys_b / idx_b (scratch after the main
+// sort): the cell's (original index) order becomes (key, index) order. A deep
+// cell's positions are then flagged for the boundary test; a cell re-sorted
+// only because it borders a deep one has its mark cleared.
+__device__ void sort_cell(const Plan& P, uint32_t a, uint32_t b, bool deep, uint32_t* s_base,
+                          uint32_t (*s_w)[256], uint32_t* s_scan) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     for (int pass = 0; pass < SEG_PASSES; ++pass) {
@@ -593,21 +594,87 @@ __device__ void sort_deep_cell(const Plan& P, uint32_t a, uint32_t b, uint32_t* 
         }
         __syncthreads();  // the pass's writes are complete before the next reads them
     }
-    for (uint32_t i = a + tid; i < b; i += SEG_BLOCK) P.deepf[i] = 1u;
+    if (deep) {
+        for (uint32_t i = a + tid; i < b; i += SEG_BLOCK) P.deepf[i] = 1u;
+    } else if (tid == 0) {
+        P.deepf[a] = 0u;
+    }
     __syncthreads();
 }
 
+// Frame of sorted position s and its range [fs, fe).
+__device__ __forceinline__ uint32_t frame_range(const Plan& P, const uint32_t* s_foff, bool lds, uint32_t s,
+                                                uint32_t* fs, uint32_t* fe) {
+    uint32_t f = 0u;
+    if (lds) {
+        f = frame_of(s_foff, P.nf, s);
+        *fs = s_foff[f];
+        *fe = s_foff[f + 1];
+    } else {
+        if (P.nf > 1u) f = frame_of(P.foff, P.nf, s);
+        *fs = P.foff[f];
+        *fe = P.foff[f + 1];
+    }
+    return f;
+}
+
+// First position in [lo, hi) whose level-10 cell prefix is >= c (the keys
+// are in cell order everywhere).
+__device__ __forceinline__ uint32_t cell_lower_bound(const uint64_t* keys, uint32_t lo, uint32_t hi, uint64_t c) {
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((keys[mid] >> CELL_SHIFT) < c) lo = mid + 1u;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // A level-10 cell splits when it holds more than `cap` points and lies above
-// its frame's depth limit. One thread per sorted position: a position that
-// starts such a cell finds the cell's end (the keys are in cell order); the
-// block then sorts the cells that start among its positions. (Blocks that
+// its frame's depth limit ("deep"). Its leaves lie below level 10, and so do
+// the halo cells around them, which reach into the 26 level-10 cells next to
+// it: every one of those needs its points in whole-key order too, so that a
+// deeper cell is one contiguous key range. One thread per sorted position: a
+// position that starts a deep cell marks (deepf = 2) the start of that cell
+// and of each non-empty neighbouring cell in its frame. The marks are plain
+// stores of one value, so cells marked twice need no atomics.
+__global__ __launch_bounds__(SEG_BLOCK) void deep_mark_kernel(Plan P, uint32_t cap) {
+    __shared__ uint32_t s_foff[SORT_FOFF_LDS];  // batches of fewer frames search the offsets here
+    const bool lds = P.nf > 1u && P.nf < SORT_FOFF_LDS;
+    if (lds)
+        for (uint32_t i = threadIdx.x; i <= P.nf; i += blockDim.x) s_foff[i] = P.foff[i];
+    __syncthreads();
+    for (uint32_t s = blockIdx.x * SEG_BLOCK + threadIdx.x; s < P.n; s += gridDim.x * SEG_BLOCK) {
+        uint32_t fs, fe;
+        const uint32_t f = frame_range(P, s_foff, lds, s, &fs, &fe);
+        const uint64_t c = P.keys_a[s] >> CELL_SHIFT;
+        const bool start = P.fc[f].dmax > SORT_SHORT_LEVEL && (s == fs || (P.keys_a[s - 1] >> CELL_SHIFT) != c) &&
+                           (uint64_t)s + cap < fe && (P.keys_a[s + cap] >> CELL_SHIFT) == c;
+        if (!start) continue;
+        P.deepf[s] = 2u;
+        const int32_t cx = (int32_t)compact3(c), cy = (int32_t)compact3(c >> 1), cz = (int32_t)compact3(c >> 2);
+        const int32_t side = 1 << SORT_SHORT_LEVEL;
+        for (int g = 0; g < 27; ++g) {
+            const int32_t nx = cx + g % 3 - 1, ny = cy + (g / 3) % 3 - 1, nz = cz + g / 9 - 1;
+            if (g == 13 || nx < 0 || ny < 0 || nz < 0 || nx >= side || ny >= side || nz >= side) continue;
+            const uint64_t nc = morton3((uint32_t)nx, (uint32_t)ny, (uint32_t)nz);
+            const uint32_t q = cell_lower_bound(P.keys_a, fs, fe, nc);
+            if (q < fe && (P.keys_a[q] >> CELL_SHIFT) == nc) P.deepf[q] = 2u;
+        }
+    }
+}
+
+// One thread per sorted position: a marked position starts a cell to re-sort;
+// it finds the cell's end, and the block then sorts the cells that start
+// among its positions (deep ones flagged, the others unmarked). Blocks that
 // read keys of a cell another block is sorting compare cell prefixes only,
-// which the sort does not change.)
+// which the sort does not change; a mark is only read by the thread of its
+// own position, and only that cell's block rewrites it.
 __global__ __launch_bounds__(SEG_BLOCK) void deep_cells_kernel(Plan P, uint32_t cap) {
     __shared__ uint32_t s_base[256];
     __shared__ uint32_t s_w[SEG_BLOCK / 64][256];
     __shared__ uint32_t s_scan[SEG_BLOCK / 64 + 1];
-    __shared__ uint2 s_seg[SEG_BLOCK / 2];  // cells are >= 2 points long, so at most half the positions start one
+    __shared__ uint2 s_seg[SEG_BLOCK];
+    __shared__ uint8_t s_deep[SEG_BLOCK];
     __shared__ uint32_t s_nseg;
     __shared__ uint32_t s_foff[SORT_FOFF_LDS];  // batches of fewer frames search the offsets here
     const bool lds = P.nf > 1u && P.nf < SORT_FOFF_LDS;
@@ -617,33 +684,18 @@ __global__ __launch_bounds__(SEG_BLOCK) void deep_cells_kernel(Plan P, uint32_t 
         if (threadIdx.x == 0) s_nseg = 0u;
         __syncthreads();
         const uint32_t s = base + threadIdx.x;
-        if (s < P.n) {
-            uint32_t f = 0u, fs, fe;
-            if (lds) {
-                f = frame_of(s_foff, P.nf, s);
-                fs = s_foff[f];
-                fe = s_foff[f + 1];
-            } else {
-                if (P.nf > 1u) f = frame_of(P.foff, P.nf, s);
-                fs = P.foff[f];
-                fe = P.foff[f + 1];
-            }
+        if (s < P.n && P.deepf[s] == 2u) {
+            uint32_t fs, fe;
+            const uint32_t f = frame_range(P, s_foff, lds, s, &fs, &fe);
             const uint64_t c = P.keys_a[s] >> CELL_SHIFT;
-            const bool start = P.fc[f].dmax > SORT_SHORT_LEVEL && (s == fs || (P.keys_a[s - 1] >> CELL_SHIFT) != c) &&
-                               (uint64_t)s + cap < fe && (P.keys_a[s + cap] >> CELL_SHIFT) == c;
-            if (start) {
-                uint32_t lo = s + cap + 1u, hi = fe;
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if ((P.keys_a[mid] >> CELL_SHIFT) == c) lo = mid + 1u;
-                    else hi = mid;
-                }
-                s_seg[atomicAdd(&s_nseg, 1u)] = make_uint2(s, lo);
-            }
+            const uint32_t e = cell_lower_bound(P.keys_a, s + 1u, fe, c + 1u);
+            const uint32_t slot = atomicAdd(&s_nseg, 1u);
+            s_seg[slot] = make_uint2(s, e);
+            s_deep[slot] = (uint8_t)(P.fc[f].dmax > SORT_SHORT_LEVEL && e - s > cap);
         }
         __syncthreads();
         const uint32_t ns = s_nseg;
-        for (uint32_t g = 0; g < ns; ++g) sort_deep_cell(P, s_seg[g].x, s_seg[g].y, s_base, s_w, s_scan);
+        for (uint32_t g = 0; g < ns; ++g) sort_cell(P, s_seg[g].x, s_seg[g].y, s_deep[g] != 0u, s_base, s_w, s_scan);
         __syncthreads();
     }
 }
@@ -671,6 +723,7 @@ void launch_sort(const Plan& P, const Params& prm, hipStream_t st) {
     unsigned blocks = (P.n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(deep_mark_kernel, dim3(blocks), dim3(SEG_BLOCK), 0, st, P, (uint32_t)prm.leaf_cap);
     hipLaunchKernelGGL(deep_cells_kernel, dim3(blocks), dim3(SEG_BLOCK), 0, st, P, (uint32_t)prm.leaf_cap);
 }
 

@@ -50,17 +50,31 @@ SHORT_SORT_LEVEL = 10  # the radix passes cover key bits 32..62 (every level-10 
 def expected_order(ref):
     """The kernels' sorted order: (key bits 32..62, original index), except
     inside "deep" level-10 cells (more than leaf_cap points, split further by
-    the octree), which are re-sorted on the whole key: there the order is the
-    oracle's (key, index). Deep cells exist exactly when a leaf lies below
-    level 10."""
+    the octree) and the level-10 cells next to them (where the deep leaves'
+    halo cells reach), which are re-sorted on the whole key: there the order
+    is the oracle's (key, index). Deep cells exist exactly when a leaf lies
+    below level 10."""
     n = len(ref["keep"])
     key = ref["key"].astype(np.uint64)
     masked = key & ~np.uint64(0xFFFFFFFF)
     if ref["n_leaves"] and int(ref["leaf_level"].max()) > SHORT_SORT_LEVEL:
         cell = key >> np.uint64(3 * (21 - SHORT_SORT_LEVEL))
-        _, inv, cnt = np.unique(cell, return_inverse=True, return_counts=True)
-        deep = cnt[inv] > int(ref["params"]["leaf_cap"])
-        masked = np.where(deep, key, masked)
+        u, cnt = np.unique(cell, return_counts=True)
+        resort = set()
+        side = 1 << SHORT_SORT_LEVEL
+        for c in u[cnt > int(ref["params"]["leaf_cap"])]:
+            c = int(c)
+            xyz = [sum(((c >> (3 * b + a)) & 1) << b for b in range(SHORT_SORT_LEVEL)) for a in range(3)]
+            for dx in (-1, 0, 1):
+                for dy in (-1, 0, 1):
+                    for dz in (-1, 0, 1):
+                        q = (xyz[0] + dx, xyz[1] + dy, xyz[2] + dz)
+                        if min(q) < 0 or max(q) >= side:
+                            continue
+                        resort.add(sum(((q[a] >> b) & 1) << (3 * b + a)
+                                       for b in range(SHORT_SORT_LEVEL) for a in range(3)))
+        full = np.isin(cell, np.array(sorted(resort), np.uint64))
+        masked = np.where(full, key, masked)
     return np.lexsort((np.arange(n), masked)).astype(np.uint32)
 
 
