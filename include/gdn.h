@@ -113,6 +113,25 @@ gdn_status gdn_denoise(gdn_ctx *ctx, const gdn_params *p, const float *xyz, int6
                        uint8_t *keep, float *score, uint8_t *stage,
                        uint32_t *kept_idx, int64_t *n_kept, void *stream);
 
+/*
+ * Denoise one frame without allocating anything, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation. Same arguments, results and errors as
+ * gdn_denoise, without the workspace: the frame's intermediates live in a
+ * fixed scratch array of GDN_NOALLOC_MAX_BYTES inside the library, one per
+ * GPU, held from the library's first use on that GPU until the process ends.
+ * A frame whose gdn_workspace_size exceeds it is refused with GDN_ECAPACITY
+ * (a 120k-point frame at k = 32 needs about 179 MiB). Every call on one GPU
+ * shares that GPU's array and it keeps the last call's contents
+ * (gdn_debug_dump reads them): calls that overlap on one GPU, on any streams
+ * or contexts, race and give unspecified results. The call never allocates
+ * or frees device memory and never synchronises the host.
+ */
+#define GDN_NOALLOC_MAX_BYTES (192u << 20)
+gdn_status gdn_denoise_noalloc(gdn_ctx *ctx, const gdn_params *p, const float *xyz, int64_t n,
+                               uint8_t *keep, float *score, uint8_t *stage,
+                               uint32_t *kept_idx, int64_t *n_kept, void *stream);
+
 /* Workspace bytes gdn_denoise_batch needs for nf frames of n points in all
  * (1 <= nf <= GDN_MAX_FRAMES). */
 gdn_status gdn_workspace_size_batch(gdn_ctx *ctx, const gdn_params *p, int64_t n, int64_t nf, size_t *bytes);

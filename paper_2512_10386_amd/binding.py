@@ -20,6 +20,7 @@ GDN_DEV_NONFINITE = 1
 GDN_DEV_WAIT_LIMIT = 2
 GDN_DEV_BAD_FRAMES = 4
 GDN_MAX_FRAMES = 4096
+GDN_NOALLOC_MAX_BYTES = 192 << 20
 GDN_STAGE_VOXEL, GDN_STAGE_DENSITY, GDN_STAGE_SCORE, GDN_STAGES_ALL = 1, 2, 4, 7
 
 DUMP = dict(STATUS=0, COUNTS=1, KEYS=2, ORDER=3, LEAF_OF=4, LEAF_TABLE=5, OCC=6, P1=7,
@@ -74,6 +75,7 @@ def lib():
         L.gdn_destroy.restype = None
         L.gdn_workspace_size.argtypes = [vp, C.POINTER(gdn_params), i64, C.POINTER(sz)]
         L.gdn_denoise.argtypes = [vp, C.POINTER(gdn_params), vp, i64, vp, sz, vp, vp, vp, vp, vp, vp]
+        L.gdn_denoise_noalloc.argtypes = [vp, C.POINTER(gdn_params), vp, i64, vp, vp, vp, vp, vp, vp]
         L.gdn_workspace_size_batch.argtypes = [vp, C.POINTER(gdn_params), i64, i64, C.POINTER(sz)]
         L.gdn_denoise_batch.argtypes = [vp, C.POINTER(gdn_params), vp, i64, vp, i64, vp, sz,
                                         vp, vp, vp, vp, vp, vp]
@@ -107,7 +109,7 @@ def lib():
         L.gdn_status_string.restype = C.c_char_p
         L.gdn_last_error.argtypes = [vp]
         L.gdn_last_error.restype = C.c_char_p
-        for f in ("gdn_default_params", "gdn_create", "gdn_workspace_size", "gdn_denoise",
+        for f in ("gdn_default_params", "gdn_create", "gdn_workspace_size", "gdn_denoise", "gdn_denoise_noalloc",
                   "gdn_debug_dump", "gdn_set_timing", "gdn_timing", "gdn_workspace_size_batch",
                   "gdn_denoise_batch", "gdn_graph_create", "gdn_graph_launch", "gdn_autotune",
                   "gdn_fit_workspace_size", "gdn_fit_loss_grad", "gdn_nearest_workspace_size",
@@ -155,6 +157,10 @@ def gdn_denoise(ctx, p, xyz, n, workspace, workspace_bytes, keep, score, stage,
                 kept_idx, n_kept, stream) -> None:
     _check(ctx, lib().gdn_denoise(ctx, C.byref(p), xyz, n, workspace, workspace_bytes,
                                   keep, score, stage, kept_idx, n_kept, stream))
+
+
+def gdn_denoise_noalloc(ctx, p, xyz, n, keep, score, stage, kept_idx, n_kept, stream) -> None:
+    _check(ctx, lib().gdn_denoise_noalloc(ctx, C.byref(p), xyz, n, keep, score, stage, kept_idx, n_kept, stream))
 
 
 def gdn_workspace_size_batch(ctx: int, p: gdn_params, n: int, nf: int) -> int:

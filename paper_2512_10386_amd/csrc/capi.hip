@@ -3,6 +3,7 @@
 // sequence and the leaf-capacity / chunk-length autotuner.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -20,6 +21,7 @@ struct CallEvents {
 struct gdn_ctx {
     int device = 0;
     int num_cus = 256;
+    void* scratch = nullptr;  // this device's copy of the no-allocation scratch array
     std::string err;
     gdn::Plan last{};
     gdn::Params last_prm{};
@@ -34,7 +36,33 @@ size_t dump_bytes(uint32_t n, int k, int what);
 int context_device(const gdn_ctx* ctx) { return ctx ? ctx->device : 0; }
 }
 
+// Scratch memory of gdn_denoise_noalloc: the workspace of one frame, in a
+// fixed array that every GPU the library runs on holds (its own copy, at its
+// own address) until the process ends. Host code never names the array
+// itself in a kernel argument or copy: it uses the address
+// hipGetSymbolAddress returns for the current device, kept per device.
+static __device__ __align__(256) unsigned char scratch[GDN_NOALLOC_MAX_BYTES];
+
 namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// The device address of `scratch` on `device` (which must be current),
+// looked up once per device.
+hipError_t scratch_address(int device, void** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 constexpr int64_t MAX_POINTS = (1ll << 30) - 1;
 static_assert(GDN_MAX_FRAMES == gdn::MAX_FRAMES, "frame limit of the ABI and the kernels");
@@ -228,6 +256,13 @@ gdn_status gdn_create(gdn_ctx** out, int device) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         c->num_cus = cus;
+    {
+        DeviceGuard guard(device);
+        if (scratch_address(device, &c->scratch) != hipSuccess) {
+            delete c;
+            return GDN_EHIP;
+        }
+    }
     *out = c;
     return GDN_OK;
 }
@@ -374,6 +409,22 @@ gdn_status gdn_denoise(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int6
     DeviceGuard guard(ctx->device);
     return run(ctx, p, xyz, n, nullptr, 1, workspace, workspace_bytes, keep, score, stage, kept_idx, n_kept,
                (hipStream_t)stream, true);
+}
+
+gdn_status gdn_denoise_noalloc(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int64_t n, uint8_t* keep,
+                               float* score, uint8_t* stage, uint32_t* kept_idx, int64_t* n_kept, void* stream) {
+    if (!ctx) return GDN_EINVAL;
+    size_t need = 0;
+    const gdn_status e = gdn_workspace_size(ctx, p, n, &need);
+    if (e != GDN_OK) return e;
+    if (need > (size_t)GDN_NOALLOC_MAX_BYTES)
+        return fail(ctx, GDN_ECAPACITY,
+                    "frame needs " + std::to_string(need) + " bytes of scratch; gdn_denoise_noalloc holds " +
+                        std::to_string((size_t)GDN_NOALLOC_MAX_BYTES) + " (use gdn_denoise with a workspace)");
+    if (!ctx->scratch) return fail(ctx, GDN_EHIP, "no scratch address for this device");
+    DeviceGuard guard(ctx->device);
+    return run(ctx, p, xyz, n, nullptr, 1, ctx->scratch, (size_t)GDN_NOALLOC_MAX_BYTES, keep, score, stage,
+               kept_idx, n_kept, (hipStream_t)stream, true);
 }
 
 gdn_status gdn_denoise_batch(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int64_t n,
