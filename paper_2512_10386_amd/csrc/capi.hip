@@ -148,6 +148,7 @@ gdn::Plan make_plan(uint32_t n, uint32_t nf, int k, char* base) {
     P.krec = (uint4*)take(16 * N);
     P.outrec = (uint2*)take(8 * N);
     P.tau_c = (float*)take(4 * N);
+    P.gbox = (GroupBox*)take(sizeof(GroupBox) * ((N + KNN_GRP - 1) / KNN_GRP));
     P.rho_c = (double*)take(8 * N);
     P.r64_c = (double*)take(8 * N);
     P.afac_c = (double2*)take(16 * N);

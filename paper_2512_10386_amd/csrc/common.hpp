@@ -36,6 +36,7 @@ constexpr int PLAN_LEVELS = 8;                // candidate chunk lengths chunk0 
 constexpr int KNN_TQ = 16;                    // queries per kNN work item (one wave)
 constexpr int KNN_CC0 = 16384;                // default initial candidate chunk
 constexpr int KNN_NCH_MAX = 32;               // max candidate chunks per leaf
+constexpr int KNN_GRP = 64;                   // P1 positions per culling group of the kNN (one per lane)
 constexpr uint32_t KNN_STREAMS = 8;           // kNN work-queue streams (cursors)
 constexpr int HALO = 27;
 constexpr int VOX_BLOCK = 256;
@@ -94,6 +95,11 @@ struct FrameConst {
     int32_t dmax;
     double S;
     double scale;
+};
+
+// Bounding box of the P1 points at positions [KNN_GRP g, KNN_GRP (g + 1)).
+struct GroupBox {
+    float4 lo, hi;  // w unused
 };
 
 // One kNN work item: queries [q0, q1) of leaf `leaf` against candidate chunk
@@ -192,6 +198,7 @@ struct Plan {
     uint4* krec;              // [n] k-th neighbour (none: 0xFFFFFFFF), fp32 bits of the (k-1)-th and k-th d2
     uint2* outrec;            // [n] by original index: fp32 score bits, stage (large inputs' outputs)
     float* tau_c;             // [n] per-query upper bound of r^2_K (-1: none)
+    GroupBox* gbox;           // [ceil(n / KNN_GRP)] boxes of aligned groups of the P1 order
     double* rho_c;            // [n]
     double* r64_c;            // [n]
     double2* afac_c;          // [n] (rho_i / (rho_med^2 + eps))^(alpha/2), 1 / (2 (sigma r_K,i)^2)

@@ -84,6 +84,7 @@ constexpr int BOUND_SPLIT = 8;     // adjacent lanes sharing one query's distanc
 // less than it costs the kNN there).
 constexpr uint32_t BOUND_COARSE_MIN_N = 1u << 20;
 constexpr int BOUND_Q = 128;       // queries per block (BOUND_Q * BOUND_SPLIT threads)
+static_assert(BOUND_Q % KNN_GRP == 0, "a bound block covers whole culling groups");
 
 // tau: the largest d2 to the k points next to the query in Morton order inside
 // [qb, qe), a run of candidates holding the query; then, over the run's points
@@ -161,6 +162,23 @@ __global__ __launch_bounds__(BOUND_Q * BOUND_SPLIT) void knn_bound_kernel(Plan P
         const uint32_t hi = min(np1, q_first + BOUND_Q + (uint32_t)BOUND_MARGIN + 1u);
         for (uint32_t j = lo + threadIdx.x; j < hi; j += blockDim.x) s_pts[j - lo] = cand4[j];
         __syncthreads();
+        {
+            // the boxes of the culling groups among this block's queries (q_first
+            // is a multiple of KNN_GRP), one wave per group
+            const uint32_t wv = threadIdx.x / 64u, ln = threadIdx.x % 64u;
+            const uint32_t g0 = q_first + wv * (uint32_t)KNN_GRP;
+            if (wv < (uint32_t)(BOUND_Q / KNN_GRP) && g0 < np1) {
+                const uint32_t p = g0 + ln;
+                const bool ok = p < np1;
+                const float4 c = ok ? s_pts[p - lo] : make_float4(0.f, 0.f, 0.f, 0.f);
+                const float lx = wave_min(ok ? c.x : INFINITY, ln), ly = wave_min(ok ? c.y : INFINITY, ln),
+                            lz = wave_min(ok ? c.z : INFINITY, ln);
+                const float hx = wave_max(ok ? c.x : -INFINITY, ln), hy = wave_max(ok ? c.y : -INFINITY, ln),
+                            hz = wave_max(ok ? c.z : -INFINITY, ln);
+                if (ln == 0u)
+                    P.gbox[g0 / (uint32_t)KNN_GRP] = GroupBox{make_float4(lx, ly, lz, 0.f), make_float4(hx, hy, hz, 0.f)};
+            }
+        }
         const uint32_t qi = q_first + ql;
         const bool live = qi < np1;
         uint32_t t = 0, qb = 0, qe = 0, rb = 0, re = 0;
@@ -585,6 +603,276 @@ __global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restric
     }
 }
 
+// ---------------------------------------------------------------- kNN by culling groups
+//
+// The candidates of an item are visited in aligned groups of KNN_GRP P1
+// positions (one per lane), whose bounding boxes the bound kernel wrote. A
+// group is loaded only if the box passes for at least one query of the
+// tile: a round box-tests GPT groups against the Q queries at once (lane
+// L: query L % Q, group L / Q), with the same fp32 operations as dist2, so a
+// skipped group holds no candidate with d2 <= the query's bound. Positions of
+// a group outside the range's part in this chunk are not candidates; they
+// are given NaN coordinates (d2 <= bound never holds). Groups of the range
+// holding the tile come first, from the tile's group outwards, then the
+// other ranges in order.
+template <bool POS, int Q>
+__global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __restrict__ cand4, int kk) {
+    using PT = typename Pending<POS>::T;
+    constexpr int GPT = 64 / Q;  // groups per box-test round
+    static_assert(Q * GPT == 64 && Q <= 64, "tile shape");
+    extern __shared__ unsigned long long s_dyn[];
+    const uint32_t lane = threadIdx.x;
+    const uint32_t k = (uint32_t)kk;
+    const bool half = k <= 32u;
+    unsigned long long* const s_list = s_dyn;           // [Q][k]
+    PT* const s_pend = (PT*)(s_dyn + (size_t)Q * k);    // [Q][PEND]
+    const uint32_t jl = lane % (uint32_t)Q;             // this lane's query in box tests
+    const uint32_t ul = lane / (uint32_t)Q;             // this lane's group slot in box tests
+    const uint32_t n_items = P.ctr->n_items;
+    const uint32_t G = gridDim.x;
+    const uint32_t s0 = blockIdx.x % KNN_STREAMS;
+    uint32_t it = blockIdx.x;
+    uint32_t sv = 0;
+    for (;;) {
+        while (it >= n_items && sv < KNN_STREAMS) {
+            const uint32_t s = (s0 + sv) % KNN_STREAMS;
+            uint32_t got = 0;
+            if (lane == 0) got = atomicAdd(&P.ctr->knn_q[s][0], 1u);
+            got = __builtin_amdgcn_readfirstlane(__shfl(got, 0, 64));
+            const uint32_t base = G > s ? (G - s + KNN_STREAMS - 1) / KNN_STREAMS : 0u;
+            it = (base + got) * KNN_STREAMS + s;
+            if (it >= n_items) ++sv;
+        }
+        if (it >= n_items) break;
+        const KnnItem w = P.items[it];
+        const uint32_t t = w.leaf;
+        const uint32_t nr = P.leaf_nr[t];
+        const uint32_t ncand = P.leaf_ncand[t], nch = P.leaf_nch[t], cc = P.leaf_cc[t];
+        const uint32_t qb = P.p1pos[P.leaf_begin[t]];
+        const uint32_t qn = w.q1 - w.q0;
+
+        // lane r < nr: range r, its part [sa, sb) of P1 positions inside this
+        // chunk (the chunk is [c_lo, c_hi) of the ranges' concatenated order)
+        // and the aligned groups [g0, g0 + gn) overlapping that part
+        uint32_t len = 0, rbeg = 0;
+        if (lane < nr) {
+            const uint2 R = P.leaf_ranges[(size_t)t * HALO + lane];
+            rbeg = R.x;
+            len = R.y - R.x;
+        }
+        const uint32_t cpre = wave_incl_scan(len) - len;
+        const uint32_t c_lo = w.chunk * cc;
+        const uint32_t c_hi = min(ncand, c_lo + cc);
+        uint32_t sa = 0, sb = 0;
+        if (lane < nr) {
+            const uint32_t a = max(cpre, c_lo), b = min(cpre + len, c_hi);
+            if (a < b) {
+                sa = rbeg + (a - cpre);
+                sb = rbeg + (b - cpre);
+            }
+        }
+        const uint32_t g0 = sa / (uint32_t)KNN_GRP;
+        const uint32_t gn = sb > sa ? (sb - 1u) / (uint32_t)KNN_GRP - g0 + 1u : 0u;
+        // the range holding the tile's queries comes first
+        const uint32_t nro = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(lane < nr && rbeg <= w.q0));
+        const uint32_t ro = nro ? nro - 1u : 0u;  // (a leaf with queries always has its own range)
+        const uint32_t g0o = (uint32_t)__builtin_amdgcn_readlane((int)g0, (int)ro);
+        const uint32_t gno = (uint32_t)__builtin_amdgcn_readlane((int)gn, (int)ro);
+        const uint32_t gt = gno ? min(max(w.q0 / (uint32_t)KNN_GRP, g0o), g0o + gno - 1u) : 0u;
+        const uint32_t n_up = gno ? g0o + gno - 1u - gt : 0u, n_dn = gno ? gt - g0o : 0u;
+        const uint32_t n_alt = min(n_up, n_dn);
+        const uint32_t u2n = (lane < nr && lane != ro) ? gn : 0u;
+        const uint32_t u2pre = wave_incl_scan(u2n) - u2n;
+        const uint32_t n_units = gno + (uint32_t)__builtin_amdgcn_readlane((int)(u2pre + u2n), 63);
+        // unit u -> (range, group): own range outwards, then the others
+        auto unit = [&](uint32_t u, uint32_t* r, uint32_t* g) {
+            if (u < gno) {
+                *r = ro;
+                if (u == 0u) {
+                    *g = gt;
+                } else if (u <= 2u * n_alt) {
+                    const uint32_t d = (u + 1u) >> 1;
+                    *g = (u & 1u) ? gt + d : gt - d;
+                } else {
+                    const uint32_t d = u - n_alt;
+                    *g = n_up > n_dn ? gt + d : gt - d;
+                }
+            } else {
+                const uint32_t v = u - gno;
+                const uint64_t mk = __builtin_amdgcn_ballot_w64(u2n > 0u && u2pre <= v);
+                const uint32_t rr = 63u - (uint32_t)__clzll((long long)mk);
+                *r = rr;
+                *g = (uint32_t)__builtin_amdgcn_readlane((int)g0, (int)rr) + v -
+                     (uint32_t)__builtin_amdgcn_readlane((int)u2pre, (int)rr);
+            }
+        };
+
+        // lists start as k tau placeholders (or empty). Lane L holds query
+        // L % Q's coordinates and bound (`worst`: candidates with d2 <= worst
+        // may enter); lane j < Q holds query j's pending count.
+        const bool qok = jl < qn;
+        float worst = -1.0f;
+        float4 qv = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (qok) {
+            const float tb = P.tau_c[w.q0 + jl];
+            worst = tb >= 0.0f ? tb : INFINITY;
+            qv = cand4[w.q0 + jl];
+        }
+        uint32_t pcnt = 0;
+        for (uint32_t j = 0; j < qn; ++j) {
+            const float tb = P.tau_c[w.q0 + j];
+            if (lane < k) s_list[j * k + lane] = tb >= 0.0f ? make_key(tb, NONE32) : KEY_EMPTY;
+        }
+        wave_lds_fence();
+
+        for (uint32_t u0 = 0; u0 < n_units; u0 += (uint32_t)GPT) {
+            uint32_t gs[GPT], ra[GPT], rb[GPT];
+#pragma unroll
+            for (int i = 0; i < GPT; ++i) {
+                gs[i] = NONE32;
+                ra[i] = rb[i] = 0u;
+                if (u0 + (uint32_t)i < n_units) {
+                    uint32_t r, g;
+                    unit(u0 + (uint32_t)i, &r, &g);
+                    gs[i] = g;
+                    ra[i] = (uint32_t)__builtin_amdgcn_readlane((int)sa, (int)r);
+                    rb[i] = (uint32_t)__builtin_amdgcn_readlane((int)sb, (int)r);
+                }
+            }
+            // box test of (query jl, group slot ul)
+            uint32_t gmine = gs[0];
+#pragma unroll
+            for (int i = 1; i < GPT; ++i)
+                if (ul == (uint32_t)i) gmine = gs[i];
+            bool need = false;
+            if (qok && gmine != NONE32) {
+                const GroupBox B = P.gbox[gmine];
+                const float gx = fmaxf(fmaxf(B.lo.x - qv.x, qv.x - B.hi.x), 0.0f);
+                const float gy = fmaxf(fmaxf(B.lo.y - qv.y, qv.y - B.hi.y), 0.0f);
+                const float gz = fmaxf(fmaxf(B.lo.z - qv.z, qv.z - B.hi.z), 0.0f);
+                need = !((gx * gx + gy * gy) + gz * gz > worst);
+            }
+            const unsigned long long nm = __builtin_amdgcn_ballot_w64(need);
+            if (nm == 0ull) continue;
+            // load the groups some query needs, then test their candidates
+            float4 c[GPT];
+            uint32_t cp[GPT];
+#pragma unroll
+            for (int i = 0; i < GPT; ++i) {
+                cp[i] = NONE32;
+                if ((nm >> (i * Q)) & (Q == 64 ? ~0ull : ((1ull << Q) - 1ull))) {
+                    const uint32_t p = gs[i] * (uint32_t)KNN_GRP + lane;
+                    if (p >= ra[i] && p < rb[i]) {
+                        c[i] = cand4[p];
+                        cp[i] = p;
+                    } else {
+                        const float nan = __uint_as_float(0x7FC00000u);
+                        c[i] = make_float4(nan, nan, nan, __uint_as_float(NONE32));
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < GPT; ++i) {
+                unsigned long long qm = (nm >> (i * Q)) & (Q == 64 ? ~0ull : ((1ull << Q) - 1ull));
+                while (qm != 0ull) {
+                    const uint32_t j = (uint32_t)__ffsll((long long)qm) - 1u;
+                    qm &= qm - 1ull;
+                    const float4 q = query_of(qv, j);
+                    float wj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(worst), (int)j));
+                    const float d = dist2(q, c[i]);
+                    unsigned long long m = __builtin_amdgcn_ballot_w64(d <= wj);
+                    if (m == 0ull) continue;
+                    uint32_t pc = (uint32_t)__popcll(m);
+                    // a group holding more than k + 1 passing candidates (one may
+                    // be the query) first lowers the bound: if k + 1 of them lie
+                    // within wj * 2^(-1/4), the k-th distance cannot exceed it
+                    if (pc > k + 1u && wj < INFINITY) {
+                        for (int r = 0; r < 12; ++r) {
+                            const float t2 = wj * 0.84089642f;
+                            if ((uint32_t)__popcll(__builtin_amdgcn_ballot_w64(d <= t2)) < k + 1u) break;
+                            wj = t2;
+                        }
+                        m = __builtin_amdgcn_ballot_w64(d <= wj);
+                        pc = (uint32_t)__popcll(m);
+                    }
+                    uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)pcnt, (int)j);
+                    PT* const pend = s_pend + (size_t)j * PEND;
+                    if (cnt + pc > (uint32_t)PEND) {
+                        const unsigned long long selfkey =
+                            (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j);
+                        wj = fminf(wj, flush<POS>(s_list + (size_t)j * k, pend, cnt, lane, k, selfkey, cand4, q));
+                        cnt = 0;
+                        m = __builtin_amdgcn_ballot_w64(d <= wj);
+                        pc = (uint32_t)__popcll(m);
+                    }
+                    if (pc) {
+                        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                        if ((m >> lane) & 1ull) {
+                            if constexpr (POS)
+                                pend[cnt + rank] = cp[i];
+                            else
+                                pend[cnt + rank] = make_key(d, __float_as_uint(c[i].w));
+                        }
+                        cnt += pc;
+                    }
+                    if (lane == j) pcnt = cnt;
+                    if (jl == j) worst = wj;
+                }
+            }
+        }
+        // drain the pending buffers: when k <= 32, two queries per merge if
+        // both hold at most 32 pending keys
+        if (half) {
+            for (uint32_t j = 0; j < qn; j += 2u) {
+                const uint32_t j1 = j + 1u;
+                const bool two = j1 < qn;
+                const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)pcnt, (int)j);
+                const uint32_t c1 = two ? (uint32_t)__builtin_amdgcn_readlane((int)pcnt, (int)j1) : 0u;
+                if ((c0 | c1) == 0u) continue;
+                const unsigned long long sk0 =
+                    (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j);
+                const unsigned long long sk1 =
+                    two ? (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j1) : 0ull;
+                unsigned long long* const l0 = s_list + (size_t)j * k;
+                PT* const p0 = s_pend + (size_t)j * PEND;
+                const float4 q0 = query_of(qv, j);
+                const float4 q1 = two ? query_of(qv, j1) : q0;
+                if (c0 <= (uint32_t)PEND_HALF && c1 <= (uint32_t)PEND_HALF) {
+                    float b0, b1;
+                    flush_half<POS>(l0, p0, c0, sk0, q0, l0 + k, p0 + PEND, c1, sk1, q1, two, lane, k, cand4, &b0,
+                                    &b1);
+                } else {
+                    if (c0) (void)flush<POS>(l0, p0, c0, lane, k, sk0, cand4, q0);
+                    if (c1) (void)flush<POS>(l0 + k, p0 + PEND, c1, lane, k, sk1, cand4, q1);
+                }
+            }
+        } else {
+            for (uint32_t j = 0; j < qn; ++j) {
+                const uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)pcnt, (int)j);
+                const unsigned long long selfkey =
+                    (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j);
+                if (cnt)
+                    (void)flush<POS>(s_list + (size_t)j * k, s_pend + (size_t)j * PEND, cnt, lane, k, selfkey,
+                                     cand4, query_of(qv, j));
+            }
+        }
+
+        if (nch > 1) {
+            unsigned long long* base = (unsigned long long*)P.plist + (size_t)P.leaf_plist[t] * k;
+            for (uint32_t j = 0; j < qn; ++j)
+                if (lane < k) base[((size_t)(w.q0 + j - qb) * nch + w.chunk) * k + lane] = s_list[j * k + lane];
+        } else {
+            for (uint32_t j = 0; j < qn; ++j) {
+                const unsigned long long v = lane < k ? s_list[j * k + lane] : KEY_EMPTY;
+                write_final(P, w.q0 + j, k, lane, v);
+            }
+        }
+        wave_lds_fence();
+        it = n_items;
+    }
+}
+
 // ---------------------------------------------------------------- chunk merge
 //
 // MERGE_SPLIT waves per query tile of a chunked leaf (each takes a share of
@@ -717,10 +1005,10 @@ void launch_knn(const Plan& P, int k, int num_cus, hipStream_t st) {
     // frame's run is set by its longest items, where a gather per merge costs
     // more (keys).
     if (P.n > KNN_POS_MIN_N)
-        hipLaunchKernelGGL(knn_kernel<true>, dim3(blocks), dim3(64), knn_lds_bytes(k, true), st, P,
+        hipLaunchKernelGGL((knn_group_kernel<true, QPW>), dim3(blocks), dim3(64), knn_lds_bytes(k, true), st, P,
                            (const float4*)P.cand4, k);
     else
-        hipLaunchKernelGGL(knn_kernel<false>, dim3(blocks), dim3(64), knn_lds_bytes(k, false), st, P,
+        hipLaunchKernelGGL((knn_group_kernel<false, QPW>), dim3(blocks), dim3(64), knn_lds_bytes(k, false), st, P,
                            (const float4*)P.cand4, k);
 }
 
