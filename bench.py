@@ -373,7 +373,7 @@ def main():
     flops = pairs * FLOPS_PER_PAIR
     achieved = flops / (knn_ms * 1e-3) / 1e12
     roofline = {
-        "kernel": "knn_kernel",
+        "kernel": "knn_group_kernel",
         "bound": "alu",
         "achieved": round(achieved, 3),
         "peak": FP32_VECTOR_PEAK_TFLOPS,

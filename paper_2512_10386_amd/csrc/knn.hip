@@ -1,26 +1,30 @@
 // Leaf-local brute-force kNN with halo candidates (Sec. 3: N_K(i), d_ij and
 // r_K,i on the voxel-filtered set P1).
 //
-// Work item = (leaf, up to 16 queries, candidate chunk), one wave each.
-// Lane-per-candidate: each lane holds 8 candidates of a 512-candidate block
-// (coalesced loads, the next block prefetched), reused for the item's 16
-// queries, whose coordinates are wave-uniform (scalar loads). Squared
-// distances are fp32 (dx*dx + dy*dy) + dz*dz without contraction, so the
-// neighbour sets are exact.
+// Work item = (leaf, up to 16 queries, candidate chunk), one wave each. The
+// candidates are the P1 positions of the leaf's merged halo ranges; they are
+// visited in aligned groups of 64 positions (one per lane), whose bounding
+// boxes the bound kernel writes. Up to 64 groups at a time are box-tested
+// against the tile's queries and ordered nearest-first; before a group is
+// tested its box is checked again against every query's current bound, and
+// only the queries that still need it compute their squared distances to its
+// 64 candidates, in fp32 as (dx*dx + dy*dy) + dz*dz without contraction, so
+// the neighbour sets are exact. A skipped group holds no candidate within the
+// query's bound (the box distance uses the same rounded operations, which are
+// monotone), so skipping never changes a result.
 //
 // Each query keeps, in LDS, its k best (d2, original index) keys (d2 bits <<
 // 32 | index), sorted, one per lane when loaded, and a pending buffer of up
-// to 64 candidates (their P1 positions, 4 bytes each: the keys are rebuilt
-// when the buffer is merged, which halves the LDS a wave needs). A candidate block is tested against the query's current k-th
-// distance with one compare per lane; the candidates that pass are appended
-// to the pending buffer (ballot + lane rank). A full buffer, and the buffer
-// at the end of the chunk, is merged into the list: the 64 pending keys are
-// sorted descending by a wave-wide bitonic network, the elementwise minimum
-// with the ascending list holds the 64 smallest keys of both as a bitonic
-// sequence, and six more exchange steps sort it. The list keeps the first k.
-// When k <= 32, buffers holding at most 32 keys at the end of an item are
-// merged on 32-lane halves, two queries at once (15 + 5 exchange steps for
-// both instead of 21 + 6 for one).
+// to 64 candidates (the keys, or their P1 positions above 1M points, which
+// halves the LDS a wave needs; a key is then rebuilt from the position with
+// the same fp32 expression). A candidate passes with one compare against the
+// query's bound; the passing ones are appended (ballot + lane rank). A full
+// buffer, and the buffer at the end of the item, is merged into the list: the
+// 64 pending keys are sorted descending by a wave-wide bitonic network, the
+// elementwise minimum with the ascending list holds the 64 smallest keys of
+// both as a bitonic sequence, and six more exchange steps sort it. The list
+// keeps the first k. When k <= 32, buffers holding at most 32 keys at the end
+// of an item are merged on 32-lane halves, two queries at once.
 //
 // Bound: knn_bound_kernel gives each query tau >= its k-th squared distance
 // (from k of its own candidates), so its list starts as k placeholder keys
@@ -42,11 +46,15 @@ namespace gdn {
 constexpr uint32_t NONE32 = 0xFFFFFFFFu;
 constexpr unsigned long long KEY_EMPTY = (unsigned long long)LLONG_MAX;
 constexpr int QPW = KNN_TQ;  // queries per wave item
-constexpr int CPL = 8;       // candidates per lane per block
-constexpr int CBLK = 64 * CPL;
 constexpr int PEND = 64;     // pending keys per query
 constexpr int PEND_HALF = 32;  // pending keys a half-wave merge takes (k <= 32)
 constexpr uint32_t KNN_POS_MIN_N = 1u << 20;  // above: pending buffers of positions
+// Short items gain little from ordering their groups or from an early merge:
+// groups are visited nearest-first only when more than KNN_SORT_MIN_UNITS are
+// needed in a round, and a query's first k + 1 pending candidates are merged
+// early only in items of more than KNN_TIGHT_MIN_UNITS groups.
+constexpr uint32_t KNN_SORT_MIN_UNITS = 0;
+constexpr uint32_t KNN_TIGHT_MIN_UNITS = 0xFFFFFFFFu;
 
 __device__ __forceinline__ float dist2(const float4 q, const float4 c) {
     const float dx = c.x - q.x, dy = c.y - q.y, dz = c.z - q.z;
@@ -317,317 +325,30 @@ __device__ __forceinline__ void flush_half(unsigned long long* __restrict__ lst0
     *b1 = bound_of((uint32_t)__builtin_amdgcn_readlane((int)hi, 32 + (int)k - 1));
 }
 
-// One wave per block. Dynamic LDS: per query, the list (k keys) and the
-// pending buffer (PEND keys or candidate positions).
-template <bool POS>
-__global__ __launch_bounds__(64) void knn_kernel(Plan P, const float4* __restrict__ cand4, int kk) {
-    using PT = typename Pending<POS>::T;
-    extern __shared__ unsigned long long s_dyn[];
-    const uint32_t lane = threadIdx.x;
-    const uint32_t k = (uint32_t)kk;
-    const bool half = k <= 32u;
-    unsigned long long* const s_list = s_dyn;                    // [QPW][k]
-    PT* const s_pend = (PT*)(s_dyn + (size_t)QPW * k);  // [QPW][PEND]
-    const uint32_t n_items = P.ctr->n_items;
-    // Work queue: every wave starts on item blockIdx.x without an atomic;
-    // the rest are claimed from KNN_STREAMS interleaved streams (item i in
-    // stream i % KNN_STREAMS, cursor per stream past the items handed out
-    // statically), own stream first, then the others. One device-scope
-    // cursor for all would serialise every claim on one address.
-    const uint32_t G = gridDim.x;
-    const uint32_t s0 = blockIdx.x % KNN_STREAMS;
-    uint32_t it = blockIdx.x;
-    uint32_t sv = 0;  // streams visited after the own one
-    for (;;) {
-        while (it >= n_items && sv < KNN_STREAMS) {
-            const uint32_t s = (s0 + sv) % KNN_STREAMS;
-            uint32_t got = 0;
-            if (lane == 0) got = atomicAdd(&P.ctr->knn_q[s][0], 1u);
-            got = __builtin_amdgcn_readfirstlane(__shfl(got, 0, 64));
-            const uint32_t base = G > s ? (G - s + KNN_STREAMS - 1) / KNN_STREAMS : 0u;  // static items of s
-            it = (base + got) * KNN_STREAMS + s;
-            if (it >= n_items) ++sv;
-        }
-        if (it >= n_items) break;
-        const KnnItem w = P.items[it];
-        const uint32_t t = w.leaf;
-        const uint32_t nr = P.leaf_nr[t];
-        const uint32_t ncand = P.leaf_ncand[t], nch = P.leaf_nch[t], cc = P.leaf_cc[t];
-        const uint32_t qb = P.p1pos[P.leaf_begin[t]];
-        const uint32_t qn = w.q1 - w.q0;
-
-        // The leaf's candidate ranges, concatenated: lane r holds where range
-        // r starts in that order (cpre; past the end for lanes >= nr) and the
-        // offset from there to its P1 index (coff). The range of a position L
-        // is the number of lanes 1..nr-1 with cpre <= L.
-        uint32_t len = 0, rbeg = 0;
-        if (lane < nr) {
-            const uint2 R = P.leaf_ranges[(size_t)t * HALO + lane];
-            rbeg = R.x;
-            len = R.y - R.x;
-        }
-        const uint32_t cpre = wave_incl_scan(len) - len + (lane < nr ? 0u : ncand);
-        const uint32_t coff = rbeg - cpre;
-        auto range_of = [&](uint32_t L) -> uint32_t {
-            return (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(lane >= 1u && lane < nr && cpre <= L));
-        };
-
-        // lists start as k tau placeholders (or empty); lane j holds query
-        // j's coordinates, its distance bound (`worst`: candidates with d2 <=
-        // worst may enter) and its pending count
-        float worst = lane < qn ? INFINITY : -1.0f;
-        uint32_t pcnt = 0;
-        float4 qv = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (lane < qn) {
-            const float tb = P.tau_c[w.q0 + lane];
-            if (tb >= 0.0f) worst = tb;
-            qv = cand4[w.q0 + lane];
-        }
-        for (uint32_t j = 0; j < qn; ++j) {
-            const float tb = P.tau_c[w.q0 + j];
-            if (lane < k) s_list[j * k + lane] = tb >= 0.0f ? make_key(tb, NONE32) : KEY_EMPTY;
-        }
-        wave_lds_fence();
-
-        const uint32_t c_lo = w.chunk * cc;
-        const uint32_t c_hi = min(ncand, c_lo + cc);
-        float4 cn[CPL];
-        uint32_t cni[CPL];  // their P1 indices
-        // candidates [pos, pos + CBLK) of the concatenated order into cn
-        auto load_block = [&](uint32_t pos) {
-            const uint32_t last = min(c_hi, pos + (uint32_t)CBLK) - 1u;
-            const uint32_t ra = range_of(pos), rb = range_of(last);
-            const uint32_t off0 = (uint32_t)__builtin_amdgcn_readlane((int)coff, (int)ra);
-#pragma unroll
-            for (int g = 0; g < CPL; ++g) {
-                const uint32_t Lg = pos + (uint32_t)g * 64u + lane;
-                uint32_t off = off0;
-                for (uint32_t r = ra + 1u; r <= rb; ++r)
-                    if ((uint32_t)__builtin_amdgcn_readlane((int)cpre, (int)r) <= Lg)
-                        off = (uint32_t)__builtin_amdgcn_readlane((int)coff, (int)r);
-                if (Lg < c_hi) {
-                    cn[g] = cand4[off + Lg];
-                    cni[g] = off + Lg;
-                } else {
-                    // NaN coordinates: d2 <= bound never holds
-                    const float nan = __uint_as_float(0x7FC00000u);
-                    cn[g] = make_float4(nan, nan, nan, __uint_as_float(NONE32));
-                    cni[g] = NONE32;
-                }
-            }
-        };
-        // Blocks nearest to the tile in Morton order first, so that the bounds
-        // tighten early: start at the block holding the tile's position in the
-        // concatenated order (or the chunk end nearest to it), then alternate
-        // outwards.
-        const uint32_t ro = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(lane >= 1u && lane < nr && rbeg <= w.q0));
-        const uint32_t p_t = (uint32_t)__builtin_amdgcn_readlane((int)cpre, (int)ro) +
-                             (w.q0 - (uint32_t)__builtin_amdgcn_readlane((int)rbeg, (int)ro));
-        const int nblk = c_lo < c_hi ? (int)((c_hi - c_lo + CBLK - 1) / CBLK) : 0;
-        const int b_start = p_t < c_lo ? 0 : min((int)((p_t - c_lo) / CBLK), nblk - 1);
-        int nx_hi = b_start + 1, nx_lo = b_start - 1;
-        bool up = true;
-        auto next_block = [&]() -> int {
-            if (up && nx_hi < nblk) {
-                up = false;
-                return nx_hi++;
-            }
-            if (nx_lo >= 0) {
-                up = true;
-                return nx_lo--;
-            }
-            if (nx_hi < nblk) return nx_hi++;
-            return -1;
-        };
-        if (nblk > 0) load_block(c_lo + (uint32_t)b_start * CBLK);
-        for (int b = nblk > 0 ? b_start : -1; b >= 0;) {
-            float4 c[CPL];
-            uint32_t ci[CPL];
-#pragma unroll
-            for (int g = 0; g < CPL; ++g) {
-                c[g] = cn[g];
-                ci[g] = cni[g];
-            }
-            const int b_next = next_block();
-            if (b_next >= 0) load_block(c_lo + (uint32_t)b_next * CBLK);
-            b = b_next;
-            // append query j's passing candidates (masks m) to its pending
-            // buffer, merging the buffer into the list when it would overflow
-            auto append = [&](uint32_t j, float wj, unsigned long long (&m)[CPL], const float (&d)[CPL], float4 q) {
-                uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)pcnt, (int)j);
-                const unsigned long long selfkey =
-                    (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j);
-                PT* const pend = s_pend + (size_t)j * PEND;
-                unsigned long long* const lst = s_list + (size_t)j * k;
-#pragma unroll
-                for (int g = 0; g < CPL; ++g) {
-                    if (m[g] == 0ull) continue;
-                    uint32_t pc = (uint32_t)__popcll(m[g]);
-                    if (cnt + pc > (uint32_t)PEND) {
-                        wj = fminf(wj, flush<POS>(lst, pend, cnt, lane, k, selfkey, cand4, q));
-                        cnt = 0;
-#pragma unroll
-                        for (int h = g; h < CPL; ++h) m[h] = __builtin_amdgcn_ballot_w64(d[h] <= wj);
-                        pc = (uint32_t)__popcll(m[g]);
-                        if (pc == 0u) continue;
-                    }
-                    const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
-                        (uint32_t)(m[g] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[g], 0u));
-                    if ((m[g] >> lane) & 1ull) {
-                        if constexpr (POS)
-                            pend[cnt + rank] = ci[g];
-                        else
-                            pend[cnt + rank] = make_key(d[g], __float_as_uint(c[g].w));
-                    }
-                    cnt += pc;
-                }
-                if (lane == j) {
-                    pcnt = cnt;
-                    worst = wj;
-                }
-            };
-            // Cull by the block's bounding box: with lo <= c <= hi per axis,
-            // fl(lo - q) <= fl(c - q) (and likewise above hi), and rounded
-            // squares and sums are monotone, so the box distance computed in
-            // the same order as dist2 is <= the d2 of every candidate in the
-            // block. A query whose box distance exceeds its bound skips the
-            // block; the result is unchanged. (fminf/fmaxf skip the NaN
-            // padding of a ragged block.)
-            float lx = c[0].x, ly = c[0].y, lz = c[0].z, hx = c[0].x, hy = c[0].y, hz = c[0].z;
-#pragma unroll
-            for (int g = 1; g < CPL; ++g) {
-                lx = fminf(lx, c[g].x); ly = fminf(ly, c[g].y); lz = fminf(lz, c[g].z);
-                hx = fmaxf(hx, c[g].x); hy = fmaxf(hy, c[g].y); hz = fmaxf(hz, c[g].z);
-            }
-            lx = wave_min(lx, lane); ly = wave_min(ly, lane); lz = wave_min(lz, lane);
-            hx = wave_max(hx, lane); hy = wave_max(hy, lane); hz = wave_max(hz, lane);
-            const float gx = fmaxf(fmaxf(lx - qv.x, qv.x - hx), 0.0f);
-            const float gy = fmaxf(fmaxf(ly - qv.y, qv.y - hy), 0.0f);
-            const float gz = fmaxf(fmaxf(lz - qv.z, qv.z - hz), 0.0f);
-            const float bd = (gx * gx + gy * gy) + gz * gz;
-            unsigned long long qm = __builtin_amdgcn_ballot_w64(lane < qn && !(bd > worst));
-            while (qm != 0ull) {
-                const uint32_t j = (uint32_t)__ffsll((long long)qm) - 1u;
-                qm &= qm - 1ull;
-                const float4 q = query_of(qv, j);
-                float wj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(worst), (int)j));
-                float d[CPL];
-                unsigned long long m[CPL];
-                unsigned long long any = 0ull;
-                uint32_t tot = 0;
-#pragma unroll
-                for (int g = 0; g < CPL; ++g) {
-                    d[g] = dist2(q, c[g]);
-                    m[g] = __builtin_amdgcn_ballot_w64(d[g] <= wj);
-                    any |= m[g];
-                    tot += (uint32_t)__popcll(m[g]);
-                }
-                // A block that would overflow the pending buffer first lowers
-                // the bound: if at least k + 1 of its candidates (one may be
-                // the query itself) lie within wj * 2^(-1/4), the k-th
-                // distance cannot exceed that, so nothing needed is lost.
-                if (tot > (uint32_t)PEND - (uint32_t)__builtin_amdgcn_readlane((int)pcnt, (int)j) &&
-                    tot > k + 1u && wj < INFINITY) {
-                    for (int i = 0; i < 12; ++i) {
-                        const float t2 = wj * 0.84089642f;
-                        uint32_t c2 = 0;
-#pragma unroll
-                        for (int g = 0; g < CPL; ++g)
-                            c2 += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(d[g] <= t2));
-                        if (c2 < k + 1u) break;
-                        wj = t2;
-                    }
-                    any = 0ull;
-#pragma unroll
-                    for (int g = 0; g < CPL; ++g) {
-                        m[g] = __builtin_amdgcn_ballot_w64(d[g] <= wj);
-                        any |= m[g];
-                    }
-                    if (lane == j) worst = wj;
-                }
-                if (any != 0ull) append(j, wj, m, d, q);
-            }
-        }
-        // drain the pending buffers: when k <= 32, two queries per merge if
-        // both hold at most 32 pending keys
-        if (half) {
-            for (uint32_t j = 0; j < qn; j += 2u) {
-                const uint32_t j1 = j + 1u;
-                const bool two = j1 < qn;
-                const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)pcnt, (int)j);
-                const uint32_t c1 = two ? (uint32_t)__builtin_amdgcn_readlane((int)pcnt, (int)j1) : 0u;
-                if ((c0 | c1) == 0u) continue;
-                const unsigned long long s0 =
-                    (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j);
-                const unsigned long long s1 =
-                    two ? (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j1) : 0ull;
-                unsigned long long* const l0 = s_list + (size_t)j * k;
-                PT* const p0 = s_pend + (size_t)j * PEND;
-                const float4 q0 = query_of(qv, j);
-                const float4 q1 = two ? query_of(qv, j1) : q0;
-                if (c0 <= (uint32_t)PEND_HALF && c1 <= (uint32_t)PEND_HALF) {
-                    float b0, b1;
-                    // without a second query the upper half touches no memory
-                    flush_half<POS>(l0, p0, c0, s0, q0, l0 + k, p0 + PEND, c1, s1, q1, two, lane, k, cand4, &b0,
-                                    &b1);
-                } else {
-                    if (c0) (void)flush<POS>(l0, p0, c0, lane, k, s0, cand4, q0);
-                    if (c1) (void)flush<POS>(l0 + k, p0 + PEND, c1, lane, k, s1, cand4, q1);
-                }
-            }
-        } else {
-            for (uint32_t j = 0; j < qn; ++j) {
-                const uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)pcnt, (int)j);
-                const unsigned long long selfkey =
-                    (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j);
-                if (cnt)
-                    (void)flush<POS>(s_list + (size_t)j * k, s_pend + (size_t)j * PEND, cnt, lane, k, selfkey,
-                                     cand4, query_of(qv, j));
-            }
-        }
-
-        if (nch > 1) {
-            // partial lists [query][chunk][r]: one coalesced row per list,
-            // merged by knn_merge_kernel
-            unsigned long long* base = (unsigned long long*)P.plist + (size_t)P.leaf_plist[t] * k;
-            for (uint32_t j = 0; j < qn; ++j)
-                if (lane < k) base[((size_t)(w.q0 + j - qb) * nch + w.chunk) * k + lane] = s_list[j * k + lane];
-        } else {
-            for (uint32_t j = 0; j < qn; ++j) {
-                const unsigned long long v = lane < k ? s_list[j * k + lane] : KEY_EMPTY;
-                write_final(P, w.q0 + j, k, lane, v);
-            }
-        }
-        wave_lds_fence();
-        it = n_items;  // claim the next one
-    }
-}
-
 // ---------------------------------------------------------------- kNN by culling groups
 //
 // The candidates of an item are visited in aligned groups of KNN_GRP P1
-// positions (one per lane), whose bounding boxes the bound kernel wrote. A
-// group is loaded only if the box passes for at least one query of the
-// tile: a round box-tests GPT groups against the Q queries at once (lane
-// L: query L % Q, group L / Q), with the same fp32 operations as dist2, so a
-// skipped group holds no candidate with d2 <= the query's bound. Positions of
-// a group outside the range's part in this chunk are not candidates; they
-// are given NaN coordinates (d2 <= bound never holds). Groups of the range
-// holding the tile come first, from the tile's group outwards, then the
-// other ranges in order.
+// positions (one per lane), whose bounding boxes the bound kernel wrote. Up
+// to 64 groups at a time are mapped onto the lanes (their boxes loaded in one
+// coalesced load) and box-tested against every query of the tile, with the
+// same fp32 operations as dist2: a query skips a group whose box distance
+// exceeds its bound, so the group holds no candidate with d2 <= that bound.
+// Lane j then holds query j's mask of needed groups; a group is loaded only
+// if some query needs it, the next needed group's candidates being fetched
+// while the current one is tested. Positions of a group outside the range's
+// part in this chunk are not candidates: they get NaN coordinates (d2 <=
+// bound never holds). Groups of the range holding the tile come first, from
+// the tile's group outwards, then the other ranges in order.
 template <bool POS, int Q>
 __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __restrict__ cand4, int kk) {
     using PT = typename Pending<POS>::T;
-    constexpr int GPT = 64 / Q;  // groups per box-test round
-    static_assert(Q * GPT == 64 && Q <= 64, "tile shape");
+    static_assert(Q <= 64, "tile shape");
     extern __shared__ unsigned long long s_dyn[];
     const uint32_t lane = threadIdx.x;
     const uint32_t k = (uint32_t)kk;
     const bool half = k <= 32u;
     unsigned long long* const s_list = s_dyn;           // [Q][k]
     PT* const s_pend = (PT*)(s_dyn + (size_t)Q * k);    // [Q][PEND]
-    const uint32_t jl = lane % (uint32_t)Q;             // this lane's query in box tests
-    const uint32_t ul = lane / (uint32_t)Q;             // this lane's group slot in box tests
     const uint32_t n_items = P.ctr->n_items;
     const uint32_t G = gridDim.x;
     const uint32_t s0 = blockIdx.x % KNN_STREAMS;
@@ -684,102 +405,128 @@ __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __r
         const uint32_t u2n = (lane < nr && lane != ro) ? gn : 0u;
         const uint32_t u2pre = wave_incl_scan(u2n) - u2n;
         const uint32_t n_units = gno + (uint32_t)__builtin_amdgcn_readlane((int)(u2pre + u2n), 63);
-        // unit u -> (range, group): own range outwards, then the others
-        auto unit = [&](uint32_t u, uint32_t* r, uint32_t* g) {
-            if (u < gno) {
-                *r = ro;
-                if (u == 0u) {
-                    *g = gt;
-                } else if (u <= 2u * n_alt) {
-                    const uint32_t d = (u + 1u) >> 1;
-                    *g = (u & 1u) ? gt + d : gt - d;
-                } else {
-                    const uint32_t d = u - n_alt;
-                    *g = n_up > n_dn ? gt + d : gt - d;
-                }
-            } else {
-                const uint32_t v = u - gno;
-                const uint64_t mk = __builtin_amdgcn_ballot_w64(u2n > 0u && u2pre <= v);
-                const uint32_t rr = 63u - (uint32_t)__clzll((long long)mk);
-                *r = rr;
-                *g = (uint32_t)__builtin_amdgcn_readlane((int)g0, (int)rr) + v -
-                     (uint32_t)__builtin_amdgcn_readlane((int)u2pre, (int)rr);
-            }
-        };
 
-        // lists start as k tau placeholders (or empty). Lane L holds query
-        // L % Q's coordinates and bound (`worst`: candidates with d2 <= worst
-        // may enter); lane j < Q holds query j's pending count.
-        const bool qok = jl < qn;
+        // lists start as k tau placeholders (or empty); lane j < qn holds query
+        // j's coordinates, bound (`worst`: candidates with d2 <= worst may
+        // enter) and pending count
         float worst = -1.0f;
         float4 qv = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (qok) {
-            const float tb = P.tau_c[w.q0 + jl];
+        if (lane < qn) {
+            const float tb = P.tau_c[w.q0 + lane];
             worst = tb >= 0.0f ? tb : INFINITY;
-            qv = cand4[w.q0 + jl];
+            qv = cand4[w.q0 + lane];
         }
         uint32_t pcnt = 0;
         for (uint32_t j = 0; j < qn; ++j) {
-            const float tb = P.tau_c[w.q0 + j];
-            if (lane < k) s_list[j * k + lane] = tb >= 0.0f ? make_key(tb, NONE32) : KEY_EMPTY;
+            const float tb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(worst), (int)j));
+            if (lane < k) s_list[j * k + lane] = tb < INFINITY ? make_key(tb, NONE32) : KEY_EMPTY;
         }
         wave_lds_fence();
 
-        for (uint32_t u0 = 0; u0 < n_units; u0 += (uint32_t)GPT) {
-            uint32_t gs[GPT], ra[GPT], rb[GPT];
-#pragma unroll
-            for (int i = 0; i < GPT; ++i) {
-                gs[i] = NONE32;
-                ra[i] = rb[i] = 0u;
-                if (u0 + (uint32_t)i < n_units) {
-                    uint32_t r, g;
-                    unit(u0 + (uint32_t)i, &r, &g);
-                    gs[i] = g;
-                    ra[i] = (uint32_t)__builtin_amdgcn_readlane((int)sa, (int)r);
-                    rb[i] = (uint32_t)__builtin_amdgcn_readlane((int)sb, (int)r);
-                }
-            }
-            // box test of (query jl, group slot ul)
-            uint32_t gmine = gs[0];
-#pragma unroll
-            for (int i = 1; i < GPT; ++i)
-                if (ul == (uint32_t)i) gmine = gs[i];
-            bool need = false;
-            if (qok && gmine != NONE32) {
-                const GroupBox B = P.gbox[gmine];
-                const float gx = fmaxf(fmaxf(B.lo.x - qv.x, qv.x - B.hi.x), 0.0f);
-                const float gy = fmaxf(fmaxf(B.lo.y - qv.y, qv.y - B.hi.y), 0.0f);
-                const float gz = fmaxf(fmaxf(B.lo.z - qv.z, qv.z - B.hi.z), 0.0f);
-                need = !((gx * gx + gy * gy) + gz * gz > worst);
-            }
-            const unsigned long long nm = __builtin_amdgcn_ballot_w64(need);
-            if (nm == 0ull) continue;
-            // load the groups some query needs, then test their candidates
-            float4 c[GPT];
-            uint32_t cp[GPT];
-#pragma unroll
-            for (int i = 0; i < GPT; ++i) {
-                cp[i] = NONE32;
-                if ((nm >> (i * Q)) & (Q == 64 ? ~0ull : ((1ull << Q) - 1ull))) {
-                    const uint32_t p = gs[i] * (uint32_t)KNN_GRP + lane;
-                    if (p >= ra[i] && p < rb[i]) {
-                        c[i] = cand4[p];
-                        cp[i] = p;
-                    } else {
-                        const float nan = __uint_as_float(0x7FC00000u);
-                        c[i] = make_float4(nan, nan, nan, __uint_as_float(NONE32));
+        uint32_t tight = 0;  // lane j: query j's bound is already a k-th distance of real candidates
+        for (uint32_t ub = 0; ub < n_units; ub += 64u) {
+            // lane u: unit ub + u -> its range's part [ua, ue) and group ug
+            const uint32_t u = ub + lane;
+            uint32_t ug = 0, ua = 0, ue = 0;
+            const bool uok = u < n_units;
+            {
+                uint32_t r = ro;
+                if (u < gno) {
+                    if (u == 0u) ug = gt;
+                    else if (u <= 2u * n_alt) ug = (u & 1u) ? gt + ((u + 1u) >> 1) : gt - ((u + 1u) >> 1);
+                    else ug = n_up > n_dn ? gt + (u - n_alt) : gt - (u - n_alt);
+                } else {
+                    const uint32_t v = u - gno;
+                    uint32_t vg = 0;
+                    for (uint32_t q = 0; q < nr; ++q) {
+                        const uint32_t pn = (uint32_t)__builtin_amdgcn_readlane((int)u2n, (int)q);
+                        const uint32_t pp = (uint32_t)__builtin_amdgcn_readlane((int)u2pre, (int)q);
+                        if (pn > 0u && pp <= v) {
+                            r = q;
+                            vg = (uint32_t)__builtin_amdgcn_readlane((int)g0, (int)q) + (v - pp);
+                        }
                     }
+                    ug = vg;
                 }
+                ua = (uint32_t)__shfl((int)sa, (int)r, 64);
+                ue = (uint32_t)__shfl((int)sb, (int)r, 64);
             }
-#pragma unroll
-            for (int i = 0; i < GPT; ++i) {
-                unsigned long long qm = (nm >> (i * Q)) & (Q == 64 ? ~0ull : ((1ull << Q) - 1ull));
+            // lane u: its group's box, the smallest box distance to a query of
+            // the tile and whether any query needs the group now
+            GroupBox B{};
+            if (uok) B = P.gbox[ug];
+            float bmin = INFINITY;
+            bool need = false;
+            for (uint32_t j = 0; j < qn; ++j) {
+                const float4 q = query_of(qv, j);
+                const float wj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(worst), (int)j));
+                const float gx = fmaxf(fmaxf(B.lo.x - q.x, q.x - B.hi.x), 0.0f);
+                const float gy = fmaxf(fmaxf(B.lo.y - q.y, q.y - B.hi.y), 0.0f);
+                const float gz = fmaxf(fmaxf(B.lo.z - q.z, q.z - B.hi.z), 0.0f);
+                const float bd = (gx * gx + gy * gy) + gz * gz;
+                bmin = fminf(bmin, bd);
+                need = need || !(bd > wj);
+            }
+            need = need && uok;
+            const uint32_t nn = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(need));
+            if (nn == 0u) continue;
+            // needed groups nearest first: sorted descending over the lanes, so
+            // the i-th nearest sits in lane 63 - i
+            const unsigned long long sk0 =
+                need ? (((unsigned long long)(nn > KNN_SORT_MIN_UNITS ? __float_as_uint(bmin) : 0u) << 32) | (63u - lane))
+                     : ~0ull;
+            const unsigned long long sk = nn > KNN_SORT_MIN_UNITS ? sort64_desc(sk0, lane) : sk0;
+            // unsorted: the needed lanes' keys keep unit order (key 63 - u); the
+            // i-th needed one is found by rank
+            const unsigned long long needm = __builtin_amdgcn_ballot_w64(need);
+            auto unit_of = [&](uint32_t i) -> uint32_t {
+                if (nn > KNN_SORT_MIN_UNITS) return 63u - ((uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)sk, 63 - (int)i));
+                unsigned long long mm = needm;
+                for (uint32_t x = 0; x < i; ++x) mm &= mm - 1ull;
+                return (uint32_t)__ffsll((long long)mm) - 1u;
+            };
+            // candidates of unit uu into c (NaN outside its range part)
+            auto load_unit = [&](uint32_t uu, float4& c, uint32_t& cp) {
+                const uint32_t gg = (uint32_t)__builtin_amdgcn_readlane((int)ug, (int)uu);
+                const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)ua, (int)uu);
+                const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)ue, (int)uu);
+                const uint32_t p = gg * (uint32_t)KNN_GRP + lane;
+                if (p >= a && p < e) {
+                    c = cand4[p];
+                    cp = p;
+                } else {
+                    const float nan = __uint_as_float(0x7FC00000u);
+                    c = make_float4(nan, nan, nan, __uint_as_float(NONE32));
+                    cp = NONE32;
+                }
+            };
+            float4 cn = make_float4(0.f, 0.f, 0.f, 0.f);
+            uint32_t cpn = NONE32;
+            load_unit(unit_of(0), cn, cpn);
+            for (uint32_t i = 0; i < nn; ++i) {
+                const uint32_t uu = unit_of(i);
+                const float4 c = cn;
+                const uint32_t cp = cpn;
+                if (i + 1u < nn) load_unit(unit_of(i + 1u), cn, cpn);
+                // the queries that need this group with their current bounds
+                // (lane j: query j)
+                const float lx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(B.lo.x), (int)uu));
+                const float ly = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(B.lo.y), (int)uu));
+                const float lz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(B.lo.z), (int)uu));
+                const float hx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(B.hi.x), (int)uu));
+                const float hy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(B.hi.y), (int)uu));
+                const float hz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(B.hi.z), (int)uu));
+                const float gx = fmaxf(fmaxf(lx - qv.x, qv.x - hx), 0.0f);
+                const float gy = fmaxf(fmaxf(ly - qv.y, qv.y - hy), 0.0f);
+                const float gz = fmaxf(fmaxf(lz - qv.z, qv.z - hz), 0.0f);
+                unsigned long long qm =
+                    __builtin_amdgcn_ballot_w64(lane < qn && !((gx * gx + gy * gy) + gz * gz > worst));
                 while (qm != 0ull) {
                     const uint32_t j = (uint32_t)__ffsll((long long)qm) - 1u;
                     qm &= qm - 1ull;
                     const float4 q = query_of(qv, j);
                     float wj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(worst), (int)j));
-                    const float d = dist2(q, c[i]);
+                    const float d = dist2(q, c);
                     unsigned long long m = __builtin_amdgcn_ballot_w64(d <= wj);
                     if (m == 0ull) continue;
                     uint32_t pc = (uint32_t)__popcll(m);
@@ -797,10 +544,12 @@ __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __r
                     }
                     uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)pcnt, (int)j);
                     PT* const pend = s_pend + (size_t)j * PEND;
+                    const unsigned long long selfkey =
+                        (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j);
+                    bool tj = ((uint32_t)__builtin_amdgcn_readlane((int)tight, (int)j)) != 0u;
                     if (cnt + pc > (uint32_t)PEND) {
-                        const unsigned long long selfkey =
-                            (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j);
                         wj = fminf(wj, flush<POS>(s_list + (size_t)j * k, pend, cnt, lane, k, selfkey, cand4, q));
+                        tj = tj || cnt > k;
                         cnt = 0;
                         m = __builtin_amdgcn_ballot_w64(d <= wj);
                         pc = (uint32_t)__popcll(m);
@@ -810,14 +559,25 @@ __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __r
                                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
                         if ((m >> lane) & 1ull) {
                             if constexpr (POS)
-                                pend[cnt + rank] = cp[i];
+                                pend[cnt + rank] = cp;
                             else
-                                pend[cnt + rank] = make_key(d, __float_as_uint(c[i].w));
+                                pend[cnt + rank] = make_key(d, __float_as_uint(c.w));
                         }
                         cnt += pc;
                     }
-                    if (lane == j) pcnt = cnt;
-                    if (jl == j) worst = wj;
+                    // the first time k + 1 candidates are pending (one may be
+                    // the query), merge them: the bound becomes a true k-th
+                    // distance for the groups still to come
+                    if (!tj && cnt > k && n_units > KNN_TIGHT_MIN_UNITS) {
+                        wj = fminf(wj, flush<POS>(s_list + (size_t)j * k, pend, cnt, lane, k, selfkey, cand4, q));
+                        cnt = 0;
+                        tj = true;
+                    }
+                    if (lane == j) {
+                        pcnt = cnt;
+                        worst = wj;
+                        tight = tj ? 1u : 0u;
+                    }
                 }
             }
         }
@@ -1000,7 +760,7 @@ size_t knn_lds_bytes(int k, bool pos) {
 }
 
 void launch_knn(const Plan& P, int k, int num_cus, hipStream_t st) {
-    const unsigned blocks = (unsigned)(num_cus > 0 ? num_cus : 256) * 16u;
+    const unsigned blocks = (unsigned)(num_cus > 0 ? num_cus : 256) * (P.n > KNN_POS_MIN_N ? 20u : 16u);
     // Large batches run long enough for occupancy to pay (positions); a single
     // frame's run is set by its longest items, where a gather per merge costs
     // more (keys).
