@@ -143,6 +143,7 @@ gdn::Plan make_plan(uint32_t n, uint32_t nf, int k, char* base) {
     P.cand4 = (float4*)take(16 * N);
     P.cand_leaf = (uint32_t*)take(4 * N);
     P.nbr = (uint32_t*)take(4 * N * k);
+    P.inv_p1 = (uint32_t*)take(4 * N);
     P.nbr_d2 = (float*)take(4 * N * k);
     P.r2k = (float*)take(4 * N);
     P.krec = (uint4*)take(16 * N);
@@ -155,7 +156,7 @@ gdn::Plan make_plan(uint32_t n, uint32_t nf, int k, char* base) {
     P.p2 = (uint8_t*)take(N);
     P.stage_c = (uint8_t*)take(N);
     P.score_c = (double*)take(8 * N);
-    P.rec_o = (NbrRec*)take(sizeof(NbrRec) * N);
+    P.rec_p = (NbrRec*)take(sizeof(NbrRec) * N);
     P.items = (KnnItem*)take(sizeof(KnnItem) * (size_t)P.items_max);
     P.plist = (uint64_t*)take(8 * (size_t)P.plist_max * k);
     P.bytes = off;

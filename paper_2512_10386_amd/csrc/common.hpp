@@ -82,7 +82,7 @@ struct Counters {
 };
 
 // What the score reads of a neighbour, in one 32-byte record at the
-// neighbour's original index (one gather instead of two).
+// neighbour's P1 position (one gather instead of two).
 struct __align__(32) NbrRec {
     float4 p;      // x, y, z (bit copies of the input), original index bits
     double gpow;   // rho^(alpha/2)
@@ -192,10 +192,11 @@ struct Plan {
     // compacted P1 (query/candidate index q)
     float4* cand4;            // [n]
     uint32_t* cand_leaf;      // [n]
-    uint32_t* nbr;            // [n][k] original indices
+    uint32_t* nbr;            // [n][k] P1 positions of the neighbours (sorted by d2, then original index)
+    uint32_t* inv_p1;         // [n] by original index: the P1 position of a P1 point
     float* nbr_d2;            // [n][k]
     float* r2k;               // [n] (written by the density kernel from krec)
-    uint4* krec;              // [n] k-th neighbour (none: 0xFFFFFFFF), fp32 bits of the (k-1)-th and k-th d2
+    uint4* krec;              // [n] k-th neighbour's P1 position (none: 0xFFFFFFFF), fp32 bits of the (k-1)-th and k-th d2
     uint2* outrec;            // [n] by original index: fp32 score bits, stage (large inputs' outputs)
     float* tau_c;             // [n] per-query upper bound of r^2_K (-1: none)
     GroupBox* gbox;           // [ceil(n / KNN_GRP)] boxes of aligned groups of the P1 order
@@ -205,7 +206,7 @@ struct Plan {
     uint8_t* p2;              // [n]
     uint8_t* stage_c;         // [n] 1 density-removed, 2 score-removed, 3 kept
     double* score_c;          // [n]
-    NbrRec* rec_o;            // [n] original order: coordinates, rho^(alpha/2)
+    NbrRec* rec_p;            // [n] P1 order: coordinates, rho^(alpha/2)
     // kNN work
     KnnItem* items;           // [items_max]
     uint32_t items_max;

@@ -23,7 +23,11 @@ __global__ __launch_bounds__(256) void dump_kernel(Plan P, int what, void* dst) 
             case GDN_DUMP_NBR_IDX:
                 if (pt)
                     for (uint32_t r = 0; r < k; ++r)
-                        ((uint32_t*)dst)[(size_t)i * k + r] = in1 ? P.nbr[(size_t)qi * k + r] : 0xFFFFFFFFu;
+                    {
+                        // neighbours are stored by P1 position: map back to the original index
+                        const uint32_t pj = in1 ? P.nbr[(size_t)qi * k + r] : 0xFFFFFFFFu;
+                        ((uint32_t*)dst)[(size_t)i * k + r] = pj != 0xFFFFFFFFu ? __float_as_uint(P.cand4[pj].w) : pj;
+                    }
                 break;
             case GDN_DUMP_NBR_D2:
                 if (pt)

@@ -36,17 +36,17 @@ __device__ __forceinline__ double wave_sum_f(double v) {
     return v;
 }
 
-// ln rho of every P1 point, at its original (batch) index: the neighbours'
-// densities are read there. rho = 0 (fewer than k candidates) gives -inf.
-__global__ __launch_bounds__(256) void fit_prep_kernel(Plan P, double* __restrict__ lrho_o) {
+// ln rho of every P1 point, at its P1 position (where the neighbour lists
+// point). rho = 0 (fewer than k candidates) gives -inf.
+__global__ __launch_bounds__(256) void fit_prep_kernel(Plan P, double* __restrict__ lrho_p) {
     const uint32_t np1 = P.ctr->n_p1;
     for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < np1; q += gridDim.x * blockDim.x)
-        lrho_o[__float_as_uint(P.cand4[q].w)] = log(P.rho_c[q]);
+        lrho_p[q] = log(P.rho_c[q]);
 }
 
 __global__ __launch_bounds__(256) void fit_kernel(Plan P, const float* __restrict__ xyz,
                                                   const uint8_t* __restrict__ label,
-                                                  const double* __restrict__ lrho_o, int kk, FitArgs a,
+                                                  const double* __restrict__ lrho_p, int kk, FitArgs a,
                                                   double* __restrict__ part) {
     __shared__ double s_red[4][FIT_PARTS];
     const uint32_t np1 = P.ctr->n_p1;
@@ -68,12 +68,15 @@ __global__ __launch_bounds__(256) void fit_kernel(Plan P, const float* __restric
             const uint32_t j = P.nbr[(size_t)qi * k + r];
             if (j < P.n) {
                 const double med = P.leaf_rho_med[P.cand_leaf[qi]];
-                const double lr = log(P.rho_c[qi]) + lrho_o[j] - log(med * med + a.eps);
+                const double lr = log(P.rho_c[qi]) + lrho_p[j] - log(med * med + a.eps);
                 const double r64 = P.r64_c[qi];
                 const double r2 = r64 * r64;
-                const double dx = (double)xyz[3 * (size_t)j] - (double)xyz[3 * (size_t)i];
-                const double dy = (double)xyz[3 * (size_t)j + 1] - (double)xyz[3 * (size_t)i + 1];
-                const double dz = (double)xyz[3 * (size_t)j + 2] - (double)xyz[3 * (size_t)i + 2];
+                // the neighbour (P1 position j) and the query from their sorted
+                // copies of the input coordinates
+                const float4 cj = P.cand4[j], ci = P.cand4[qi];
+                const double dx = (double)cj.x - (double)ci.x;
+                const double dy = (double)cj.y - (double)ci.y;
+                const double dz = (double)cj.z - (double)ci.z;
                 const double d2 = dx * dx + dy * dy + dz * dz;
                 const double lk = log(d2 + a.eps);
                 const double w_den = exp(0.5 * a.alpha * lr);
@@ -153,14 +156,14 @@ size_t fit_workspace_bytes(uint32_t n) {
 
 void launch_fit(const Plan& P, const float* xyz, const uint8_t* label, const FitArgs& a, void* workspace,
                 double* out, hipStream_t st) {
-    double* lrho_o = (double*)workspace;
+    double* lrho_p = (double*)workspace;
     double* part = (double*)((char*)workspace + (((size_t)8 * P.n + 255) & ~(size_t)255));
     unsigned pb = (P.n + 255) / 256;
     if (pb > 4096) pb = 4096;
     if (pb == 0) pb = 1;
-    hipLaunchKernelGGL(fit_prep_kernel, dim3(pb), dim3(256), 0, st, P, lrho_o);
+    hipLaunchKernelGGL(fit_prep_kernel, dim3(pb), dim3(256), 0, st, P, lrho_p);
     const unsigned nb = fit_blocks(P.n, P.k);
-    hipLaunchKernelGGL(fit_kernel, dim3(nb), dim3(256), 0, st, P, xyz, label, lrho_o, P.k, a, part);
+    hipLaunchKernelGGL(fit_kernel, dim3(nb), dim3(256), 0, st, P, xyz, label, lrho_p, P.k, a, part);
     hipLaunchKernelGGL(fit_final_kernel, dim3(1), dim3(64), 0, st, part, nb, out);
 }
 

@@ -230,10 +230,47 @@ __device__ __forceinline__ void write_final(const Plan& P, uint32_t qi, uint32_t
     const float d = ok ? __uint_as_float((uint32_t)(v >> 32)) : INFINITY;
     const float d1 = __shfl(d, k >= 2u ? (int)k - 2 : 0, 64);
     if (lane < k) {
-        P.nbr[(size_t)qi * k + lane] = ok ? (uint32_t)v : NONE32;
+        // the list is ordered by (d2, original index); the neighbour is stored
+        // by its P1 position, where everything read about it later sits in
+        // Morton order
+        const uint32_t pj = ok ? P.inv_p1[(uint32_t)v] : NONE32;
+        P.nbr[(size_t)qi * k + lane] = pj;
         P.nbr_d2[(size_t)qi * k + lane] = d;
         // the k-th entry and the (k-1)-th distance again, densely, for the density
-        if (lane == k - 1) P.krec[qi] = make_uint4(ok ? (uint32_t)v : NONE32, __float_as_uint(d1), __float_as_uint(d), 0u);
+        if (lane == k - 1) P.krec[qi] = make_uint4(pj, __float_as_uint(d1), __float_as_uint(d), 0u);
+    }
+}
+
+// The final lists of a tile's qn queries (in LDS, k keys each), eight
+// queries at a time: their position lookups are issued before any store, so
+// the tile waits for a round trip per eight queries instead of per query.
+__device__ __forceinline__ void write_tile(const Plan& P, const unsigned long long* s_list, uint32_t q0, uint32_t qn,
+                                           uint32_t k, uint32_t lane) {
+    constexpr int B = 8;
+    for (uint32_t j0 = 0; j0 < qn; j0 += (uint32_t)B) {
+        unsigned long long v[B];
+        uint32_t pj[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            v[j] = (j0 + (uint32_t)j < qn && lane < k) ? s_list[(j0 + (uint32_t)j) * k + lane] : KEY_EMPTY;
+            pj[j] = NONE32;
+        }
+#pragma unroll
+        for (int j = 0; j < B; ++j)
+            if (lane < k && real_entry(v[j])) pj[j] = P.inv_p1[(uint32_t)v[j]];
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            if (j0 + (uint32_t)j >= qn) break;
+            const uint32_t qi = q0 + j0 + (uint32_t)j;
+            const bool ok = lane < k && real_entry(v[j]);
+            const float d = ok ? __uint_as_float((uint32_t)(v[j] >> 32)) : INFINITY;
+            const float d1 = __shfl(d, k >= 2u ? (int)k - 2 : 0, 64);
+            if (lane < k) {
+                P.nbr[(size_t)qi * k + lane] = pj[j];
+                P.nbr_d2[(size_t)qi * k + lane] = d;
+                if (lane == k - 1) P.krec[qi] = make_uint4(pj[j], __float_as_uint(d1), __float_as_uint(d), 0u);
+            }
+        }
     }
 }
 
@@ -623,10 +660,7 @@ __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __r
             for (uint32_t j = 0; j < qn; ++j)
                 if (lane < k) base[((size_t)(w.q0 + j - qb) * nch + w.chunk) * k + lane] = s_list[j * k + lane];
         } else {
-            for (uint32_t j = 0; j < qn; ++j) {
-                const unsigned long long v = lane < k ? s_list[j * k + lane] : KEY_EMPTY;
-                write_final(P, w.q0 + j, k, lane, v);
-            }
+            write_tile(P, s_list, w.q0, qn, k, lane);
         }
         wave_lds_fence();
         it = n_items;

@@ -390,11 +390,14 @@ struct P1Emit {
     const uint32_t* leaf_of;
     float4* cand4;
     uint32_t* cand_leaf;
+    uint32_t* inv_p1;
     __device__ void operator()(uint32_t s, uint32_t ex, uint32_t f) const {
         p1pos[s] = ex;
         if (f) {
-            cand4[ex] = pos4[s];
+            const float4 c = pos4[s];
+            cand4[ex] = c;
             cand_leaf[ex] = leaf_of[s];
+            inv_p1[__float_as_uint(c.w)] = ex;
         }
     }
 };
@@ -409,7 +412,7 @@ struct P1Fin {
 };
 
 void launch_p1_compact(const Plan& P, hipStream_t st) {
-    launch_scan(P1Get{P.p1}, P1Emit{P.p1pos, P.pos4, P.leaf_of, P.cand4, P.cand_leaf},
+    launch_scan(P1Get{P.p1}, P1Emit{P.p1pos, P.pos4, P.leaf_of, P.cand4, P.cand_leaf, P.inv_p1},
                 P1Fin{P.ctr, P.p1pos, P.n}, nullptr, P.n, P.scan_status + P.scan_tiles,
                 &P.ctr->scan_tile_ctr[1], &P.ctr->status, st);
 }

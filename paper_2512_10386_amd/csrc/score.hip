@@ -69,10 +69,12 @@ __device__ __forceinline__ Dens density_at(const Plan& P, const float* __restric
         // the query's coordinates: cand4 holds bit copies of the input
         const float4 cq = P.cand4[qi];
         const double xi = cq.x, yi = cq.y, zi = cq.z;
+        // neighbour at P1 position j: its sorted copy of the input coordinates
         auto d2_to = [&](uint32_t j) -> double {
-            const double dx = (double)xyz[3 * (size_t)j] - xi;
-            const double dy = (double)xyz[3 * (size_t)j + 1] - yi;
-            const double dz = (double)xyz[3 * (size_t)j + 2] - zi;
+            const float4 cj = P.cand4[j];
+            const double dx = (double)cj.x - xi;
+            const double dy = (double)cj.y - yi;
+            const double dz = (double)cj.z - zi;
             return dx * dx + dy * dy + dz * dz;
         };
         const float thr = out.r2 * (1.0f - 1.0f / 65536.0f);
@@ -321,8 +323,7 @@ __global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params p
             const double sr = prm.sigma * P.r64_c[qi];
             P.afac_c[qi] = make_double2(pow_ha<SQRT>(P.rho_c[qi] / den, ha), 1.0 / (2.0 * sr * sr));
             // rho_j^(alpha/2) of Eq. 17's factored density weight, by original index
-            const float4 c = P.cand4[qi];
-            P.rec_o[__float_as_uint(c.w)] = NbrRec{c, pow_ha<SQRT>(P.rho_c[qi], ha), 0.0};
+            P.rec_p[qi] = NbrRec{P.cand4[qi], pow_ha<SQRT>(P.rho_c[qi], ha), 0.0};
         }
         if (threadIdx.x == 0) { P.leaf_rho_med[t] = med; P.leaf_r2cut[t] = cut; }
         __syncthreads();
@@ -431,8 +432,7 @@ __global__ __launch_bounds__(256) void leaf_select_small_kernel(Plan P, Params p
             P.p2[qi] = (!shortv[j] && __uint_as_float((uint32_t)r2v.v[j]) <= cut) ? 1 : 0;
             const double sr = prm.sigma * r64v[j];
             P.afac_c[qi] = make_double2(pow_ha<SQRT>(rho / den, ha), 1.0 / (2.0 * sr * sr));
-            const float4 c = P.cand4[qi];
-            P.rec_o[__float_as_uint(c.w)] = NbrRec{c, pow_ha<SQRT>(rho, ha), 0.0};
+            P.rec_p[qi] = NbrRec{P.cand4[qi], pow_ha<SQRT>(rho, ha), 0.0};
         }
         if (lane == 0) { P.leaf_rho_med[t] = med; P.leaf_r2cut[t] = cut; }
     }
@@ -492,7 +492,7 @@ __global__ __launch_bounds__(256) void score_kernel(Plan P, int kk, double eps, 
         if (!live) j = 0xFFFFFFFFu;
         double term = 0.0;
         if (j < P.n) {
-            const NbrRec R = P.rec_o[j];
+            const NbrRec R = P.rec_p[j];
             const double dx = (double)R.p.x - (double)a.x;
             const double dy = (double)R.p.y - (double)a.y;
             const double dz = (double)R.p.z - (double)a.z;
