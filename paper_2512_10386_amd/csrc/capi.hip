@@ -130,6 +130,7 @@ gdn::Plan make_plan(uint32_t n, uint32_t nf, int k, char* base) {
     P.leaf_h = (float*)take(4 * N);
     P.leaf_nr = (uint32_t*)take(4 * N);
     P.leaf_ranges = (uint2*)take(sizeof(uint2) * HALO * N);
+    P.leaf_own = (uint2*)take(sizeof(uint2) * N);
     P.leaf_ncand = (uint32_t*)take(4 * N);
     P.leaf_nch = (uint32_t*)take(4 * N);
     P.leaf_cc = (uint32_t*)take(4 * N);

@@ -179,6 +179,7 @@ struct Plan {
     float* leaf_h;            // [n]
     uint32_t* leaf_nr;        // [n] number of candidate ranges
     uint2* leaf_ranges;       // [n][HALO] compacted candidate ranges
+    uint2* leaf_own;          // [n] the candidate range holding the leaf's own P1 points
     uint32_t* leaf_ncand;     // [n]
     uint32_t* leaf_nch;       // [n] candidate chunks
     uint32_t* leaf_cc;        // [n] chunk length

@@ -98,13 +98,18 @@ static_assert(BOUND_Q % KNN_GRP == 0, "a bound block covers whole culling groups
 // [qb, qe), a run of candidates holding the query; then, over the run's points
 // within BOUND_MARGIN positions, count those under each rung of the ladder
 // (LEVELS rungs, each the previous times STEP) and keep the smallest threshold
-// still holding k. -1 when the run has <= k points.
+// still holding k; finally bisect (geometrically, BISECT steps) between that
+// rung and the next one down, keeping the smaller threshold whenever it still
+// holds k. Every threshold kept holds k of the query's own candidates, so it
+// is >= its k-th distance. -1 when the run has <= k points.
 // The BOUND_SPLIT lanes of a query each take every BOUND_SPLIT-th point and
 // combine their maxima and counts (exact, so tau does not depend on the
 // split); every lane of the wave calls this, `run` false for idle ones.
+constexpr int BOUND_WPL = (2 * BOUND_MARGIN + 1 + BOUND_SPLIT - 1) / BOUND_SPLIT;  // window points per lane
 template <int LEVELS, class Pts>
 __device__ float query_bound(Pts cand4, uint32_t qb, uint32_t qe, uint32_t qi, int k, uint32_t sub, bool live) {
     constexpr float STEP = LEVELS == 10 ? 0.70710678f : 0.5f;
+    constexpr int BISECT = LEVELS == 10 ? 4 : 5;  // down to a factor 2^(1/32)
     static_assert(LEVELS == 10 || LEVELS == 5, "ladder");
     const bool run = live && qe - qb > (uint32_t)k;
     float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -117,11 +122,34 @@ __device__ float query_bound(Pts cand4, uint32_t qb, uint32_t qe, uint32_t qi, i
         wlo = (qi - qb > (uint32_t)BOUND_MARGIN) ? qi - (uint32_t)BOUND_MARGIN : qb;
         whi = min(qe, qi + (uint32_t)BOUND_MARGIN + 1u);
     }
+    static_assert(BOUND_SPLIT == 8, "the lane groups are DPP rows of 8");
+    const uint32_t lane = threadIdx.x & 63u;
+    // sum / max over the BOUND_SPLIT lanes of a query (lanes ^ 1, 2, 4), by DPP
+    auto sum8 = [&](uint32_t c) -> uint32_t {
+        c += xor_lane<1>(c, lane);
+        c += xor_lane<2>(c, lane);
+        return c + xor_lane<4>(c, lane);
+    };
     float tau = 0.0f;
     for (uint32_t j = s0 + sub; j < s1; j += BOUND_SPLIT)
         if (j != qi) tau = fmaxf(tau, dist2(q, cand4[j]));
+    tau = fmaxf(tau, xor_f32<1>(tau, lane));
+    tau = fmaxf(tau, xor_f32<2>(tau, lane));
+    tau = fmaxf(tau, xor_f32<4>(tau, lane));
+    // this lane's window distances (the query itself and absent points: +inf)
+    float dw[BOUND_WPL];
 #pragma unroll
-    for (int o = 1; o < BOUND_SPLIT; o <<= 1) tau = fmaxf(tau, __shfl_xor(tau, o, 64));
+    for (int i = 0; i < BOUND_WPL; ++i) {
+        const uint32_t j = wlo + sub + (uint32_t)i * BOUND_SPLIT;
+        dw[i] = (j < whi && j != qi) ? dist2(q, cand4[j]) : INFINITY;
+    }
+    auto count_le = [&](float t) -> uint32_t {
+        uint32_t c = 0;
+#pragma unroll
+        for (int i = 0; i < BOUND_WPL; ++i) c += (dw[i] <= t) ? 1u : 0u;
+        return sum8(c);
+    };
+    // the rungs' counts are independent: all of them first, then the choice
     float th[LEVELS];
     uint32_t cnt[LEVELS];
     float f = tau;
@@ -130,19 +158,19 @@ __device__ float query_bound(Pts cand4, uint32_t qb, uint32_t qe, uint32_t qi, i
         f = f * STEP;
         th[m] = f;
         cnt[m] = 0;
-    }
-    for (uint32_t j = wlo + sub; j < whi; j += BOUND_SPLIT) {
-        const float d = dist2(q, cand4[j]);
-        const uint32_t notself = (j != qi) ? 1u : 0u;
 #pragma unroll
-        for (int m = 0; m < LEVELS; ++m) cnt[m] += (d <= th[m]) ? notself : 0u;
+        for (int i = 0; i < BOUND_WPL; ++i) cnt[m] += (dw[i] <= f) ? 1u : 0u;
     }
     float best = tau;
 #pragma unroll
-    for (int m = 0; m < LEVELS; ++m) {
+    for (int m = 0; m < LEVELS; ++m)
+        if (sum8(cnt[m]) >= (uint32_t)k) best = th[m];
+    float r = STEP;
 #pragma unroll
-        for (int o = 1; o < BOUND_SPLIT; o <<= 1) cnt[m] += (uint32_t)__shfl_xor((int)cnt[m], o, 64);
-        if (cnt[m] >= (uint32_t)k) best = th[m];
+    for (int b = 0; b < BISECT; ++b) {
+        r = sqrtf(r);
+        const float mid = best * r;
+        if (count_le(mid) >= (uint32_t)k) best = mid;
     }
     return run ? best : -1.0f;
 }
@@ -196,17 +224,9 @@ __global__ __launch_bounds__(BOUND_Q * BOUND_SPLIT) void knn_bound_kernel(Plan P
             qe = P.p1pos[P.leaf_begin[t + 1]];
             // the window lives in the merged candidate range holding the query,
             // which may reach past a small leaf (every point of it is a candidate)
-            rb = qb;
-            re = qe;
-            const uint32_t nr = P.leaf_nr[t];
-            for (uint32_t r = 0; r < nr; ++r) {
-                const uint2 R = P.leaf_ranges[(size_t)t * HALO + r];
-                if (R.x <= qi && qi < R.y) {
-                    rb = R.x;
-                    re = R.y;
-                    break;
-                }
-            }
+            const uint2 R = P.leaf_own[t];
+            rb = R.x;
+            re = R.y;
         }
         const float b = query_bound<LEVELS>(StagedPts{s_pts, lo}, rb, re, qi, k, sub, live);
         if (live && sub == 0u) {

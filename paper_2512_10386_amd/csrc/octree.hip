@@ -525,7 +525,11 @@ __global__ __launch_bounds__(256) void halo_kernel(Plan P, uint32_t cap) {
             const unsigned long long later = sm & ~(below | (1ull << lane));
             const uint32_t nxt = later ? (uint32_t)__ffsll((long long)later) - 1u - (lane & 32u) : m;
             const uint32_t o = (uint32_t)__popcll(sm & below);
-            P.leaf_ranges[(size_t)t * HALO + o] = make_uint2(cur.x, s_s[grp][nxt - 1u].y);
+            const uint2 run = make_uint2(cur.x, s_s[grp][nxt - 1u].y);
+            P.leaf_ranges[(size_t)t * HALO + o] = run;
+            // the run holding the leaf's own cell (block position 13) holds its queries
+            const uint2 own = s_r[grp][13];
+            if (own.y > own.x && run.x <= own.x && own.x < run.y) P.leaf_own[t] = run;
         }
         uint32_t len = (uint32_t)g < m ? cur.y - cur.x : 0u;
         for (int o = 16; o > 0; o >>= 1) len += (uint32_t)__shfl_xor((int)len, o, 32);
