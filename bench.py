@@ -37,10 +37,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def knn_traffic(knn_ms_launch):
-    """HBM bytes per kNN launch from the committed PMC summary, if it was taken
+def knn_traffic(name="knn_lidar_120k_traffic.json"):
+    """HBM bytes per kNN launch from a committed PMC summary, if it was taken
     on the current kernel source; otherwise None."""
-    path = os.path.join(ROOT, "profiles", "knn_lidar_120k_traffic.json")
+    path = os.path.join(ROOT, "profiles", name)
     src = os.path.join(ROOT, "paper_2512_10386_amd", "csrc", "knn.hip")
     try:
         rec = json.load(open(path))
@@ -96,8 +96,9 @@ def cpu_baseline(xyz, params, workload, budget_s=12.0, single_budget_s=10.0):
     return rec
 
 
-def bench_batch(steps):
-    """The 64-frame batch: autotune, graph replay, eager batch, plain loop."""
+def bench_batch(steps, cap=0, chunk=0, plain_loop=True):
+    """The 64-frame batch: autotune (unless cap is given), graph replay, eager
+    batch, and the same frames as plain calls (unless plain_loop is False)."""
     import numpy as np
     import torch
     from paper_2512_10386_amd import synth
@@ -112,10 +113,15 @@ def bench_batch(steps):
     xyz = torch.from_numpy(np.concatenate(frames)).to(dev)
     offd = torch.from_numpy(off).to(dev)
     log(f"[bench] batch: {nf} frames, {n} points (min {min(sizes)}, max {max(sizes)})")
-    bd = BatchDenoiser(0, **params)
-    table = bd.autotune(xyz, offd, caps=synth.LIDAR_BATCH_CAPS, chunks=(8192, 16384, 32768), reps=2)
-    cap, chunk = bd.params.leaf_cap, bd.params.knn_chunk
-    log(f"[bench] autotune -> leaf_cap {cap}, knn_chunk {chunk}")
+    if cap:
+        bd = BatchDenoiser(0, **dict(params, leaf_cap=cap, knn_chunk=chunk))
+        table = {}
+        log(f"[bench] batch at leaf_cap {cap}, knn_chunk {chunk} (no autotune)")
+    else:
+        bd = BatchDenoiser(0, **params)
+        table = bd.autotune(xyz, offd, caps=synth.LIDAR_BATCH_CAPS, chunks=(8192, 16384, 32768), reps=2)
+        cap, chunk = bd.params.leaf_cap, bd.params.knn_chunk
+        log(f"[bench] autotune -> leaf_cap {cap}, knn_chunk {chunk}")
     out = bd.alloc(n, nf)
     for _ in range(3):
         bd.graph(xyz, offd, out)
@@ -139,34 +145,44 @@ def bench_batch(steps):
     bd.check_status(n)
     counts = bd.dump("COUNTS", n).cpu().numpy()
     pairs = int(counts[2])
-    # the same frames as plain single-frame calls, back to back
-    pd = Denoiser(0, **dict(params, leaf_cap=cap, knn_chunk=chunk))
-    xs = [xyz[int(off[f]):int(off[f + 1])] for f in range(nf)]
-    outs = []
-    for x in xs:
-        outs.append(pd(x))
-    torch.cuda.synchronize()
-    t0.record()
-    reps = max(1, steps // 4)
-    for _ in range(reps):
-        for x, o in zip(xs, outs):
-            pd(x, o)
-    t1.record()
-    torch.cuda.synchronize()
-    ms_plain = t0.elapsed_time(t1) / reps
+    ms_plain = None
+    if plain_loop:
+        # the same frames as plain single-frame calls, back to back
+        pd = Denoiser(0, **dict(params, leaf_cap=cap, knn_chunk=chunk))
+        xs = [xyz[int(off[f]):int(off[f + 1])] for f in range(nf)]
+        outs = []
+        for x in xs:
+            outs.append(pd(x))
+        torch.cuda.synchronize()
+        t0.record()
+        reps = max(1, steps // 4)
+        for _ in range(reps):
+            for x, o in zip(xs, outs):
+                pd(x, o)
+        t1.record()
+        torch.cuda.synchronize()
+        ms_plain = t0.elapsed_time(t1) / reps
+        pd.close()
     bd.close()
-    pd.close()
-    mp = lambda ms: round(n / (ms * 1e-3) / 1e6, 2)
+    mp = lambda ms: round(n / (ms * 1e-3) / 1e6, 2) if ms else None
     res = {"workload": "lidar_batch_64", "frames": nf, "points": n, "k": params["k"],
            "leaf_cap": cap, "knn_chunk": chunk, "steps": steps,
            "ms_per_batch_graph": round(ms_graph, 4), "ms_per_batch_eager": round(ms_eager, 4),
-           "ms_plain_loop": round(ms_plain, 4),
+           "ms_plain_loop": round(ms_plain, 4) if ms_plain else None,
            "mpoints_s_graph": mp(ms_graph), "mpoints_s_eager": mp(ms_eager), "mpoints_s_plain_loop": mp(ms_plain),
            "knn_kernel_ms": round(knn_ms, 4), "pairs": pairs,
            "knn_tflops_algorithmic": round(pairs * FLOPS_PER_PAIR / (knn_ms * 1e-3) / 1e12, 3),
            "autotune_ms": {f"{c}/{h}": round(v, 3) for (c, h), v in table.items()}}
+    achieved = pairs * FLOPS_PER_PAIR / (knn_ms * 1e-3) / 1e12
+    res["roofline"] = {"kernel": "knn_group_kernel", "bound": "alu", "achieved": round(achieved, 3),
+                       "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                       "traffic": knn_traffic("knn_lidar_batch64_traffic.json") if cap == 256 else None,
+                       "pairs_per_launch": pairs, "flops_per_pair": FLOPS_PER_PAIR, "kernel_ms": round(knn_ms, 5),
+                       "exact_fp32_ceiling": FP32_EXACT_CEILING_TOPS,
+                       "frac_of_exact_ceiling": round(achieved / FP32_EXACT_CEILING_TOPS, 4)}
     log(f"[bench] batch: graph {ms_graph:.3f} ms ({res['mpoints_s_graph']} Mpts/s), eager {ms_eager:.3f} ms, "
-        f"plain loop {ms_plain:.3f} ms ({res['mpoints_s_plain_loop']} Mpts/s), kNN {knn_ms:.3f} ms")
+        f"plain loop {ms_plain or 0:.3f} ms ({res['mpoints_s_plain_loop']} Mpts/s), kNN {knn_ms:.3f} ms")
     return res
 
 
@@ -292,6 +308,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched (64-frame) leg")
     ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--batch-cap", type=int, default=0, help="batch leaf cap (skips the autotuner)")
+    ap.add_argument("--batch-chunk", type=int, default=32768, help="batch kNN chunk with --batch-cap")
+    ap.add_argument("--no-plain-loop", action="store_true", help="skip the batch frames as plain calls")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream leg")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--no-extras", action="store_true", help="skip the ablation and fit legs")
@@ -367,8 +386,10 @@ def main():
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - s) * 1e3)
     lat = np.array(lat)
-    p50, p99 = float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
-    log(f"[bench] latency over {len(lat)} solo frames: p50 {p50:.4f} ms p99 {p99:.4f} ms max {lat.max():.4f} ms")
+    p50 = p99 = None
+    if len(lat):
+        p50, p99 = float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+        log(f"[bench] latency over {len(lat)} solo frames: p50 {p50:.4f} ms p99 {p99:.4f} ms max {lat.max():.4f} ms")
 
     flops = pairs * FLOPS_PER_PAIR
     achieved = flops / (knn_ms * 1e-3) / 1e12
@@ -379,7 +400,7 @@ def main():
         "peak": FP32_VECTOR_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-        "traffic": knn_traffic(knn_ms),
+        "traffic": knn_traffic(),
         "pairs_per_launch": pairs,
         "flops_per_pair": FLOPS_PER_PAIR,
         "kernel_ms": round(knn_ms, 5),
@@ -405,12 +426,13 @@ def main():
         "config": {"workload": args.workload, "points": n, "k": params["k"],
                    "leaf_cap": params["leaf_cap"], "frames_per_step": 1, "path": "plain single-frame",
                    "score_dtype": "f64", "leaves": n_leaves, "p1_points": n_p1, "kept": n_kept},
-        "latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4), "frames": int(len(lat)),
+        "latency_ms": {"p50": round(p50, 4) if p50 else None, "p99": round(p99, 4) if p99 else None,
+                       "frames": int(len(lat)),
                        "how": "solo frames, host clock from the call to the end of a device synchronize"},
         "roofline": roofline,
     }
     if not args.no_batch:
-        rec["batched"] = bench_batch(args.batch_steps)
+        rec["batched"] = bench_batch(args.batch_steps, args.batch_cap, args.batch_chunk, not args.no_plain_loop)
     if not args.no_serve:
         rec["served"] = bench_serve(args.serve_seconds)
     if not args.no_extras:
