@@ -3,8 +3,8 @@
 ``Server`` wraps one gdn_server; ``simulate`` streams frames from simulated
 sensors (Poisson arrivals) into it in real time, polls it, and reports
 per-frame latency (arrival to completion seen by the poll) and throughput.
-The frames must already be resident on the device; every request gets its
-own output buffers from a ring that is reused once its frame is done.
+Frames may sit on the device or arrive in pinned host memory (copied to the
+device on a copy stream first); every request gets its own output buffers.
 """
 from __future__ import annotations
 
@@ -86,11 +86,18 @@ def arrivals(n_sensors: int, rate_hz: float, duration_s: float, seed: int):
 
 def simulate(server: Server, frames, n_sensors: int = 16, rate_hz: float = 10.0, duration_s: float = 32.0,
              warmup_s: float = 2.0, seed: int = 5, log=None):
-    """Stream frames (device tensors, picked round-robin per sensor) into the
-    server at their Poisson arrival times; returns latency percentiles and
-    throughput over the arrivals after the warm-up."""
+    """Stream frames (picked round-robin per sensor) into the server at their
+    Poisson arrival times; returns latency percentiles and throughput over the
+    arrivals after the warm-up.
+
+    Frames on the device are submitted as they arrive. Frames in (pinned)
+    host memory are first copied to the device on a copy stream; each is
+    submitted once its copy has completed, so its latency includes the copy."""
     torch = server.torch
     ev = arrivals(n_sensors, rate_hz, duration_s, seed)
+    host = frames[0].device.type == "cpu"
+    copy_stream = torch.cuda.Stream(device=server.device) if host else None
+    copying = []   # (event, device tensor, arrival time) in arrival order
     torch.cuda.synchronize()  # the frames are written before the server's streams read them
     outs = {}
     pending = {}   # ticket -> (arrival wall time, n points, sensor seq)
@@ -99,17 +106,32 @@ def simulate(server: Server, frames, n_sensors: int = 16, rate_hz: float = 10.0,
     i = 0
     seq = [0] * n_sensors
     last_log = t0
-    while i < len(ev) or pending:
+
+    def submit(x, t_arr):
+        out = server.alloc(x.shape[0])
+        tk = server.submit(x, out)
+        outs[tk] = (out, x)
+        pending[tk] = (t_arr, x.shape[0])
+
+    while i < len(ev) or pending or copying:
         now = time.perf_counter() - t0
         while i < len(ev) and ev[i][0] <= now:
             t_arr, s = ev[i]
             f = frames[(s * 7 + seq[s]) % len(frames)]
             seq[s] += 1
-            out = server.alloc(f.shape[0])
-            tk = server.submit(f, out)
-            outs[tk] = out
-            pending[tk] = (t_arr, f.shape[0])
+            if host:
+                with torch.cuda.stream(copy_stream):
+                    d = torch.empty(f.shape, dtype=f.dtype, device=server.device)
+                    d.copy_(f, non_blocking=True)
+                    e = torch.cuda.Event()
+                    e.record(copy_stream)
+                copying.append((e, d, t_arr))
+            else:
+                submit(f, t_arr)
             i += 1
+        while copying and copying[0][0].query():
+            _, d, t_arr = copying.pop(0)
+            submit(d, t_arr)
         done, nw, nb = server.poll()
         now = time.perf_counter() - t0
         for tk in done:
@@ -118,7 +140,7 @@ def simulate(server: Server, frames, n_sensors: int = 16, rate_hz: float = 10.0,
             if t_arr >= warmup_s:
                 lat.append((now - t_arr) * 1e3)
                 lat_pts += n
-        if not done and (i >= len(ev) or ev[i][0] > now):
+        if not done and not copying and (i >= len(ev) or ev[i][0] > now):
             time.sleep(0.0001)
         if log and now - (last_log - t0) > 5.0:
             last_log = time.perf_counter()

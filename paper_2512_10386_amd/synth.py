@@ -255,11 +255,12 @@ CONFIGS = {
     "lidar_batch_64": dict(gen="lidar_batch", kwargs=dict(seed=4000, n_frames=64),
                            params=dict(k=32, leaf_cap=1024)),
     # frame pool of a served stream: 32 LiDAR frames of 20k-130k points that
-    # simulated sensors send round-robin
+    # simulated sensors send round-robin; leaf cap 256, the autotuner's choice
+    # for batches of this generator's frames (listed after the fit set)
     # three 200k-point score-fit frames (noise 0.5%, 1%, 2% of the diagonal)
     "fit_200k": dict(gen="fit_set", kwargs=dict(seed=30), params=dict(k=16, leaf_cap=512)),
     "lidar_stream_pool": dict(gen="lidar_batch", kwargs=dict(seed=5000, n_frames=32, lo=20_000, hi=130_000),
-                              params=dict(k=32, leaf_cap=1024)),
+                              params=dict(k=32, leaf_cap=256)),
 }
 
 LIDAR_BATCH_CAPS = (256, 512, 1024, 2048)
