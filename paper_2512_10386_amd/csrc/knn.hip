@@ -335,17 +335,26 @@ __device__ __forceinline__ unsigned long long pending_key(const float4* __restri
 
 // Merge query j's pending candidates into its list, dropping the query's own
 // key (the hot loop does not test for it); returns the new distance bound.
+// `fresh`: the list still holds only its placeholders (tau, 0xFFFFFFFF),
+// which exceed every pending key (pending keys have d2 <= tau and a real
+// index): the result is then the pending keys sorted ascending (a descending
+// sort of their complements), with empty keys after them, and the list is
+// not read.
 template <bool POS>
 __device__ __forceinline__ float flush(unsigned long long* __restrict__ lst,
                                        const typename Pending<POS>::T* __restrict__ pend, uint32_t cnt,
                                        uint32_t lane, uint32_t k, unsigned long long selfkey,
-                                       const float4* __restrict__ cand4, float4 q) {
+                                       const float4* __restrict__ cand4, float4 q, bool fresh = false) {
     wave_lds_fence();
     unsigned long long v = lane < cnt ? pending_key<POS>(cand4, pend, lane, q) : KEY_EMPTY;
     if (v == selfkey) v = KEY_EMPTY;
-    const unsigned long long L = lane < k ? lst[lane] : KEY_EMPTY;
-    v = sort64_desc(v, lane);
-    v = merge64_asc(L < v ? L : v, lane);
+    if (fresh) {
+        v = ~sort64_desc(~v, lane);
+    } else {
+        const unsigned long long L = lane < k ? lst[lane] : KEY_EMPTY;
+        v = sort64_desc(v, lane);
+        v = merge64_asc(L < v ? L : v, lane);
+    }
     if (lane < k) lst[lane] = v;
     wave_lds_fence();
     return bound_of((uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)k - 1));
@@ -362,7 +371,7 @@ __device__ __forceinline__ void flush_half(unsigned long long* __restrict__ lst0
                                            const typename Pending<POS>::T* __restrict__ pend1,
                                            uint32_t cnt1, unsigned long long self1, float4 q1, bool two,
                                            uint32_t lane, uint32_t k, const float4* __restrict__ cand4, float* b0,
-                                           float* b1) {
+                                           float* b1, bool fresh = false) {
     wave_lds_fence();
     const bool up = lane >= 32u;
     const uint32_t h = lane & 31u;
@@ -372,9 +381,13 @@ __device__ __forceinline__ void flush_half(unsigned long long* __restrict__ lst0
     const uint32_t cnt = up ? cnt1 : cnt0;
     unsigned long long v = act && h < cnt ? pending_key<POS>(cand4, pend, h, up ? q1 : q0) : KEY_EMPTY;
     if (v == (up ? self1 : self0)) v = KEY_EMPTY;
-    const unsigned long long L = act && h < k ? lst[h] : KEY_EMPTY;
-    v = sort32x2_desc(v, lane);
-    v = merge32x2_asc(L < v ? L : v, lane);
+    if (fresh) {  // both lists hold only placeholders (see flush)
+        v = ~sort32x2_desc(~v, lane);
+    } else {
+        const unsigned long long L = act && h < k ? lst[h] : KEY_EMPTY;
+        v = sort32x2_desc(v, lane);
+        v = merge32x2_asc(L < v ? L : v, lane);
+    }
     if (act && h < k) lst[h] = v;
     wave_lds_fence();
     const uint32_t hi = (uint32_t)(v >> 32);
@@ -481,6 +494,7 @@ __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __r
         wave_lds_fence();
 
         uint32_t tight = 0;  // lane j: query j's bound is already a k-th distance of real candidates
+        uint32_t merged = 0;  // lane j: query j's list has been merged into during this item
         for (uint32_t ub = 0; ub < n_units; ub += 64u) {
             // lane u: unit ub + u -> its range's part [ua, ue) and group ug
             const uint32_t u = ub + lane;
@@ -604,9 +618,11 @@ __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __r
                     const unsigned long long selfkey =
                         (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j);
                     bool tj = ((uint32_t)__builtin_amdgcn_readlane((int)tight, (int)j)) != 0u;
+                    bool mj = false;
                     if (cnt + pc > (uint32_t)PEND) {
                         wj = fminf(wj, flush<POS>(s_list + (size_t)j * k, pend, cnt, lane, k, selfkey, cand4, q));
                         tj = tj || cnt > k;
+                        mj = true;
                         cnt = 0;
                         m = __builtin_amdgcn_ballot_w64(d <= wj);
                         pc = (uint32_t)__popcll(m);
@@ -629,11 +645,13 @@ __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __r
                         wj = fminf(wj, flush<POS>(s_list + (size_t)j * k, pend, cnt, lane, k, selfkey, cand4, q));
                         cnt = 0;
                         tj = true;
+                        mj = true;
                     }
                     if (lane == j) {
                         pcnt = cnt;
                         worst = wj;
                         tight = tj ? 1u : 0u;
+                        if (mj) merged = 1u;
                     }
                 }
             }
@@ -655,13 +673,15 @@ __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __r
                 PT* const p0 = s_pend + (size_t)j * PEND;
                 const float4 q0 = query_of(qv, j);
                 const float4 q1 = two ? query_of(qv, j1) : q0;
+                const bool f0 = __builtin_amdgcn_readlane((int)merged, (int)j) == 0;
+                const bool f1 = !two || __builtin_amdgcn_readlane((int)merged, (int)j1) == 0;
                 if (c0 <= (uint32_t)PEND_HALF && c1 <= (uint32_t)PEND_HALF) {
                     float b0, b1;
                     flush_half<POS>(l0, p0, c0, sk0, q0, l0 + k, p0 + PEND, c1, sk1, q1, two, lane, k, cand4, &b0,
-                                    &b1);
+                                    &b1, f0 && f1);
                 } else {
-                    if (c0) (void)flush<POS>(l0, p0, c0, lane, k, sk0, cand4, q0);
-                    if (c1) (void)flush<POS>(l0 + k, p0 + PEND, c1, lane, k, sk1, cand4, q1);
+                    if (c0) (void)flush<POS>(l0, p0, c0, lane, k, sk0, cand4, q0, f0);
+                    if (c1) (void)flush<POS>(l0 + k, p0 + PEND, c1, lane, k, sk1, cand4, q1, f1);
                 }
             }
         } else {
@@ -671,7 +691,7 @@ __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __r
                     (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j);
                 if (cnt)
                     (void)flush<POS>(s_list + (size_t)j * k, s_pend + (size_t)j * PEND, cnt, lane, k, selfkey,
-                                     cand4, query_of(qv, j));
+                                     cand4, query_of(qv, j), __builtin_amdgcn_readlane((int)merged, (int)j) == 0);
             }
         }
 
