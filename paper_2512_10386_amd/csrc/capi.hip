@@ -86,6 +86,7 @@ gdn::Plan make_plan(uint32_t n, uint32_t nf, int k, char* base) {
     P.nf = nf;
     P.sort_passes = SORT_PASSES + (nf > 256u ? 2u : (nf > 1u ? 1u : 0u));
     P.sort_items = n > SORT_BIG_N ? 16u : 4u;
+    P.tq = n > KNN_TQ_SMALL_MAX_N ? (uint32_t)KNN_TQ : (uint32_t)KNN_TQ_SMALL;
     const size_t sort_tile = (size_t)SORT_BLOCK * P.sort_items;
     P.sort_tiles = (uint32_t)((N + sort_tile - 1) / sort_tile);
     if (P.sort_tiles == 0) P.sort_tiles = 1;

@@ -33,7 +33,9 @@ constexpr int SCAN_ITEMS = 16;
 constexpr uint32_t SCAN_SMALL_N = 1u << 20;   // scans up to this size: 4 items per thread
 constexpr int SCAN_SLOTS = 6;                 // scans per call: leaves, P1, keep, 3 kNN plan scans
 constexpr int PLAN_LEVELS = 8;                // candidate chunk lengths chunk0 << 0..7 (parallel plan)
-constexpr int KNN_TQ = 16;                    // queries per kNN work item (one wave)
+constexpr int KNN_TQ = 16;                    // queries per kNN work item (one wave), at most
+constexpr int KNN_TQ_SMALL = 8;               // ... for inputs of up to 2^20 points (shorter items, shorter tail)
+constexpr uint32_t KNN_TQ_SMALL_MAX_N = 1u << 20;
 constexpr int KNN_CC0 = 16384;                // default initial candidate chunk
 constexpr int KNN_NCH_MAX = 32;               // max candidate chunks per leaf
 constexpr int KNN_GRP = 64;                   // P1 positions per culling group of the kNN (one per lane)
@@ -151,6 +153,7 @@ struct Plan {
     uint32_t* scan_status;    // [SCAN_SLOTS][scan_tiles]
     uint32_t sort_tiles, scan_tiles;
     uint32_t sort_items;      // keys per thread of the radix passes (4 or 16)
+    uint32_t tq;              // queries per kNN work item (KNN_TQ_SMALL or KNN_TQ)
     uint8_t* deepf;           // [n] 1 at sorted positions inside deep level-10 cells; between the two
                               // deep-cell kernels, 2 marks the start of a cell to re-sort (zeroed block)
     // frames

@@ -87,18 +87,18 @@ __device__ __forceinline__ unsigned long long shfl64(unsigned long long v, int s
 
 constexpr int BOUND_MARGIN = 64;   // window reaches this far on each side of a query
 constexpr int BOUND_SPLIT = 8;     // adjacent lanes sharing one query's distances
-// Threshold ladders: tau * 2^(-m/2), m = 1..10, for single frames; tau * 2^-m,
-// m = 1..5, above 1M points (small leaves: the coarser ladder costs the bound
-// less than it costs the kNN there).
-constexpr uint32_t BOUND_COARSE_MIN_N = 1u << 20;
+// Threshold ladder tau * 2^-m, m = 1..BOUND_RUNGS, then BOUND_BISECT geometric
+// bisection steps (down to a factor 2^(1/32) between thresholds tried).
+constexpr int BOUND_RUNGS = 5;
+constexpr int BOUND_BISECT = 5;
 constexpr int BOUND_Q = 128;       // queries per block (BOUND_Q * BOUND_SPLIT threads)
 static_assert(BOUND_Q % KNN_GRP == 0, "a bound block covers whole culling groups");
 
 // tau: the largest d2 to the k points next to the query in Morton order inside
 // [qb, qe), a run of candidates holding the query; then, over the run's points
 // within BOUND_MARGIN positions, count those under each rung of the ladder
-// (LEVELS rungs, each the previous times STEP) and keep the smallest threshold
-// still holding k; finally bisect (geometrically, BISECT steps) between that
+// (BOUND_RUNGS rungs, each half the previous) and keep the smallest threshold
+// still holding k; finally bisect (geometrically, BOUND_BISECT steps) between that
 // rung and the next one down, keeping the smaller threshold whenever it still
 // holds k. Every threshold kept holds k of the query's own candidates, so it
 // is >= its k-th distance. -1 when the run has <= k points.
@@ -106,11 +106,10 @@ static_assert(BOUND_Q % KNN_GRP == 0, "a bound block covers whole culling groups
 // combine their maxima and counts (exact, so tau does not depend on the
 // split); every lane of the wave calls this, `run` false for idle ones.
 constexpr int BOUND_WPL = (2 * BOUND_MARGIN + 1 + BOUND_SPLIT - 1) / BOUND_SPLIT;  // window points per lane
-template <int LEVELS, class Pts>
+template <class Pts>
 __device__ float query_bound(Pts cand4, uint32_t qb, uint32_t qe, uint32_t qi, int k, uint32_t sub, bool live) {
-    constexpr float STEP = LEVELS == 10 ? 0.70710678f : 0.5f;
-    constexpr int BISECT = LEVELS == 10 ? 4 : 5;  // down to a factor 2^(1/32)
-    static_assert(LEVELS == 10 || LEVELS == 5, "ladder");
+    constexpr int LEVELS = BOUND_RUNGS;
+    constexpr float STEP = 0.5f;
     const bool run = live && qe - qb > (uint32_t)k;
     float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
     uint32_t s0 = 0, s1 = 0, wlo = 0, whi = 0;
@@ -167,7 +166,7 @@ __device__ float query_bound(Pts cand4, uint32_t qb, uint32_t qe, uint32_t qi, i
         if (sum8(cnt[m]) >= (uint32_t)k) best = th[m];
     float r = STEP;
 #pragma unroll
-    for (int b = 0; b < BISECT; ++b) {
+    for (int b = 0; b < BOUND_BISECT; ++b) {
         r = sqrtf(r);
         const float mid = best * r;
         if (count_le(mid) >= (uint32_t)k) best = mid;
@@ -187,7 +186,6 @@ struct StagedPts {
 // the plan gave the leaf. A block takes BOUND_Q consecutive queries; every
 // window lies within BOUND_MARGIN of its query, so the block stages those
 // points.
-template <int LEVELS>
 __global__ __launch_bounds__(BOUND_Q * BOUND_SPLIT) void knn_bound_kernel(Plan P, const float4* __restrict__ cand4,
                                                                          int k) {
     __shared__ float4 s_pts[BOUND_Q + 2 * BOUND_MARGIN + 1];
@@ -228,13 +226,13 @@ __global__ __launch_bounds__(BOUND_Q * BOUND_SPLIT) void knn_bound_kernel(Plan P
             rb = R.x;
             re = R.y;
         }
-        const float b = query_bound<LEVELS>(StagedPts{s_pts, lo}, rb, re, qi, k, sub, live);
+        const float b = query_bound(StagedPts{s_pts, lo}, rb, re, qi, k, sub, live);
         if (live && sub == 0u) {
             P.tau_c[qi] = b;
-            if ((qi - qb) % (uint32_t)KNN_TQ == 0u) {
+            if ((qi - qb) % P.tq == 0u) {
                 const uint32_t nch = P.leaf_nch[t];
-                const uint32_t grp = P.leaf_item[t] + ((qi - qb) / (uint32_t)KNN_TQ) * nch;
-                const uint32_t q1 = min(qe, qi + (uint32_t)KNN_TQ);
+                const uint32_t grp = P.leaf_item[t] + ((qi - qb) / P.tq) * nch;
+                const uint32_t q1 = min(qe, qi + P.tq);
                 for (uint32_t c = 0; c < nch; ++c) P.items[grp + c] = KnnItem{t, qi, q1, c, grp, 0u};
             }
         }
@@ -730,9 +728,9 @@ __global__ __launch_bounds__(64) void knn_merge_kernel(Plan P, int kk) {
         const KnnItem w = P.items[it];
         if (w.chunk != 0u) continue;
         // this wave's share of the tile's queries
-        const uint32_t q0 = w.q0 + part * (uint32_t)(KNN_TQ / MERGE_SPLIT);
+        const uint32_t q0 = w.q0 + part * (P.tq / (uint32_t)MERGE_SPLIT);
         if (q0 >= w.q1) continue;
-        const uint32_t q1 = min(w.q1, q0 + (uint32_t)(KNN_TQ / MERGE_SPLIT));
+        const uint32_t q1 = min(w.q1, q0 + P.tq / (uint32_t)MERGE_SPLIT);
         const uint32_t t = w.leaf;
         const uint32_t nch = P.leaf_nch[t];
         const uint32_t qb = P.p1pos[P.leaf_begin[t]];
@@ -824,13 +822,13 @@ void launch_knn_bound(const Plan& P, int k, int num_cus, hipStream_t st) {
     unsigned blocks = (P.n + BOUND_Q - 1) / BOUND_Q;
     if (blocks > 4096) blocks = 4096;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(P.n > BOUND_COARSE_MIN_N ? knn_bound_kernel<5> : knn_bound_kernel<10>, dim3(blocks),
+    hipLaunchKernelGGL(knn_bound_kernel, dim3(blocks),
                        dim3(BOUND_Q * BOUND_SPLIT), 0, st, P, (const float4*)P.cand4, k);
 }
 
-size_t knn_lds_bytes(int k, bool pos) {
-    return (size_t)QPW * ((size_t)k * sizeof(unsigned long long) +
-                          (size_t)PEND * (pos ? sizeof(uint32_t) : sizeof(unsigned long long)));
+size_t knn_lds_bytes(uint32_t q, int k, bool pos) {
+    return (size_t)q * ((size_t)k * sizeof(unsigned long long) +
+                        (size_t)PEND * (pos ? sizeof(uint32_t) : sizeof(unsigned long long)));
 }
 
 void launch_knn(const Plan& P, int k, int num_cus, hipStream_t st) {
@@ -838,12 +836,15 @@ void launch_knn(const Plan& P, int k, int num_cus, hipStream_t st) {
     // Large batches run long enough for occupancy to pay (positions); a single
     // frame's run is set by its longest items, where a gather per merge costs
     // more (keys).
+    // The plan's tile size goes with the pending-buffer kind: tiles of
+    // KNN_TQ_SMALL queries exactly for the inputs that keep keys.
+    static_assert(KNN_TQ_SMALL_MAX_N == KNN_POS_MIN_N, "tile size and buffer kind switch together");
     if (P.n > KNN_POS_MIN_N)
-        hipLaunchKernelGGL((knn_group_kernel<true, QPW>), dim3(blocks), dim3(64), knn_lds_bytes(k, true), st, P,
-                           (const float4*)P.cand4, k);
+        hipLaunchKernelGGL((knn_group_kernel<true, KNN_TQ>), dim3(blocks), dim3(64), knn_lds_bytes(KNN_TQ, k, true),
+                           st, P, (const float4*)P.cand4, k);
     else
-        hipLaunchKernelGGL((knn_group_kernel<false, QPW>), dim3(blocks), dim3(64), knn_lds_bytes(k, false), st, P,
-                           (const float4*)P.cand4, k);
+        hipLaunchKernelGGL((knn_group_kernel<false, KNN_TQ_SMALL>), dim3(blocks), dim3(64),
+                           knn_lds_bytes(KNN_TQ_SMALL, k, false), st, P, (const float4*)P.cand4, k);
 }
 
 void launch_knn_merge(const Plan& P, int k, int num_cus, hipStream_t st) {

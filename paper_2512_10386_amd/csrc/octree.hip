@@ -580,7 +580,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void knn_plan_kernel(Plan P, int chunk0
             if (nch < 1) nch = 1;
             if (nch > KNN_NCH_MAX) nch = KNN_NCH_MAX;
             if (nch > 1) lists += (unsigned long long)n1 * nch;
-            items += (unsigned long long)((n1 + KNN_TQ - 1) / KNN_TQ) * nch;
+            items += (unsigned long long)((n1 + P.tq - 1) / P.tq) * nch;
             pairs += (unsigned long long)n1 * (nc - 1);
         }
         for (int o = 32; o > 0; o >>= 1) {
@@ -611,7 +611,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void knn_plan_kernel(Plan P, int chunk0
             const uint32_t n1 = qe - qb, nc = P.leaf_ncand[t];
             uint32_t nch = (nc + cc - 1) / cc;
             if (nch > KNN_NCH_MAX) nch = KNN_NCH_MAX;
-            if (n1 > 0 && nch > 1) ic += (unsigned long long)((n1 + KNN_TQ - 1) / KNN_TQ) * nch;
+            if (n1 > 0 && nch > 1) ic += (unsigned long long)((n1 + P.tq - 1) / P.tq) * nch;
         }
         for (int o = 32; o > 0; o >>= 1) ic += __shfl_xor(ic, o, 64);
         if (lane == 0) s_red[wave][0] = ic;
@@ -638,7 +638,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void knn_plan_kernel(Plan P, int chunk0
             if (nch < 1) nch = 1;
             if (nch > KNN_NCH_MAX) nch = KNN_NCH_MAX;
             if (n1 == 0) nch = 1;
-            const uint32_t ni = n1 ? ((n1 + KNN_TQ - 1) / KNN_TQ) * nch : 0u;
+            const uint32_t ni = n1 ? ((n1 + P.tq - 1) / P.tq) * nch : 0u;
             nl1 = (nch > 1) ? n1 * nch : 0u;
             if (nch > 1) nic = ni; else niu = ni;
         }
@@ -688,7 +688,7 @@ __global__ __launch_bounds__(256) void plan_count_kernel(Plan P, uint32_t chunk0
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nl; t += gridDim.x * blockDim.x) {
         const uint32_t n1 = P.p1pos[P.leaf_begin[t + 1]] - P.p1pos[P.leaf_begin[t]], nc = P.leaf_ncand[t];
         if (n1 == 0) continue;
-        const unsigned long long tiles = (n1 + KNN_TQ - 1) / KNN_TQ;
+        const unsigned long long tiles = (n1 + P.tq - 1) / P.tq;
 #pragma unroll
         for (int l = 0; l < PLAN_LEVELS; ++l) {
             const uint32_t cc = chunk0 << l;
@@ -768,7 +768,7 @@ struct ItemsGet {
     __device__ uint32_t operator()(uint32_t t) const {
         uint32_t n1, nc, nch;
         PlanLeaf{&P}.get(t, &n1, &nc, &nch);
-        return ((nch > 1) == CHUNKED && n1) ? ((n1 + KNN_TQ - 1) / KNN_TQ) * nch : 0u;
+        return ((nch > 1) == CHUNKED && n1) ? ((n1 + P.tq - 1) / P.tq) * nch : 0u;
     }
 };
 template <bool CHUNKED>
