@@ -49,12 +49,7 @@ constexpr int QPW = KNN_TQ;  // queries per wave item
 constexpr int PEND = 64;     // pending keys per query
 constexpr int PEND_HALF = 32;  // pending keys a half-wave merge takes (k <= 32)
 constexpr uint32_t KNN_POS_MIN_N = 1u << 20;  // above: pending buffers of positions
-// Short items gain little from ordering their groups or from an early merge:
-// groups are visited nearest-first only when more than KNN_SORT_MIN_UNITS are
-// needed in a round, and a query's first k + 1 pending candidates are merged
-// early only in items of more than KNN_TIGHT_MIN_UNITS groups.
-constexpr uint32_t KNN_SORT_MIN_UNITS = 0;
-constexpr uint32_t KNN_TIGHT_MIN_UNITS = 0xFFFFFFFFu;
+constexpr int KNN_NB = 4;      // needed groups held in registers at a time
 
 __device__ __forceinline__ float dist2(const float4 q, const float4 c) {
     const float dx = c.x - q.x, dy = c.y - q.y, dz = c.z - q.z;
@@ -410,7 +405,7 @@ __device__ __forceinline__ void flush_half(unsigned long long* __restrict__ lst0
 template <bool POS, int Q>
 __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __restrict__ cand4, int kk) {
     using PT = typename Pending<POS>::T;
-    static_assert(Q <= 64, "tile shape");
+    static_assert(Q <= 32, "tile shape (a query mask per group fits 32 bits)");
     extern __shared__ unsigned long long s_dyn[];
     const uint32_t lane = threadIdx.x;
     const uint32_t k = (uint32_t)kk;
@@ -491,8 +486,7 @@ __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __r
         }
         wave_lds_fence();
 
-        uint32_t tight = 0;  // lane j: query j's bound is already a k-th distance of real candidates
-        uint32_t merged = 0;  // lane j: query j's list has been merged into during this item
+        unsigned long long merged = 0;  // bit j: query j's list has been merged into during this item
         for (uint32_t ub = 0; ub < n_units; ub += 64u) {
             // lane u: unit ub + u -> its range's part [ua, ue) and group ug
             const uint32_t u = ub + lane;
@@ -521,136 +515,152 @@ __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __r
                 ue = (uint32_t)__shfl((int)sb, (int)r, 64);
             }
             // lane u: its group's box, the smallest box distance to a query of
-            // the tile and whether any query needs the group now
-            GroupBox B{};
-            if (uok) B = P.gbox[ug];
+            // the tile and the queries that need the group (bit j: the box
+            // distance to query j does not exceed its bound)
+            uint32_t qmask = 0;
             float bmin = INFINITY;
-            bool need = false;
-            for (uint32_t j = 0; j < qn; ++j) {
-                const float4 q = query_of(qv, j);
-                const float wj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(worst), (int)j));
-                const float gx = fmaxf(fmaxf(B.lo.x - q.x, q.x - B.hi.x), 0.0f);
-                const float gy = fmaxf(fmaxf(B.lo.y - q.y, q.y - B.hi.y), 0.0f);
-                const float gz = fmaxf(fmaxf(B.lo.z - q.z, q.z - B.hi.z), 0.0f);
-                const float bd = (gx * gx + gy * gy) + gz * gz;
-                bmin = fminf(bmin, bd);
-                need = need || !(bd > wj);
+            if (uok) {
+                const GroupBox B = P.gbox[ug];
+                for (uint32_t j = 0; j < qn; ++j) {
+                    const float4 q = query_of(qv, j);
+                    const float wj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(worst), (int)j));
+                    const float gx = fmaxf(fmaxf(B.lo.x - q.x, q.x - B.hi.x), 0.0f);
+                    const float gy = fmaxf(fmaxf(B.lo.y - q.y, q.y - B.hi.y), 0.0f);
+                    const float gz = fmaxf(fmaxf(B.lo.z - q.z, q.z - B.hi.z), 0.0f);
+                    const float bd = (gx * gx + gy * gy) + gz * gz;
+                    bmin = fminf(bmin, bd);
+                    if (!(bd > wj)) qmask |= 1u << j;
+                }
             }
-            need = need && uok;
-            const uint32_t nn = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(need));
+            const uint32_t nn = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(qmask != 0u));
             if (nn == 0u) continue;
             // needed groups nearest first: sorted descending over the lanes, so
             // the i-th nearest sits in lane 63 - i
-            const unsigned long long sk0 =
-                need ? (((unsigned long long)(nn > KNN_SORT_MIN_UNITS ? __float_as_uint(bmin) : 0u) << 32) | (63u - lane))
-                     : ~0ull;
-            const unsigned long long sk = nn > KNN_SORT_MIN_UNITS ? sort64_desc(sk0, lane) : sk0;
-            // unsorted: the needed lanes' keys keep unit order (key 63 - u); the
-            // i-th needed one is found by rank
-            const unsigned long long needm = __builtin_amdgcn_ballot_w64(need);
-            auto unit_of = [&](uint32_t i) -> uint32_t {
-                if (nn > KNN_SORT_MIN_UNITS) return 63u - ((uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)sk, 63 - (int)i));
-                unsigned long long mm = needm;
-                for (uint32_t x = 0; x < i; ++x) mm &= mm - 1ull;
-                return (uint32_t)__ffsll((long long)mm) - 1u;
-            };
-            // candidates of unit uu into c (NaN outside its range part)
-            auto load_unit = [&](uint32_t uu, float4& c, uint32_t& cp) {
-                const uint32_t gg = (uint32_t)__builtin_amdgcn_readlane((int)ug, (int)uu);
-                const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)ua, (int)uu);
-                const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)ue, (int)uu);
-                const uint32_t p = gg * (uint32_t)KNN_GRP + lane;
-                if (p >= a && p < e) {
-                    c = cand4[p];
-                    cp = p;
-                } else {
+            const unsigned long long sk = sort64_desc(
+                qmask ? (((unsigned long long)__float_as_uint(bmin) << 32) | (63u - lane)) : ~0ull, lane);
+            for (uint32_t i0 = 0; i0 < nn; i0 += (uint32_t)KNN_NB) {
+                // the next KNN_NB needed groups: candidates in registers (NaN
+                // outside the range part), group base and query mask uniform
+                float4 c[KNN_NB];
+                uint32_t gb[KNN_NB], mk[KNN_NB];
+                uint32_t qany = 0;
+#pragma unroll
+                for (int b = 0; b < KNN_NB; ++b) {
                     const float nan = __uint_as_float(0x7FC00000u);
-                    c = make_float4(nan, nan, nan, __uint_as_float(NONE32));
-                    cp = NONE32;
+                    c[b] = make_float4(nan, nan, nan, __uint_as_float(NONE32));
+                    gb[b] = 0u;
+                    mk[b] = 0u;
+                    if (i0 + (uint32_t)b < nn) {
+                        const uint32_t uu =
+                            63u - (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)sk, 63 - (int)(i0 + (uint32_t)b));
+                        const uint32_t gg = (uint32_t)__builtin_amdgcn_readlane((int)ug, (int)uu);
+                        const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)ua, (int)uu);
+                        const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)ue, (int)uu);
+                        mk[b] = (uint32_t)__builtin_amdgcn_readlane((int)qmask, (int)uu);
+                        gb[b] = gg * (uint32_t)KNN_GRP;
+                        const uint32_t p = gb[b] + lane;
+                        if (p >= a && p < e) c[b] = cand4[p];
+                    }
+                    qany |= mk[b];
                 }
-            };
-            float4 cn = make_float4(0.f, 0.f, 0.f, 0.f);
-            uint32_t cpn = NONE32;
-            load_unit(unit_of(0), cn, cpn);
-            for (uint32_t i = 0; i < nn; ++i) {
-                const uint32_t uu = unit_of(i);
-                const float4 c = cn;
-                const uint32_t cp = cpn;
-                if (i + 1u < nn) load_unit(unit_of(i + 1u), cn, cpn);
-                // the queries that need this group with their current bounds
-                // (lane j: query j)
-                const float lx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(B.lo.x), (int)uu));
-                const float ly = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(B.lo.y), (int)uu));
-                const float lz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(B.lo.z), (int)uu));
-                const float hx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(B.hi.x), (int)uu));
-                const float hy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(B.hi.y), (int)uu));
-                const float hz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(B.hi.z), (int)uu));
-                const float gx = fmaxf(fmaxf(lx - qv.x, qv.x - hx), 0.0f);
-                const float gy = fmaxf(fmaxf(ly - qv.y, qv.y - hy), 0.0f);
-                const float gz = fmaxf(fmaxf(lz - qv.z, qv.z - hz), 0.0f);
-                unsigned long long qm =
-                    __builtin_amdgcn_ballot_w64(lane < qn && !((gx * gx + gy * gy) + gz * gz > worst));
-                while (qm != 0ull) {
-                    const uint32_t j = (uint32_t)__ffsll((long long)qm) - 1u;
-                    qm &= qm - 1ull;
+                // each query that needs any of them, against those it needs:
+                // the passing candidates of all of them at the query's bound;
+                // appended at once unless the buffer would overflow or a group
+                // holds more than k + 1 passing candidates
+                while (qany != 0u) {
+                    const uint32_t j = (uint32_t)__ffs(qany) - 1u;
+                    qany &= qany - 1u;
                     const float4 q = query_of(qv, j);
                     float wj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(worst), (int)j));
-                    const float d = dist2(q, c);
-                    unsigned long long m = __builtin_amdgcn_ballot_w64(d <= wj);
-                    if (m == 0ull) continue;
-                    uint32_t pc = (uint32_t)__popcll(m);
-                    // a group holding more than k + 1 passing candidates (one may
-                    // be the query) first lowers the bound: if k + 1 of them lie
-                    // within wj * 2^(-1/4), the k-th distance cannot exceed it
-                    if (pc > k + 1u && wj < INFINITY) {
-                        for (int r = 0; r < 12; ++r) {
-                            const float t2 = wj * 0.84089642f;
-                            if ((uint32_t)__popcll(__builtin_amdgcn_ballot_w64(d <= t2)) < k + 1u) break;
-                            wj = t2;
+                    float d[KNN_NB];
+                    unsigned long long m[KNN_NB];
+                    uint32_t tot = 0;
+                    bool slow = false;
+#pragma unroll
+                    for (int b = 0; b < KNN_NB; ++b) {
+                        d[b] = INFINITY;
+                        m[b] = 0ull;
+                        if ((mk[b] >> j) & 1u) {
+                            d[b] = dist2(q, c[b]);
+                            m[b] = __builtin_amdgcn_ballot_w64(d[b] <= wj);
+                            const uint32_t pc = (uint32_t)__popcll(m[b]);
+                            tot += pc;
+                            slow = slow || (pc > k + 1u && wj < INFINITY);
                         }
-                        m = __builtin_amdgcn_ballot_w64(d <= wj);
-                        pc = (uint32_t)__popcll(m);
                     }
+                    if (tot == 0u) continue;
                     uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)pcnt, (int)j);
                     PT* const pend = s_pend + (size_t)j * PEND;
-                    const unsigned long long selfkey =
-                        (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j);
-                    bool tj = ((uint32_t)__builtin_amdgcn_readlane((int)tight, (int)j)) != 0u;
-                    bool mj = false;
-                    if (cnt + pc > (uint32_t)PEND) {
-                        wj = fminf(wj, flush<POS>(s_list + (size_t)j * k, pend, cnt, lane, k, selfkey, cand4, q));
-                        tj = tj || cnt > k;
-                        mj = true;
-                        cnt = 0;
-                        m = __builtin_amdgcn_ballot_w64(d <= wj);
-                        pc = (uint32_t)__popcll(m);
-                    }
-                    if (pc) {
-                        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                        if ((m >> lane) & 1ull) {
-                            if constexpr (POS)
-                                pend[cnt + rank] = cp;
-                            else
-                                pend[cnt + rank] = make_key(d, __float_as_uint(c.w));
+                    if (!slow && cnt + tot <= (uint32_t)PEND) {
+#pragma unroll
+                        for (int b = 0; b < KNN_NB; ++b) {
+                            if (m[b] == 0ull) continue;
+                            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(m[b] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[b], 0u));
+                            if (d[b] <= wj) {  // this lane's bit of m[b]
+                                if constexpr (POS)
+                                    pend[cnt + rank] = gb[b] + lane;
+                                else
+                                    pend[cnt + rank] = make_key(d[b], __float_as_uint(c[b].w));
+                            }
+                            cnt += (uint32_t)__popcll(m[b]);
                         }
-                        cnt += pc;
+                    } else {
+                        // one group at a time: a group holding more than k + 1
+                        // passing candidates (one may be the query) first lowers
+                        // the bound (if k + 1 of them lie within wj * 2^(-1/4),
+                        // the k-th distance cannot exceed it); a full buffer is
+                        // merged into the list, which lowers the bound too
+                        const unsigned long long selfkey =
+                            (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j);
+                        bool mj = false;
+#pragma nounroll
+                        for (int b = 0; b < KNN_NB; ++b) {
+                            float db = d[0];
+                            uint32_t gbb = gb[0];
+                            float cw = c[0].w;
+#pragma unroll
+                            for (int x = 1; x < KNN_NB; ++x)
+                                if (b == x) {
+                                    db = d[x];
+                                    gbb = gb[x];
+                                    cw = c[x].w;
+                                }
+                            unsigned long long mm = __builtin_amdgcn_ballot_w64(db <= wj);
+                            if (mm == 0ull) continue;
+                            uint32_t pc = (uint32_t)__popcll(mm);
+                            if (pc > k + 1u && wj < INFINITY) {
+                                for (int r = 0; r < 12; ++r) {
+                                    const float t2 = wj * 0.84089642f;
+                                    if ((uint32_t)__popcll(__builtin_amdgcn_ballot_w64(db <= t2)) < k + 1u) break;
+                                    wj = t2;
+                                }
+                                mm = __builtin_amdgcn_ballot_w64(db <= wj);
+                                pc = (uint32_t)__popcll(mm);
+                            }
+                            if (cnt + pc > (uint32_t)PEND) {
+                                wj = fminf(wj, flush<POS>(s_list + (size_t)j * k, pend, cnt, lane, k, selfkey, cand4, q));
+                                mj = true;
+                                cnt = 0;
+                                mm = __builtin_amdgcn_ballot_w64(db <= wj);
+                                pc = (uint32_t)__popcll(mm);
+                            }
+                            if (pc) {
+                                const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                                    (uint32_t)(mm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0u));
+                                if (db <= wj) {  // this lane's bit of mm
+                                    if constexpr (POS)
+                                        pend[cnt + rank] = gbb + lane;
+                                    else
+                                        pend[cnt + rank] = make_key(db, __float_as_uint(cw));
+                                }
+                                cnt += pc;
+                            }
+                        }
+                        if (lane == j) worst = wj;
+                        if (mj) merged |= 1ull << j;
                     }
-                    // the first time k + 1 candidates are pending (one may be
-                    // the query), merge them: the bound becomes a true k-th
-                    // distance for the groups still to come
-                    if (!tj && cnt > k && n_units > KNN_TIGHT_MIN_UNITS) {
-                        wj = fminf(wj, flush<POS>(s_list + (size_t)j * k, pend, cnt, lane, k, selfkey, cand4, q));
-                        cnt = 0;
-                        tj = true;
-                        mj = true;
-                    }
-                    if (lane == j) {
-                        pcnt = cnt;
-                        worst = wj;
-                        tight = tj ? 1u : 0u;
-                        if (mj) merged = 1u;
-                    }
+                    if (lane == j) pcnt = cnt;
                 }
             }
         }
@@ -671,8 +681,8 @@ __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __r
                 PT* const p0 = s_pend + (size_t)j * PEND;
                 const float4 q0 = query_of(qv, j);
                 const float4 q1 = two ? query_of(qv, j1) : q0;
-                const bool f0 = __builtin_amdgcn_readlane((int)merged, (int)j) == 0;
-                const bool f1 = !two || __builtin_amdgcn_readlane((int)merged, (int)j1) == 0;
+                const bool f0 = ((merged >> j) & 1ull) == 0ull;
+                const bool f1 = !two || ((merged >> j1) & 1ull) == 0ull;
                 if (c0 <= (uint32_t)PEND_HALF && c1 <= (uint32_t)PEND_HALF) {
                     float b0, b1;
                     flush_half<POS>(l0, p0, c0, sk0, q0, l0 + k, p0 + PEND, c1, sk1, q1, two, lane, k, cand4, &b0,
@@ -689,7 +699,7 @@ __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __r
                     (unsigned long long)(uint32_t)__builtin_amdgcn_readlane(__float_as_int(qv.w), (int)j);
                 if (cnt)
                     (void)flush<POS>(s_list + (size_t)j * k, s_pend + (size_t)j * PEND, cnt, lane, k, selfkey,
-                                     cand4, query_of(qv, j), __builtin_amdgcn_readlane((int)merged, (int)j) == 0);
+                                     cand4, query_of(qv, j), ((merged >> j) & 1ull) == 0ull);
             }
         }
 
