@@ -158,7 +158,7 @@ gdn::Plan make_plan(uint32_t n, uint32_t nf, int k, char* base) {
     P.p2 = (uint8_t*)take(N);
     P.stage_c = (uint8_t*)take(N);
     P.score_c = (double*)take(8 * N);
-    P.rec_p = (NbrRec*)take(sizeof(NbrRec) * N);
+    P.gpow_p = (double*)take(sizeof(double) * N);
     P.items = (KnnItem*)take(sizeof(KnnItem) * (size_t)P.items_max);
     P.plist = (uint64_t*)take(8 * (size_t)P.plist_max * k);
     P.bytes = off;

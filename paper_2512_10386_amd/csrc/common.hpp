@@ -83,14 +83,6 @@ struct Counters {
     uint32_t knn_q[KNN_STREAMS][32];
 };
 
-// What the score reads of a neighbour, in one 32-byte record at the
-// neighbour's P1 position (one gather instead of two).
-struct __align__(32) NbrRec {
-    float4 p;      // x, y, z (bit copies of the input), original index bits
-    double gpow;   // rho^(alpha/2)
-    double pad;
-};
-
 // Frame constants derived on the device from the bounding box.
 struct FrameConst {
     float lo[3];
@@ -210,7 +202,7 @@ struct Plan {
     uint8_t* p2;              // [n]
     uint8_t* stage_c;         // [n] 1 density-removed, 2 score-removed, 3 kept
     double* score_c;          // [n]
-    NbrRec* rec_p;            // [n] P1 order: coordinates, rho^(alpha/2)
+    double* gpow_p;           // [n] P1 order: rho^(alpha/2)
     // kNN work
     KnnItem* items;           // [items_max]
     uint32_t items_max;

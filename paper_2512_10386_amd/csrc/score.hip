@@ -323,7 +323,7 @@ __global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params p
             const double sr = prm.sigma * P.r64_c[qi];
             P.afac_c[qi] = make_double2(pow_ha<SQRT>(P.rho_c[qi] / den, ha), 1.0 / (2.0 * sr * sr));
             // rho_j^(alpha/2) of Eq. 17's factored density weight, by original index
-            P.rec_p[qi] = NbrRec{P.cand4[qi], pow_ha<SQRT>(P.rho_c[qi], ha), 0.0};
+            P.gpow_p[qi] = pow_ha<SQRT>(P.rho_c[qi], ha);
         }
         if (threadIdx.x == 0) { P.leaf_rho_med[t] = med; P.leaf_r2cut[t] = cut; }
         __syncthreads();
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(256) void leaf_select_small_kernel(Plan P, Params p
             P.p2[qi] = (!shortv[j] && __uint_as_float((uint32_t)r2v.v[j]) <= cut) ? 1 : 0;
             const double sr = prm.sigma * r64v[j];
             P.afac_c[qi] = make_double2(pow_ha<SQRT>(rho / den, ha), 1.0 / (2.0 * sr * sr));
-            P.rec_p[qi] = NbrRec{P.cand4[qi], pow_ha<SQRT>(rho, ha), 0.0};
+            P.gpow_p[qi] = pow_ha<SQRT>(rho, ha);
         }
         if (lane == 0) { P.leaf_rho_med[t] = med; P.leaf_r2cut[t] = cut; }
     }
@@ -466,46 +466,73 @@ void launch_leaf_select(const Plan& P, const Params& prm, const float* xyz, hipS
 
 // Instantiated for the plain kernel exponent gamma = 2 (Eq. 20, one
 // division) and the general power: a kernel holding both paths needs more
-// registers and runs slower even when the power is never taken.
-template <bool G2>
+// registers and runs slower even when the power is never taken. PAIR: each
+// wave takes two tiles of queries per step, so the loads of both (the
+// neighbour lists, then the neighbours' coordinates and density powers) are
+// in flight together; it pays on large inputs, where the step count per wave
+// is high, and costs a little on a single frame.
+constexpr uint32_t SCORE_PAIR_MIN_N = 1u << 20;
+
+template <bool G2, bool PAIR>
 __global__ __launch_bounds__(256) void score_kernel(Plan P, int kk, double eps, double gamma) {
     const uint32_t np1 = P.ctr->n_p1;
     const uint32_t k = (uint32_t)kk, kp = pow2_at_least(k), qpw = 64u / kp;
     const uint32_t lane = threadIdx.x & 63u, seg = lane / kp, r = lane % kp;
     const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
-    for (uint32_t q0 = wid * qpw; q0 < np1; q0 += nw * qpw) {
-        const uint32_t qi = q0 + seg;
-        uint32_t j = 0xFFFFFFFFu;
-        bool live = false;
-        float4 a;
-        double2 af;
+    // the query's flag, neighbour index, coordinates and factors, issued
+    // together; j = none for idle lanes and queries outside P2
+    auto fetch = [&](uint32_t q0, uint32_t& qi, uint32_t& j, bool& live, float4& a, double2& af) {
+        qi = q0 + seg;
+        j = 0xFFFFFFFFu;
+        live = false;
         if (qi < np1) {
-            // every load but the neighbour's record is issued up front, so the
-            // flag, the neighbour index and the query's values do not wait on
-            // each other; the query comes from its sorted copy and the
-            // neighbour from its record (both bit copies of the input)
             live = P.p2[qi] != 0;
             if (r < k) j = P.nbr[(size_t)qi * k + r];
             a = P.cand4[qi];
             af = P.afac_c[qi];
         }
         if (!live) j = 0xFFFFFFFFu;
-        double term = 0.0;
-        if (j < P.n) {
-            const NbrRec R = P.rec_p[j];
-            const double dx = (double)R.p.x - (double)a.x;
-            const double dy = (double)R.p.y - (double)a.y;
-            const double dz = (double)R.p.z - (double)a.z;
-            const double d2 = dx * dx + dy * dy + dz * dz;
-            const double w_den = af.x * R.gpow;
-            const double w_dis = (d2 == 0.0) ? 1.0 : exp(-(d2 * af.y));
-            double kern;
-            if constexpr (G2) kern = 1.0 / (d2 + eps);
-            else kern = pow(d2 + eps, -gamma / 2.0);
-            term = w_den * w_dis * kern;
+    };
+    // term r of the query's sum: the neighbour's coordinates (bit copies of
+    // the input, in P1 order) and density power
+    auto term_of = [&](const float4& c, double gp, const float4& a, const double2& af) -> double {
+        const double dx = (double)c.x - (double)a.x;
+        const double dy = (double)c.y - (double)a.y;
+        const double dz = (double)c.z - (double)a.z;
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        const double w_den = af.x * gp;
+        const double w_dis = (d2 == 0.0) ? 1.0 : exp(-(d2 * af.y));
+        double kern;
+        if constexpr (G2) kern = 1.0 / (d2 + eps);
+        else kern = pow(d2 + eps, -gamma / 2.0);
+        return w_den * w_dis * kern;
+    };
+    if constexpr (PAIR) {
+        for (uint32_t q0 = wid * qpw; q0 < np1; q0 += 2u * nw * qpw) {
+            uint32_t qi0, j0, qi1, j1;
+            bool l0, l1;
+            float4 a0, a1, c0{}, c1{};
+            double2 f0, f1;
+            double g0 = 0.0, g1 = 0.0;
+            fetch(q0, qi0, j0, l0, a0, f0);
+            fetch(q0 + nw * qpw, qi1, j1, l1, a1, f1);
+            if (j0 < P.n) { c0 = P.cand4[j0]; g0 = P.gpow_p[j0]; }
+            if (j1 < P.n) { c1 = P.cand4[j1]; g1 = P.gpow_p[j1]; }
+            const double F0 = seg_sum(j0 < P.n ? term_of(c0, g0, a0, f0) : 0.0, kp);
+            const double F1 = seg_sum(j1 < P.n ? term_of(c1, g1, a1, f1) : 0.0, kp);
+            if (l0 && r == 0) P.score_c[qi0] = F0;
+            if (l1 && r == 0) P.score_c[qi1] = F1;
         }
-        const double F = seg_sum(term, kp);
-        if (live && r == 0) P.score_c[qi] = F;
+    } else {
+        for (uint32_t q0 = wid * qpw; q0 < np1; q0 += nw * qpw) {
+            uint32_t qi, j;
+            bool live;
+            float4 a;
+            double2 af;
+            fetch(q0, qi, j, live, a, af);
+            const double F = seg_sum(j < P.n ? term_of(P.cand4[j], P.gpow_p[j], a, af) : 0.0, kp);
+            if (live && r == 0) P.score_c[qi] = F;
+        }
     }
 }
 
@@ -516,7 +543,11 @@ void launch_score(const Plan& P, const Params& prm, hipStream_t st) {
     unsigned blocks = (unsigned)((waves + 3) / 4);
     if (blocks > 8192) blocks = 8192;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(prm.gamma == 2.0 ? score_kernel<true> : score_kernel<false>, dim3(blocks), dim3(256), 0, st, P, prm.k, prm.eps, prm.gamma);
+    const bool pair = P.n > SCORE_PAIR_MIN_N;
+    const bool g2 = prm.gamma == 2.0;
+    auto kern = g2 ? (pair ? score_kernel<true, true> : score_kernel<true, false>)
+                   : (pair ? score_kernel<false, true> : score_kernel<false, false>);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, st, P, prm.k, prm.eps, prm.gamma);
 }
 
 // ---------------------------------------------------------------- top-lambda

@@ -7,10 +7,14 @@
 
 namespace gdn {
 
-// Value of lane ^ M, without LDS: DPP quad permutes (1, 2), row rotations
-// (4, 8) and the gfx950 permlane swaps (16, 32).
+// Value of lane ^ M without an LDS access: DPP quad permutes (1, 2) and row
+// rotation (8), ds_swizzle in bitmask mode (4, 16: the exchange runs in the
+// LDS unit's crossbar, which takes it off the VALU; with DPP, xor 4 needs two
+// row rotations and a select), and the gfx950 permlane swap (32).
 // Quad permutes and row rotations read a valid lane for every lane, so the
 // DPP move needs no old value (one instruction, no zero to materialise).
+// Every lane of the wave must be active (the sorts and reductions below are
+// called by whole waves).
 template <int M>
 __device__ __forceinline__ uint32_t xor_lane(uint32_t x, uint32_t lane) {
     if constexpr (M == 1) {
@@ -18,14 +22,11 @@ __device__ __forceinline__ uint32_t xor_lane(uint32_t x, uint32_t lane) {
     } else if constexpr (M == 2) {
         return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
     } else if constexpr (M == 4) {
-        const uint32_t a = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x124, 0xF, 0xF, true);  // row_ror:4
-        const uint32_t b = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x12C, 0xF, 0xF, true);  // row_ror:12
-        return (lane & 4u) ? a : b;
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x101F);  // bitmask mode: xor 4
     } else if constexpr (M == 8) {
         return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, true);  // row_ror:8
     } else if constexpr (M == 16) {
-        const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
-        return (lane & 16u) ? (uint32_t)r[0] : (uint32_t)r[1];
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401F);  // bitmask mode: xor 16
     } else {
         static_assert(M == 32, "xor distance");
         const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
