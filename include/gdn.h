@@ -60,7 +60,7 @@ typedef struct {
     double  eps;            /* epsilon of Eq. 17 and Eq. 20, >= 0 */
     double  keep_ratio;     /* lambda: top fraction of P2 kept per leaf, (0, 1] */
     int32_t knn_chunk;      /* initial candidate chunk length of the kNN work split;
-                               changes speed only, never results; 0 = default (16384) */
+                               changes speed only, never results; 0 = default (32768) */
     double  gamma;          /* exponent of the gravitational kernel, (d^2 + eps)^(-gamma/2):
                                2 is Eq. 20 (computed as 1/(d^2+eps)); finite, >= 0 */
     double  log_threshold;  /* NaN: the per-leaf top-lambda rule (Sec. 3); a finite value

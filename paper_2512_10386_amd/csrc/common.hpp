@@ -36,7 +36,7 @@ constexpr int PLAN_LEVELS = 8;                // candidate chunk lengths chunk0 
 constexpr int KNN_TQ = 16;                    // queries per kNN work item (one wave), at most
 constexpr int KNN_TQ_SMALL = 8;               // ... for inputs of up to 2^20 points (shorter items, shorter tail)
 constexpr uint32_t KNN_TQ_SMALL_MAX_N = 1u << 20;
-constexpr int KNN_CC0 = 16384;                // default initial candidate chunk
+constexpr int KNN_CC0 = 32768;                // default initial candidate chunk
 constexpr int KNN_NCH_MAX = 32;               // max candidate chunks per leaf
 constexpr int KNN_GRP = 64;                   // P1 positions per culling group of the kNN (one per lane)
 constexpr uint32_t KNN_STREAMS = 8;           // kNN work-queue streams (cursors)

@@ -254,6 +254,10 @@ __device__ __forceinline__ void write_final(const Plan& P, uint32_t qi, uint32_t
     }
 }
 
+// s_waitcnt operand: vector-memory count 0, export and LDS counts left at
+// their maxima (gfx9 field layout).
+constexpr int VMCNT0 = (7 << 4) | (15 << 8);
+
 // The final lists of a tile's qn queries (in LDS, k keys each), eight
 // queries at a time: their position lookups are issued before any store, so
 // the tile waits for a round trip per eight queries instead of per query.
@@ -271,6 +275,11 @@ __device__ __forceinline__ void write_tile(const Plan& P, const unsigned long lo
 #pragma unroll
         for (int j = 0; j < B; ++j)
             if (lane < k && real_entry(v[j])) pj[j] = P.inv_p1[(uint32_t)v[j]];
+        // one wait for all lookups: left to itself the compiler waits for the
+        // whole vector-memory counter before each query's stores (the lookups
+        // sit in branches), which on this chip also waits for the previous
+        // query's stores to be written
+        __builtin_amdgcn_s_waitcnt(VMCNT0);
 #pragma unroll
         for (int j = 0; j < B; ++j) {
             if (j0 + (uint32_t)j >= qn) break;
@@ -326,6 +335,22 @@ __device__ __forceinline__ unsigned long long pending_key(const float4* __restri
     }
 }
 
+// The 64 keys of the wave (one per lane, empty = KEY_EMPTY) in ascending
+// order, as the 64-bit (d2, index) keys order them, lanes 0..k-1 exact. They
+// are first sorted on 32 bits: the top 26 bits of the d2 field (a relative
+// step of 2^-17) and the source lane, and each lane then fetches its key from
+// that lane. That order is the exact one for the first k positions unless two
+// real keys among the first k + 1 agree on those 26 bits; then the 64-bit
+// network runs instead.
+__device__ __forceinline__ unsigned long long sort_keys_asc(unsigned long long v, uint32_t lane, uint32_t k) {
+    constexpr uint32_t EMPTY_TOP = (uint32_t)(KEY_EMPTY >> 32) >> 6;
+    const uint32_t s = sort64_u32<true>(((uint32_t)(v >> 32) & ~63u) | lane, lane);
+    const uint32_t p = (uint32_t)__shfl_up((int)s, 1u, 64);
+    const bool near = lane >= 1u && lane <= k && (s >> 6) == (p >> 6) && (s >> 6) != EMPTY_TOP;
+    if (__builtin_amdgcn_ballot_w64(near) == 0ull) return shfl64(v, (int)(s & 63u));
+    return ~sort64_desc(~v, lane);
+}
+
 // Merge query j's pending candidates into its list, dropping the query's own
 // key (the hot loop does not test for it); returns the new distance bound.
 // `fresh`: the list still holds only its placeholders (tau, 0xFFFFFFFF),
@@ -342,7 +367,7 @@ __device__ __forceinline__ float flush(unsigned long long* __restrict__ lst,
     unsigned long long v = lane < cnt ? pending_key<POS>(cand4, pend, lane, q) : KEY_EMPTY;
     if (v == selfkey) v = KEY_EMPTY;
     if (fresh) {
-        v = ~sort64_desc(~v, lane);
+        v = sort_keys_asc(v, lane, k);
     } else {
         const unsigned long long L = lane < k ? lst[lane] : KEY_EMPTY;
         v = sort64_desc(v, lane);
@@ -534,10 +559,11 @@ __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __r
             }
             const uint32_t nn = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(qmask != 0u));
             if (nn == 0u) continue;
-            // needed groups nearest first: sorted descending over the lanes, so
-            // the i-th nearest sits in lane 63 - i
-            const unsigned long long sk = sort64_desc(
-                qmask ? (((unsigned long long)__float_as_uint(bmin) << 32) | (63u - lane)) : ~0ull, lane);
+            // needed groups nearest first (by the top 26 bits of the box
+            // distance, a visiting order only): sorted descending over the
+            // lanes, so the i-th nearest sits in lane 63 - i
+            const uint32_t sk =
+                sort64_u32<false>(qmask ? ((__float_as_uint(bmin) & ~63u) | (63u - lane)) : 0xFFFFFFFFu, lane);
             for (uint32_t i0 = 0; i0 < nn; i0 += (uint32_t)KNN_NB) {
                 // the next KNN_NB needed groups: candidates in registers (NaN
                 // outside the range part), group base and query mask uniform
@@ -552,7 +578,7 @@ __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __r
                     mk[b] = 0u;
                     if (i0 + (uint32_t)b < nn) {
                         const uint32_t uu =
-                            63u - (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)sk, 63 - (int)(i0 + (uint32_t)b));
+                            63u - ((uint32_t)__builtin_amdgcn_readlane((int)sk, 63 - (int)(i0 + (uint32_t)b)) & 63u);
                         const uint32_t gg = (uint32_t)__builtin_amdgcn_readlane((int)ug, (int)uu);
                         const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)ua, (int)uu);
                         const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)ue, (int)uu);

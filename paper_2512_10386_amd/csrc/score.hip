@@ -346,7 +346,7 @@ __device__ __forceinline__ unsigned long long wave_rank_value(WaveVals w, uint32
                                                               uint32_t* hist) {
     // ascending rank r (0-based, r < n1) of the n1 values; the padding sorts first
     if (n1 <= 64u) {
-        const unsigned long long s = sort64_desc(w.v[0], lane);
+        const unsigned long long s = sort64_desc_dir(w.v[0], lane);
         const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)s, 63 - (int)r);
         const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(s >> 32), 63 - (int)r);
         return ((unsigned long long)hi << 32) | lo;

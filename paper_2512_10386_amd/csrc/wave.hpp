@@ -34,71 +34,6 @@ __device__ __forceinline__ uint32_t xor_lane(uint32_t x, uint32_t lane) {
     }
 }
 
-// Compare-exchange with lane ^ M: this lane keeps the smaller key iff
-// keep_min.
-template <int M>
-__device__ __forceinline__ unsigned long long cx(unsigned long long v, uint32_t lane, bool keep_min) {
-    const uint32_t lo = xor_lane<M>((uint32_t)v, lane);
-    const uint32_t hi = xor_lane<M>((uint32_t)(v >> 32), lane);
-    const unsigned long long o = ((unsigned long long)hi << 32) | lo;
-    return ((o < v) == keep_min) ? o : v;
-}
-
-// One exchange step of the descending sort: blocks of SIZE lanes alternate
-// direction so that each stage leaves bitonic blocks of twice the size.
-template <int SIZE, int M>
-__device__ __forceinline__ unsigned long long sort_step(unsigned long long v, uint32_t lane) {
-    return cx<M>(v, lane, ((lane & (uint32_t)M) == 0u) == ((lane & (uint32_t)SIZE) != 0u));
-}
-
-// Bitonic sort of one key per lane, descending over lanes 0..63.
-__device__ __forceinline__ unsigned long long sort64_desc(unsigned long long v, uint32_t lane) {
-    v = sort_step<2, 1>(v, lane);
-    v = sort_step<4, 2>(v, lane);
-    v = sort_step<4, 1>(v, lane);
-    v = sort_step<8, 4>(v, lane);
-    v = sort_step<8, 2>(v, lane);
-    v = sort_step<8, 1>(v, lane);
-    v = sort_step<16, 8>(v, lane);
-    v = sort_step<16, 4>(v, lane);
-    v = sort_step<16, 2>(v, lane);
-    v = sort_step<16, 1>(v, lane);
-    v = sort_step<32, 16>(v, lane);
-    v = sort_step<32, 8>(v, lane);
-    v = sort_step<32, 4>(v, lane);
-    v = sort_step<32, 2>(v, lane);
-    v = sort_step<32, 1>(v, lane);
-    v = sort_step<64, 32>(v, lane);
-    v = sort_step<64, 16>(v, lane);
-    v = sort_step<64, 8>(v, lane);
-    v = sort_step<64, 4>(v, lane);
-    v = sort_step<64, 2>(v, lane);
-    v = sort_step<64, 1>(v, lane);
-    return v;
-}
-
-// Bitonic sort of each 32-lane half (one key per lane), both halves
-// descending: the stages of sort64_desc up to blocks of 16, then a final
-// merge whose direction depends only on the exchange bit.
-__device__ __forceinline__ unsigned long long sort32x2_desc(unsigned long long v, uint32_t lane) {
-    v = sort_step<2, 1>(v, lane);
-    v = sort_step<4, 2>(v, lane);
-    v = sort_step<4, 1>(v, lane);
-    v = sort_step<8, 4>(v, lane);
-    v = sort_step<8, 2>(v, lane);
-    v = sort_step<8, 1>(v, lane);
-    v = sort_step<16, 8>(v, lane);
-    v = sort_step<16, 4>(v, lane);
-    v = sort_step<16, 2>(v, lane);
-    v = sort_step<16, 1>(v, lane);
-    v = sort_step<64, 16>(v, lane);
-    v = sort_step<64, 8>(v, lane);
-    v = sort_step<64, 4>(v, lane);
-    v = sort_step<64, 2>(v, lane);
-    v = sort_step<64, 1>(v, lane);
-    return v;
-}
-
 template <int M>
 __device__ __forceinline__ float xor_f32(float x, uint32_t lane) {
     return __uint_as_float(xor_lane<M>(__float_as_uint(x), lane));
@@ -123,25 +58,132 @@ __device__ __forceinline__ float wave_max(float v, uint32_t lane) {
     return fmaxf(v, xor_f32<32>(v, lane));
 }
 
+// Bitonic networks over the 64 lanes, one key per lane (32- or 64-bit).
+//
+// Every exchange keeps the smaller key in the lane whose M bit is clear, so
+// the lane pattern it needs depends on M alone: six masks for all networks
+// (left to the compiler, a pattern per (block size, M) pair fills the scalar
+// registers and spills them). The direction of a block of the sort phase
+// that merges blocks of 2^p lanes is folded into the keys instead: during
+// that phase the lanes whose bit p is set, which sort descending, hold the
+// complements of their keys (one XOR per phase).
+template <int M>
+__device__ __forceinline__ uint32_t xor_lane_key(uint32_t v, uint32_t lane) {
+    return xor_lane<M>(v, lane);
+}
+template <int M>
+__device__ __forceinline__ unsigned long long xor_lane_key(unsigned long long v, uint32_t lane) {
+    const uint32_t lo = xor_lane<M>((uint32_t)v, lane);
+    const uint32_t hi = xor_lane<M>((uint32_t)(v >> 32), lane);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Compare-exchange with lane ^ M: the lane with the M bit clear keeps the
+// smaller key.
+template <int M, class K>
+__device__ __forceinline__ K cx(K v, uint32_t lane) {
+    const K o = xor_lane_key<M>(v, lane);
+    return ((o < v) == ((lane & (uint32_t)M) == 0u)) ? o : v;
+}
+
+// All-ones where bit b of x is set.
+template <class K>
+__device__ __forceinline__ K bit_mask(uint32_t x, int b) {
+    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)x, b, 1);
+    if constexpr (sizeof(K) == 8) return ((unsigned long long)m << 32) | m;
+    else return m;
+}
+
+// The steps of one merge phase: exchanges at lane distance 2^(P-1) .. 1.
+template <int P, class K>
+__device__ __forceinline__ K merge_steps(K w, uint32_t lane) {
+    if constexpr (P >= 6) w = cx<32>(w, lane);
+    if constexpr (P >= 5) w = cx<16>(w, lane);
+    if constexpr (P >= 4) w = cx<8>(w, lane);
+    if constexpr (P >= 3) w = cx<4>(w, lane);
+    if constexpr (P >= 2) w = cx<2>(w, lane);
+    return cx<1>(w, lane);
+}
+
+// Sort each block of 2^P lanes (P = 6: the wave), ascending or descending.
+template <int P, bool ASC, class K>
+__device__ __forceinline__ K bitonic_sort(K v, uint32_t lane) {
+    // bit b of g: lane bits b and b + 1 differ (a phase boundary flips the
+    // lanes whose direction changes)
+    const uint32_t g = lane ^ (lane >> 1);
+    K w = v ^ bit_mask<K>(lane, 1);
+    w = merge_steps<1>(w, lane);
+    if constexpr (P > 2) { w ^= bit_mask<K>(g, 1); w = merge_steps<2>(w, lane); }
+    if constexpr (P > 3) { w ^= bit_mask<K>(g, 2); w = merge_steps<3>(w, lane); }
+    if constexpr (P > 4) { w ^= bit_mask<K>(g, 3); w = merge_steps<4>(w, lane); }
+    if constexpr (P > 5) { w ^= bit_mask<K>(g, 4); w = merge_steps<5>(w, lane); }
+    // the last phase: every lane in the final direction
+    w ^= bit_mask<K>(lane, P - 1);
+    if constexpr (!ASC) w = ~w;
+    w = merge_steps<P>(w, lane);
+    return ASC ? w : ~w;
+}
+
+// Bitonic sort of one 64-bit key per lane, descending over lanes 0..63.
+__device__ __forceinline__ unsigned long long sort64_desc(unsigned long long v, uint32_t lane) {
+    return bitonic_sort<6, false>(v, lane);
+}
+
+// Each 32-lane half sorted descending.
+__device__ __forceinline__ unsigned long long sort32x2_desc(unsigned long long v, uint32_t lane) {
+    return bitonic_sort<5, false>(v, lane);
+}
+
+// The same sort with each exchange's direction taken from a lane pattern
+// per (block size, M) pair: no XOR per phase, but 21 patterns held in scalar
+// registers. Measured faster in the density select kernel; the kNN and
+// top-lambda kernels use sort64_desc.
+template <int SIZE, int M>
+__device__ __forceinline__ unsigned long long cx_dir(unsigned long long v, uint32_t lane) {
+    const unsigned long long o = xor_lane_key<M>(v, lane);
+    const bool keep_min = ((lane & (uint32_t)M) == 0u) == ((lane & (uint32_t)SIZE) != 0u);
+    return ((o < v) == keep_min) ? o : v;
+}
+
+__device__ __forceinline__ unsigned long long sort64_desc_dir(unsigned long long v, uint32_t lane) {
+    v = cx_dir<2, 1>(v, lane);
+    v = cx_dir<4, 2>(v, lane);
+    v = cx_dir<4, 1>(v, lane);
+    v = cx_dir<8, 4>(v, lane);
+    v = cx_dir<8, 2>(v, lane);
+    v = cx_dir<8, 1>(v, lane);
+    v = cx_dir<16, 8>(v, lane);
+    v = cx_dir<16, 4>(v, lane);
+    v = cx_dir<16, 2>(v, lane);
+    v = cx_dir<16, 1>(v, lane);
+    v = cx_dir<32, 16>(v, lane);
+    v = cx_dir<32, 8>(v, lane);
+    v = cx_dir<32, 4>(v, lane);
+    v = cx_dir<32, 2>(v, lane);
+    v = cx_dir<32, 1>(v, lane);
+    v = cx_dir<64, 32>(v, lane);
+    v = cx_dir<64, 16>(v, lane);
+    v = cx_dir<64, 8>(v, lane);
+    v = cx_dir<64, 4>(v, lane);
+    v = cx_dir<64, 2>(v, lane);
+    v = cx_dir<64, 1>(v, lane);
+    return v;
+}
+
+// 32-bit keys, ascending or descending over lanes 0..63.
+template <bool ASC>
+__device__ __forceinline__ uint32_t sort64_u32(uint32_t v, uint32_t lane) {
+    return bitonic_sort<6, ASC>(v, lane);
+}
+
 // Sort a bitonic sequence (one key per lane) ascending.
 __device__ __forceinline__ unsigned long long merge64_asc(unsigned long long v, uint32_t lane) {
-    v = cx<32>(v, lane, (lane & 32u) == 0u);
-    v = cx<16>(v, lane, (lane & 16u) == 0u);
-    v = cx<8>(v, lane, (lane & 8u) == 0u);
-    v = cx<4>(v, lane, (lane & 4u) == 0u);
-    v = cx<2>(v, lane, (lane & 2u) == 0u);
-    v = cx<1>(v, lane, (lane & 1u) == 0u);
-    return v;
+    return merge_steps<6>(v, lane);
 }
 
 // Sort a bitonic sequence in each 32-lane half ascending.
 __device__ __forceinline__ unsigned long long merge32x2_asc(unsigned long long v, uint32_t lane) {
-    v = cx<16>(v, lane, (lane & 16u) == 0u);
-    v = cx<8>(v, lane, (lane & 8u) == 0u);
-    v = cx<4>(v, lane, (lane & 4u) == 0u);
-    v = cx<2>(v, lane, (lane & 2u) == 0u);
-    v = cx<1>(v, lane, (lane & 1u) == 0u);
-    return v;
+    return merge_steps<5>(v, lane);
 }
 
 // Orders this wave's LDS writes before its later LDS reads (no block barrier).
