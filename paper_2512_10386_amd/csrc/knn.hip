@@ -351,6 +351,18 @@ __device__ __forceinline__ unsigned long long sort_keys_asc(unsigned long long v
     return ~sort64_desc(~v, lane);
 }
 
+// The 64 keys in exact descending order, by the same 32-bit sort (its
+// order is exact unless two real keys agree on the top 26 bits of d2; then
+// the 64-bit network).
+__device__ __forceinline__ unsigned long long sort_keys_desc(unsigned long long v, uint32_t lane) {
+    constexpr uint32_t EMPTY_TOP = (uint32_t)(KEY_EMPTY >> 32) >> 6;
+    const uint32_t s = sort64_u32<false>(((uint32_t)(v >> 32) & ~63u) | lane, lane);
+    const uint32_t p = (uint32_t)__shfl_up((int)s, 1u, 64);
+    const bool near = lane >= 1u && (s >> 6) == (p >> 6) && (s >> 6) != EMPTY_TOP;
+    if (__builtin_amdgcn_ballot_w64(near) == 0ull) return shfl64(v, (int)(s & 63u));
+    return sort64_desc(v, lane);
+}
+
 // Merge query j's pending candidates into its list, dropping the query's own
 // key (the hot loop does not test for it); returns the new distance bound.
 // `fresh`: the list still holds only its placeholders (tau, 0xFFFFFFFF),
@@ -370,7 +382,8 @@ __device__ __forceinline__ float flush(unsigned long long* __restrict__ lst,
         v = sort_keys_asc(v, lane, k);
     } else {
         const unsigned long long L = lane < k ? lst[lane] : KEY_EMPTY;
-        v = sort64_desc(v, lane);
+        // (the 32-bit form costs large inputs a wave per SIMD in registers)
+        v = POS ? sort64_desc(v, lane) : sort_keys_desc(v, lane);
         v = merge64_asc(L < v ? L : v, lane);
     }
     if (lane < k) lst[lane] = v;
@@ -427,7 +440,7 @@ __device__ __forceinline__ void flush_half(unsigned long long* __restrict__ lst0
 // part in this chunk are not candidates: they get NaN coordinates (d2 <=
 // bound never holds). Groups of the range holding the tile come first, from
 // the tile's group outwards, then the other ranges in order.
-template <bool POS, int Q>
+template <bool POS, int Q, bool PREFETCH = !POS>
 __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __restrict__ cand4, int kk) {
     using PT = typename Pending<POS>::T;
     static_assert(Q <= 32, "tile shape (a query mask per group fits 32 bits)");
@@ -564,21 +577,19 @@ __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __r
             // lanes, so the i-th nearest sits in lane 63 - i
             const uint32_t sk =
                 sort64_u32<false>(qmask ? ((__float_as_uint(bmin) & ~63u) | (63u - lane)) : 0xFFFFFFFFu, lane);
-            for (uint32_t i0 = 0; i0 < nn; i0 += (uint32_t)KNN_NB) {
-                // the next KNN_NB needed groups: candidates in registers (NaN
-                // outside the range part), group base and query mask uniform
-                float4 c[KNN_NB];
-                uint32_t gb[KNN_NB], mk[KNN_NB];
-                uint32_t qany = 0;
+            // the KNN_NB needed groups from the i-th on: candidates in
+            // registers (NaN outside the range part), group base and query
+            // mask uniform
+            auto load_batch = [&](uint32_t i, float4 (&c)[KNN_NB], uint32_t (&gb)[KNN_NB], uint32_t (&mk)[KNN_NB]) {
 #pragma unroll
                 for (int b = 0; b < KNN_NB; ++b) {
                     const float nan = __uint_as_float(0x7FC00000u);
                     c[b] = make_float4(nan, nan, nan, __uint_as_float(NONE32));
                     gb[b] = 0u;
                     mk[b] = 0u;
-                    if (i0 + (uint32_t)b < nn) {
+                    if (i + (uint32_t)b < nn) {
                         const uint32_t uu =
-                            63u - ((uint32_t)__builtin_amdgcn_readlane((int)sk, 63 - (int)(i0 + (uint32_t)b)) & 63u);
+                            63u - ((uint32_t)__builtin_amdgcn_readlane((int)sk, 63 - (int)(i + (uint32_t)b)) & 63u);
                         const uint32_t gg = (uint32_t)__builtin_amdgcn_readlane((int)ug, (int)uu);
                         const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)ua, (int)uu);
                         const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)ue, (int)uu);
@@ -587,8 +598,22 @@ __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __r
                         const uint32_t p = gb[b] + lane;
                         if (p >= a && p < e) c[b] = cand4[p];
                     }
-                    qany |= mk[b];
                 }
+            };
+            float4 c[KNN_NB];
+            uint32_t gb[KNN_NB], mk[KNN_NB];
+            load_batch(0u, c, gb, mk);
+            for (uint32_t i0 = 0; i0 < nn; i0 += (uint32_t)KNN_NB) {
+                // PREFETCH: the next batch's candidates are loaded while this
+                // one is evaluated (a long item needs many batches in turn)
+                float4 cn[KNN_NB];
+                uint32_t gbn[KNN_NB], mkn[KNN_NB];
+                if constexpr (PREFETCH) {
+                    if (i0 + (uint32_t)KNN_NB < nn) load_batch(i0 + (uint32_t)KNN_NB, cn, gbn, mkn);
+                }
+                uint32_t qany = 0;
+#pragma unroll
+                for (int b = 0; b < KNN_NB; ++b) qany |= mk[b];
                 // each query that needs any of them, against those it needs:
                 // the passing candidates of all of them at the query's bound;
                 // appended at once unless the buffer would overflow or a group
@@ -687,6 +712,18 @@ __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __r
                         if (mj) merged |= 1ull << j;
                     }
                     if (lane == j) pcnt = cnt;
+                }
+                if (i0 + (uint32_t)KNN_NB < nn) {
+                    if constexpr (PREFETCH) {
+#pragma unroll
+                        for (int b = 0; b < KNN_NB; ++b) {
+                            c[b] = cn[b];
+                            gb[b] = gbn[b];
+                            mk[b] = mkn[b];
+                        }
+                    } else {
+                        load_batch(i0 + (uint32_t)KNN_NB, c, gb, mk);
+                    }
                 }
             }
         }

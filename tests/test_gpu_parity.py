@@ -124,6 +124,15 @@ def test_parameter_variety(den, oracle):
     check(den, oracle, xyz, k=10, leaf_cap=300, rho_percentile=100.0, alpha=0.0, keep_ratio=1.0)
 
 
+def test_many_leaves_in_one_frame(den, oracle):
+    """More leaves than the single-workgroup kNN plan keeps in registers
+    (2048): its re-read path and several rounds of offsets, against the
+    oracle."""
+    xyz, _ = synth.uniform_cube(21, 60000)
+    g, ref = check(den, oracle, xyz, k=8, leaf_cap=16, min_vox_count=1)
+    assert ref["n_leaves"] > 2048
+
+
 @pytest.mark.parametrize("chunk", [4096, 16384])
 def test_big_leaves_chunked_candidates(den, oracle, chunk):
     xyz, _ = synth.uniform_cube(10, 60000)
