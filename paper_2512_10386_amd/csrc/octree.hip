@@ -554,35 +554,104 @@ void launch_halo(const Plan& P, const Params& prm, hipStream_t st) {
 // candidate chunk). Leaves whose candidate set exceeds the chunk length are
 // split into chunks whose partial top-k lists knn_merge_kernel combines; the
 // chunk length doubles until the partial lists and items fit their
-// workspace. This kernel fixes, per leaf, the chunking and
-// the index of its first item; items of chunked leaves (the heaviest) come
-// first in the queue, then the rest, both in leaf order. The items themselves
-// are written by the bound kernel, one tile per thread.
+// workspace. This kernel fixes, per leaf, the chunking and the index of its
+// first item. Items of chunked leaves (the heaviest) come first in the
+// queue; the other leaves follow in PLAN_CLASSES classes by candidates per
+// query, largest first, each class in leaf order. An item's run time grows
+// with that ratio (a leaf of few, isolated points next to dense cells has
+// far k-th neighbours, so its queries test many candidate groups), and
+// starting such items first keeps them out of the kernel's tail. The items
+// themselves are written by the bound kernel, one tile per thread.
 
 constexpr int PLAN_BLOCK = 1024;
+constexpr int PLAN_R = 2;        // leaves per thread whose sizes stay in registers (more are re-read)
+constexpr int PLAN_CLASSES = 4;
+
+__device__ __forceinline__ uint32_t plan_class(uint32_t n1, uint32_t nc) {
+    const uint32_t q = n1 > 0 ? n1 : 1u;
+    return nc >= 128u * q ? 0u : nc >= 32u * q ? 1u : nc >= 8u * q ? 2u : 3u;
+}
+
+// Block exclusive scans of N values per thread at once (one set of
+// barriers); smem needs N * (blockDim / 64 + 1) words.
+template <int N>
+__device__ __forceinline__ void block_excl_scan_n(const uint32_t (&v)[N], uint32_t (&ex)[N], uint32_t (&tot)[N],
+                                                  uint32_t* smem) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint32_t inc[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) inc[i] = wave_incl_scan(v[i]);
+    if (lane == 63) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) smem[i * (nw + 1) + wave] = inc[i];
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)N) {
+        uint32_t* row = smem + threadIdx.x * (nw + 1);
+        uint32_t run = 0;
+        for (int w = 0; w < nw; ++w) {
+            const uint32_t t = row[w];
+            row[w] = run;
+            run += t;
+        }
+        row[nw] = run;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        ex[i] = smem[i * (nw + 1) + wave] + inc[i] - v[i];
+        tot[i] = smem[i * (nw + 1) + nw];
+    }
+    __syncthreads();
+}
 
 __global__ __launch_bounds__(PLAN_BLOCK) void knn_plan_kernel(Plan P, int chunk0) {
+    constexpr int NS = 2 + PLAN_CLASSES;  // partial lists, chunked items, items per class
     __shared__ unsigned long long s_red[PLAN_BLOCK / 64][3];
-    __shared__ uint32_t s_scan[PLAN_BLOCK / 64 + 1];
-    __shared__ uint32_t s_cc, s_done, s_carry_l, s_carry_c, s_carry_u, s_chunked_items;
+    __shared__ uint32_t s_scan[NS * (PLAN_BLOCK / 64 + 1)];
+    __shared__ uint32_t s_cc, s_done, s_carry[NS], s_base[NS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t nl = P.ctr->n_leaves;
+    // this thread's leaves t = tid + r * PLAN_BLOCK: P1 points and candidates
+    uint32_t c_n1[PLAN_R], c_nc[PLAN_R];
+#pragma unroll
+    for (int r = 0; r < PLAN_R; ++r) {
+        const uint32_t t = (uint32_t)tid + (uint32_t)r * PLAN_BLOCK;
+        c_n1[r] = 0;
+        c_nc[r] = 0;
+        if (t < nl) {
+            c_n1[r] = P.p1pos[P.leaf_begin[t + 1]] - P.p1pos[P.leaf_begin[t]];
+            c_nc[r] = P.leaf_ncand[t];
+        }
+    }
+    auto for_leaves = [&](auto&& f) {
+#pragma unroll
+        for (int r = 0; r < PLAN_R; ++r) {
+            const uint32_t t = (uint32_t)tid + (uint32_t)r * PLAN_BLOCK;
+            if (t < nl) f(t, c_n1[r], c_nc[r]);
+        }
+        for (uint32_t t = (uint32_t)tid + (uint32_t)PLAN_R * PLAN_BLOCK; t < nl; t += PLAN_BLOCK)
+            f(t, P.p1pos[P.leaf_begin[t + 1]] - P.p1pos[P.leaf_begin[t]], P.leaf_ncand[t]);
+    };
+    auto nch_of = [](uint32_t n1, uint32_t nc, uint32_t cc) -> uint32_t {
+        if (n1 == 0) return 1u;
+        uint32_t nch = (nc + cc - 1) / cc;
+        if (nch < 1) nch = 1;
+        if (nch > KNN_NCH_MAX) nch = KNN_NCH_MAX;
+        return nch;
+    };
     if (tid == 0) { s_cc = (uint32_t)chunk0; s_done = 0; }
     __syncthreads();
     for (int iter = 0; iter < 40; ++iter) {
         const uint32_t cc = s_cc;
         unsigned long long lists = 0, items = 0, pairs = 0;
-        for (uint32_t t = tid; t < nl; t += PLAN_BLOCK) {
-            const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
-            const uint32_t n1 = qe - qb, nc = P.leaf_ncand[t];
-            if (n1 == 0) continue;
-            uint32_t nch = (nc + cc - 1) / cc;
-            if (nch < 1) nch = 1;
-            if (nch > KNN_NCH_MAX) nch = KNN_NCH_MAX;
+        for_leaves([&](uint32_t, uint32_t n1, uint32_t nc) {
+            if (n1 == 0) return;
+            const uint32_t nch = nch_of(n1, nc, cc);
             if (nch > 1) lists += (unsigned long long)n1 * nch;
             items += (unsigned long long)((n1 + P.tq - 1) / P.tq) * nch;
             pairs += (unsigned long long)n1 * (nc - 1);
-        }
+        });
         for (int o = 32; o > 0; o >>= 1) {
             lists += __shfl_xor(lists, o, 64);
             items += __shfl_xor(items, o, 64);
@@ -604,61 +673,106 @@ __global__ __launch_bounds__(PLAN_BLOCK) void knn_plan_kernel(Plan P, int chunk0
         if (s_done) break;
     }
     const uint32_t cc = s_cc;
-    {
-        unsigned long long ic = 0;
-        for (uint32_t t = tid; t < nl; t += PLAN_BLOCK) {
-            const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
-            const uint32_t n1 = qe - qb, nc = P.leaf_ncand[t];
-            uint32_t nch = (nc + cc - 1) / cc;
-            if (nch > KNN_NCH_MAX) nch = KNN_NCH_MAX;
-            if (n1 > 0 && nch > 1) ic += (unsigned long long)((n1 + P.tq - 1) / P.tq) * nch;
+    // per leaf: its partial lists, its items (chunked, or in its class)
+    auto counts = [&](uint32_t n1, uint32_t nc, uint32_t (&v)[NS], uint32_t& nch) {
+        nch = nch_of(n1, nc, cc);
+#pragma unroll
+        for (int i = 0; i < NS; ++i) v[i] = 0;
+        const uint32_t ni = n1 ? ((n1 + P.tq - 1) / P.tq) * nch : 0u;
+        if (nch > 1) {
+            v[0] = n1 * nch;
+            v[1] = ni;
+        } else {
+            v[2 + plan_class(n1, nc)] = ni;
         }
-        for (int o = 32; o > 0; o >>= 1) ic += __shfl_xor(ic, o, 64);
-        if (lane == 0) s_red[wave][0] = ic;
-        __syncthreads();
+    };
+    if (nl <= (uint32_t)PLAN_BLOCK) {
+        // one round: the scan gives every thread the class totals too
+        uint32_t v[NS], nch = 1;
+        if ((uint32_t)tid < nl) counts(c_n1[0], c_nc[0], v, nch);
+        else {
+#pragma unroll
+            for (int i = 0; i < NS; ++i) v[i] = 0;
+        }
+        uint32_t ex[NS], tot[NS], base[NS];
+        block_excl_scan_n<NS>(v, ex, tot, s_scan);
+        base[0] = 0;
+        base[1] = 0;
+        uint32_t acc = tot[1];  // chunked items first
+#pragma unroll
+        for (int i = 2; i < NS; ++i) { base[i] = acc; acc += tot[i]; }
+        if ((uint32_t)tid < nl) {
+            const uint32_t t = (uint32_t)tid, n1 = c_n1[0], nc = c_nc[0];
+            P.leaf_nch[t] = nch;
+            P.leaf_cc[t] = (nc + nch - 1) / nch;
+            P.leaf_plist[t] = ex[0];
+            const uint32_t q = nch > 1 ? 1u : 2u + plan_class(n1, nc);
+            P.leaf_item[t] = base[q] + ex[q];
+        }
         if (tid == 0) {
-            unsigned long long T = 0;
-            for (int w = 0; w < PLAN_BLOCK / 64; ++w) T += s_red[w][0];
-            s_chunked_items = (uint32_t)T;
-            s_carry_l = 0;
-            s_carry_c = 0;
-            s_carry_u = 0;
+            P.ctr->n_items = acc;
+            P.ctr->n_chunked_items = tot[1];
+        }
+        return;
+    }
+    // totals: the queue offset of each class
+    {
+        uint32_t tot[NS];
+#pragma unroll
+        for (int i = 0; i < NS; ++i) tot[i] = 0;
+        for_leaves([&](uint32_t, uint32_t n1, uint32_t nc) {
+            uint32_t v[NS], nch;
+            counts(n1, nc, v, nch);
+#pragma unroll
+            for (int i = 0; i < NS; ++i) tot[i] += v[i];
+        });
+        uint32_t ex[NS], all[NS];
+        block_excl_scan_n<NS>(tot, ex, all, s_scan);
+        if (tid == 0) {
+            uint32_t acc = all[1];  // chunked items first
+            s_base[0] = 0;
+            s_base[1] = 0;
+            for (int i = 2; i < NS; ++i) { s_base[i] = acc; acc += all[i]; }
+            for (int i = 0; i < NS; ++i) s_carry[i] = 0;
+            P.ctr->n_items = acc;
+            P.ctr->n_chunked_items = all[1];
         }
         __syncthreads();
     }
-    const uint32_t n_chunked_items = s_chunked_items;
-    for (uint32_t t0 = 0; t0 < nl; t0 += PLAN_BLOCK) {
-        const uint32_t t = t0 + tid;
-        uint32_t nl1 = 0, nic = 0, niu = 0, nch = 1, nc = 0;
-        if (t < nl) {
-            const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
-            nc = P.leaf_ncand[t];
-            const uint32_t n1 = qe - qb;
-            nch = (nc + cc - 1) / cc;
-            if (nch < 1) nch = 1;
-            if (nch > KNN_NCH_MAX) nch = KNN_NCH_MAX;
-            if (n1 == 0) nch = 1;
-            const uint32_t ni = n1 ? ((n1 + P.tq - 1) / P.tq) * nch : 0u;
-            nl1 = (nch > 1) ? n1 * nch : 0u;
-            if (nch > 1) nic = ni; else niu = ni;
+    // offsets, one round of PLAN_BLOCK leaves at a time
+    auto round = [&](uint32_t t, uint32_t n1, uint32_t nc) {
+        uint32_t v[NS], nch = 1;
+        if (t < nl) counts(n1, nc, v, nch);
+        else {
+#pragma unroll
+            for (int i = 0; i < NS; ++i) v[i] = 0;
         }
-        uint32_t totl, totc, totu;
-        const uint32_t exl = block_excl_scan(nl1, s_scan, &totl);
-        const uint32_t exc = block_excl_scan(nic, s_scan, &totc);
-        const uint32_t exu = block_excl_scan(niu, s_scan, &totu);
+        uint32_t ex[NS], tot[NS];
+        block_excl_scan_n<NS>(v, ex, tot, s_scan);
         if (t < nl) {
             P.leaf_nch[t] = nch;
             P.leaf_cc[t] = (nc + nch - 1) / nch;
-            P.leaf_plist[t] = s_carry_l + exl;
-            P.leaf_item[t] = (nch > 1) ? s_carry_c + exc : n_chunked_items + s_carry_u + exu;
+            P.leaf_plist[t] = s_carry[0] + ex[0];
+            const uint32_t q = nch > 1 ? 1u : 2u + plan_class(n1, nc);
+            P.leaf_item[t] = s_base[q] + s_carry[q] + ex[q];
         }
         __syncthreads();
-        if (tid == 0) { s_carry_l += totl; s_carry_c += totc; s_carry_u += totu; }
+        if (tid < NS) s_carry[tid] += tot[tid];
         __syncthreads();
+    };
+#pragma unroll
+    for (int r = 0; r < PLAN_R; ++r) {
+        const uint32_t t0 = (uint32_t)r * PLAN_BLOCK;
+        if (t0 < nl) round(t0 + (uint32_t)tid, c_n1[r], c_nc[r]);
     }
-    if (tid == 0) {
-        P.ctr->n_items = s_carry_c + s_carry_u;
-        P.ctr->n_chunked_items = s_carry_c;
+    for (uint32_t t0 = (uint32_t)PLAN_R * PLAN_BLOCK; t0 < nl; t0 += PLAN_BLOCK) {
+        const uint32_t t = t0 + (uint32_t)tid;
+        uint32_t n1 = 0, nc = 0;
+        if (t < nl) {
+            n1 = P.p1pos[P.leaf_begin[t + 1]] - P.p1pos[P.leaf_begin[t]];
+            nc = P.leaf_ncand[t];
+        }
+        round(t, n1, nc);
     }
 }
 
