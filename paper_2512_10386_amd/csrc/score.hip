@@ -508,14 +508,30 @@ __global__ __launch_bounds__(256) void score_kernel(Plan P, int kk, double eps, 
         return w_den * w_dis * kern;
     };
     if constexpr (PAIR) {
-        for (uint32_t q0 = wid * qpw; q0 < np1; q0 += 2u * nw * qpw) {
+        // XCD-aware: the query tiles go in chunks of C consecutive tiles,
+        // chunk c to the blocks b with b % 8 = c % 8 (the dispatcher hands
+        // blocks to the eight XCDs in turn), so the neighbours a chunk gathers
+        // (mostly within a few hundred P1 positions) stay in one XCD's L2:
+        // half the HBM fetch of interleaved tiles, at the same speed. Whole
+        // eighths per XCD fetched as little but balanced the uneven P2 tiles
+        // worse (+5% time).
+        constexpr uint32_t C = 64;
+        const uint32_t wv = threadIdx.x >> 6, tq = qpw * (blockDim.x >> 6);
+        const uint32_t T = (np1 + tq - 1) / tq;
+        const uint32_t xcd = blockIdx.x % 8u, bi = blockIdx.x / 8u, nb = gridDim.x / 8u;
+        // this XCD's i-th tile; the loop runs while the chunk of i can hold tiles
+        auto tile_of = [&](uint32_t i) { return ((i / C) * 8u + xcd) * C + i % C; };
+        const uint32_t t_hi = T;
+        for (uint32_t i = bi; ((i / C) * 8u + xcd) * C < T || tile_of(i + nb) < T; i += 2u * nb) {
+            const uint32_t t = tile_of(i);
             uint32_t qi0, j0, qi1, j1;
             bool l0, l1;
             float4 a0, a1, c0{}, c1{};
             double2 f0, f1;
             double g0 = 0.0, g1 = 0.0;
-            fetch(q0, qi0, j0, l0, a0, f0);
-            fetch(q0 + nw * qpw, qi1, j1, l1, a1, f1);
+            fetch(t < t_hi ? t * tq + wv * qpw : np1, qi0, j0, l0, a0, f0);
+            const uint32_t t1 = tile_of(i + nb);
+            fetch(t1 < t_hi ? t1 * tq + wv * qpw : np1, qi1, j1, l1, a1, f1);
             if (j0 < P.n) { c0 = P.cand4[j0]; g0 = P.gpow_p[j0]; }
             if (j1 < P.n) { c1 = P.cand4[j1]; g1 = P.gpow_p[j1]; }
             const double F0 = seg_sum(j0 < P.n ? term_of(c0, g0, a0, f0) : 0.0, kp);
@@ -544,6 +560,7 @@ void launch_score(const Plan& P, const Params& prm, hipStream_t st) {
     if (blocks > 8192) blocks = 8192;
     if (blocks == 0) blocks = 1;
     const bool pair = P.n > SCORE_PAIR_MIN_N;
+    if (pair) blocks = (blocks + 7u) & ~7u;  // a whole number of blocks per XCD
     const bool g2 = prm.gamma == 2.0;
     auto kern = g2 ? (pair ? score_kernel<true, true> : score_kernel<true, false>)
                    : (pair ? score_kernel<false, true> : score_kernel<false, false>);
