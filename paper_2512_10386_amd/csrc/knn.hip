@@ -1,30 +1,32 @@
 // Leaf-local brute-force kNN with halo candidates (Sec. 3: N_K(i), d_ij and
 // r_K,i on the voxel-filtered set P1).
 //
-// Work item = (leaf, up to 16 queries, candidate chunk), one wave each. The
-// candidates are the P1 positions of the leaf's merged halo ranges; they are
-// visited in aligned groups of 64 positions (one per lane), whose bounding
-// boxes the bound kernel writes. Up to 64 groups at a time are box-tested
-// against the tile's queries and ordered nearest-first; before a group is
-// tested its box is checked again against every query's current bound, and
-// only the queries that still need it compute their squared distances to its
-// 64 candidates, in fp32 as (dx*dx + dy*dy) + dz*dz without contraction, so
-// the neighbour sets are exact. A skipped group holds no candidate within the
-// query's bound (the box distance uses the same rounded operations, which are
-// monotone), so skipping never changes a result.
+// Work item = (leaf, a tile of 8 queries (16 above 2^20 points), candidate
+// chunk), one wave each. The candidates are the P1 positions of the leaf's
+// merged halo ranges; they are visited in aligned groups of 64 positions (one
+// per lane), whose bounding boxes the bound kernel writes. Up to 64 groups at
+// a time are box-tested against every query of the tile (a query mask per
+// group) and ordered nearest-first; the needed groups are then taken four at
+// a time into registers, and each query that needs any of them computes its
+// squared distances to their 64 candidates, in fp32 as (dx*dx + dy*dy) + dz*dz
+// without contraction, so the neighbour sets are exact. A skipped group holds
+// no candidate within the query's bound (the box distance uses the same
+// rounded operations, which are monotone), so skipping never changes a result.
 //
 // Each query keeps, in LDS, its k best (d2, original index) keys (d2 bits <<
-// 32 | index), sorted, one per lane when loaded, and a pending buffer of up
-// to 64 candidates (the keys, or their P1 positions above 1M points, which
-// halves the LDS a wave needs; a key is then rebuilt from the position with
-// the same fp32 expression). A candidate passes with one compare against the
-// query's bound; the passing ones are appended (ballot + lane rank). A full
-// buffer, and the buffer at the end of the item, is merged into the list: the
-// 64 pending keys are sorted descending by a wave-wide bitonic network, the
-// elementwise minimum with the ascending list holds the 64 smallest keys of
-// both as a bitonic sequence, and six more exchange steps sort it. The list
-// keeps the first k. When k <= 32, buffers holding at most 32 keys at the end
-// of an item are merged on 32-lane halves, two queries at once.
+// 32 | index), sorted, and a pending buffer of up to 64 candidates (the keys,
+// or their P1 positions above 1M points, which halves the LDS a wave needs; a
+// key is then rebuilt from the position with the same fp32 expression). A
+// candidate passes with one compare against the query's bound; the passing
+// ones are appended (ballot + lane rank). A full buffer, and the buffer at
+// the end of the item, is merged into the list: the pending keys are sorted
+// descending across the wave, the elementwise minimum with the ascending list
+// holds the 64 smallest keys of both as a bitonic sequence, and six more
+// exchange steps sort it; a list never merged into takes its pending keys
+// sorted ascending. The sorts run on 32-bit keys (the top 26 bits of d2 and
+// the lane) and fall back to the 64-bit keys when two of them could tie.
+// When k <= 32, buffers holding at most 32 keys at the end of an item are
+// merged on 32-lane halves, two queries at once.
 //
 // Bound: knn_bound_kernel gives each query tau >= its k-th squared distance
 // (from k of its own candidates), so its list starts as k placeholder keys
@@ -434,12 +436,15 @@ __device__ __forceinline__ void flush_half(unsigned long long* __restrict__ lst0
 // coalesced load) and box-tested against every query of the tile, with the
 // same fp32 operations as dist2: a query skips a group whose box distance
 // exceeds its bound, so the group holds no candidate with d2 <= that bound.
-// Lane j then holds query j's mask of needed groups; a group is loaded only
-// if some query needs it, the next needed group's candidates being fetched
-// while the current one is tested. Positions of a group outside the range's
-// part in this chunk are not candidates: they get NaN coordinates (d2 <=
-// bound never holds). Groups of the range holding the tile come first, from
-// the tile's group outwards, then the other ranges in order.
+// Lane u then holds group u's mask of the queries that need it; a group is
+// loaded only if some query needs it, four at a time (with PREFETCH the next
+// four are fetched while these are evaluated). Positions of a group outside
+// the range's part in this chunk are not candidates: they get NaN coordinates
+// (d2 <= bound never holds). Groups of the range holding the tile come first,
+// from the tile's group outwards, then the other ranges in order.
+// PREFETCH (single frames): the extra registers drop the kernel to 4 waves
+// per SIMD, which is what their grid launches anyway; large inputs run 5
+// waves per SIMD and lose more to the lower occupancy than they gain.
 template <bool POS, int Q, bool PREFETCH = !POS>
 __global__ __launch_bounds__(64) void knn_group_kernel(Plan P, const float4* __restrict__ cand4, int kk) {
     using PT = typename Pending<POS>::T;
