@@ -142,9 +142,10 @@ def test_big_leaves_chunked_candidates(den, oracle, chunk):
 
 def test_single_frame_above_1m_against_oracle(den, oracle):
     """A single frame of more than 1M points takes the large-input paths
-    (16-key radix tiles, one-wave small-leaf kernels, position pending buffers
-    in the kNN, the coarse bound ladder, packed output records written out by
-    the keep scan): every intermediate against the oracle at the full parity
+    (16-key radix tiles, one-wave small-leaf kernels, 16-query kNN tiles with
+    position pending buffers, the XCD-chunked score order, packed output
+    records written out by the keep scan): every intermediate against the
+    oracle at the full parity
     bar, and the outputs consistent with each other. Nine LiDAR sweeps 200 m
     apart make one frame whose octree reaches level 13 (deep level-10 cells
     re-sorted on the whole key)."""
