@@ -231,14 +231,14 @@ struct RhoBits {
     }
 };
 
-// A block's leaves are t = blockIdx.x (mod gridDim.x). They are examined
+// A block's leaves are t = its index (mod the stride). They are examined
 // SEL_BLOCK at a time, one per thread (one round of loads instead of a chain
 // of them), and those the block must handle (with `small`, the ones above
 // SMALL_LEAF P1 points; otherwise all) are listed in order in s_list.
 // Returns the count; whole block.
 __device__ uint32_t block_leaf_round(const Plan& P, uint32_t base, uint32_t nl, bool small, uint32_t* s_list,
-                                     uint32_t* s_scan) {
-    const uint32_t ti = base + threadIdx.x * gridDim.x;
+                                     uint32_t* s_scan, uint32_t stride) {
+    const uint32_t ti = base + threadIdx.x * stride;
     uint32_t take = 0;
     if (ti < nl)
         take = small ? (P.p1pos[P.leaf_begin[ti + 1]] - P.p1pos[P.leaf_begin[ti]] > SMALL_LEAF ? 1u : 0u) : 1u;
@@ -257,14 +257,17 @@ __device__ uint32_t block_leaf_round(const Plan& P, uint32_t base, uint32_t nl, 
 // drops points with fewer than k candidates). The median of the densities is
 // the middle value, or the mean of the two middle values for even n1.
 
-template <class RG, class HG>
-__device__ void leaf_cut_and_median(RG r2, HG rho, uint32_t n1, double q, float* cut, double* med,
-                                    uint32_t* s_hist, uint32_t* s_sel) {
+template <class RG>
+__device__ float leaf_cut(RG r2, uint32_t n1, double q, uint32_t* s_hist, uint32_t* s_sel) {
     double cd = ceil((double)n1 * q / 100.0 + 0.5);
     if (cd < 1.0) cd = 1.0;
     if (cd > (double)n1) cd = (double)n1;
     const uint32_t c = (uint32_t)cd;
-    *cut = __uint_as_float(block_select<uint32_t>(r2, n1, n1 - c, s_hist, s_sel));
+    return __uint_as_float(block_select<uint32_t>(r2, n1, n1 - c, s_hist, s_sel));
+}
+
+template <class HG>
+__device__ void leaf_median(HG rho, uint32_t n1, double* med, uint32_t* s_hist, uint32_t* s_sel) {
     if (n1 & 1u) {
         *med = __longlong_as_double((long long)block_select<unsigned long long>(rho, n1, (n1 - 1) / 2, s_hist, s_sel));
     } else {
@@ -274,6 +277,11 @@ __device__ void leaf_cut_and_median(RG r2, HG rho, uint32_t n1, double q, float*
     }
 }
 
+// Two workgroups per leaf, side by side: role 0 (even blocks) finds the
+// percentile cut and writes P2, role 1 (odd blocks) the median, the weight
+// factors and the density powers. Both compute the leaf's densities (the
+// same values, stored twice); the two selects, each a chain of
+// barrier-separated passes, then run at the same time instead of in turn.
 template <bool SQRT>
 __global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params prm, bool small,
                                                                const float* __restrict__ xyz) {
@@ -285,47 +293,58 @@ __global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params p
     __shared__ uint32_t s_lscan[SEL_BLOCK / 64 + 1];
     const uint32_t nl = P.ctr->n_leaves;
     const int k = prm.k;
-    for (uint32_t base = blockIdx.x; base < nl; base += gridDim.x * SEL_BLOCK) {
-    const uint32_t nlist = block_leaf_round(P, base, nl, small, s_list, s_lscan);
+    const uint32_t role = blockIdx.x & 1u, bx = blockIdx.x >> 1, gx = gridDim.x >> 1;
+    for (uint32_t base = bx; base < nl; base += gx * SEL_BLOCK) {
+    const uint32_t nlist = block_leaf_round(P, base, nl, small, s_list, s_lscan, gx);
     for (uint32_t li = 0; li < nlist; ++li) {
         const uint32_t t = s_list[li];
         const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
         const uint32_t n1 = qe - qb;
         if (small && n1 <= SMALL_LEAF) continue;  // leaf_select_small_kernel
         if (n1 == 0) {
-            if (threadIdx.x == 0) { P.leaf_rho_med[t] = 0.0; P.leaf_r2cut[t] = 0.0f; }
+            if (threadIdx.x == 0) {
+                if (role == 0u) P.leaf_r2cut[t] = 0.0f;
+                else P.leaf_rho_med[t] = 0.0;
+            }
             continue;
         }
-        float cut;
-        double med;
+        float cut = 0.0f;
+        double med = 0.0;
         if (n1 <= SEL_LDS_MAX) {
             for (uint32_t i = threadIdx.x; i < n1; i += blockDim.x) {
                 const Dens dn = density_at(P, xyz, (uint32_t)k, qb + i);
-                s_r2[i] = __float_as_uint(dn.r2);
-                s_rho[i] = (unsigned long long)__double_as_longlong(dn.rho);
+                if (role == 0u) s_r2[i] = __float_as_uint(dn.r2);
+                else s_rho[i] = (unsigned long long)__double_as_longlong(dn.rho);
             }
             __syncthreads();
-            leaf_cut_and_median(LdsBits<uint32_t>{s_r2}, LdsBits<unsigned long long>{s_rho}, n1, prm.rho_percentile,
-                                &cut, &med, s_hist, s_sel);
+            if (role == 0u) cut = leaf_cut(LdsBits<uint32_t>{s_r2}, n1, prm.rho_percentile, s_hist, s_sel);
+            else leaf_median(LdsBits<unsigned long long>{s_rho}, n1, &med, s_hist, s_sel);
         } else {
             for (uint32_t i = threadIdx.x; i < n1; i += blockDim.x) (void)density_at(P, xyz, (uint32_t)k, qb + i);
             __syncthreads();
-            leaf_cut_and_median(R2Bits{P.r2k, qb}, RhoBits{P.rho_c, qb}, n1, prm.rho_percentile, &cut, &med, s_hist,
-                                s_sel);
+            if (role == 0u) cut = leaf_cut(R2Bits{P.r2k, qb}, n1, prm.rho_percentile, s_hist, s_sel);
+            else leaf_median(RhoBits{P.rho_c, qb}, n1, &med, s_hist, s_sel);
         }
-        const double den = med * med + prm.eps;
-        const double ha = prm.alpha / 2.0;
         // same thread-to-point mapping as the density loop: each thread reads back its own stores
-        for (uint32_t i = threadIdx.x; i < n1; i += blockDim.x) {
-            const uint32_t qi = qb + i;
-            const bool insufficient = P.krec[qi].x == NO_NBR;
-            P.p2[qi] = (!insufficient && P.r2k[qi] <= cut) ? 1 : 0;
-            const double sr = prm.sigma * P.r64_c[qi];
-            P.afac_c[qi] = make_double2(pow_ha<SQRT>(P.rho_c[qi] / den, ha), 1.0 / (2.0 * sr * sr));
-            // rho_j^(alpha/2) of Eq. 17's factored density weight, by original index
-            P.gpow_p[qi] = pow_ha<SQRT>(P.rho_c[qi], ha);
+        if (role == 0u) {
+            for (uint32_t i = threadIdx.x; i < n1; i += blockDim.x) {
+                const uint32_t qi = qb + i;
+                const bool insufficient = P.krec[qi].x == NO_NBR;
+                P.p2[qi] = (!insufficient && P.r2k[qi] <= cut) ? 1 : 0;
+            }
+            if (threadIdx.x == 0) P.leaf_r2cut[t] = cut;
+        } else {
+            const double den = med * med + prm.eps;
+            const double ha = prm.alpha / 2.0;
+            for (uint32_t i = threadIdx.x; i < n1; i += blockDim.x) {
+                const uint32_t qi = qb + i;
+                const double sr = prm.sigma * P.r64_c[qi];
+                P.afac_c[qi] = make_double2(pow_ha<SQRT>(P.rho_c[qi] / den, ha), 1.0 / (2.0 * sr * sr));
+                // rho_j^(alpha/2) of Eq. 17's factored density weight, by P1 position
+                P.gpow_p[qi] = pow_ha<SQRT>(P.rho_c[qi], ha);
+            }
+            if (threadIdx.x == 0) P.leaf_rho_med[t] = med;
         }
-        if (threadIdx.x == 0) { P.leaf_rho_med[t] = med; P.leaf_r2cut[t] = cut; }
         __syncthreads();
     }
     __syncthreads();  // s_list is refilled by the next round
@@ -450,8 +469,8 @@ void launch_leaf_select(const Plan& P, const Params& prm, const float* xyz, hipS
     }
     unsigned blocks = P.n < 2048 ? P.n : 2048;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(sq ? leaf_select_kernel<true> : leaf_select_kernel<false>, dim3(blocks), dim3(SEL_BLOCK), 0, st,
-                       P, prm, small, xyz);
+    hipLaunchKernelGGL(sq ? leaf_select_kernel<true> : leaf_select_kernel<false>, dim3(2 * blocks), dim3(SEL_BLOCK), 0,
+                       st, P, prm, small, xyz);
 }
 
 // ---------------------------------------------------------------- score
@@ -621,7 +640,7 @@ __global__ __launch_bounds__(SEL_BLOCK) void topl_kernel(Plan P, double lambda, 
     __shared__ uint32_t s_lscan[SEL_BLOCK / 64 + 1];
     const uint32_t nl = P.ctr->n_leaves;
     for (uint32_t base = blockIdx.x; base < nl; base += gridDim.x * SEL_BLOCK) {
-    const uint32_t nlist = block_leaf_round(P, base, nl, small, s_list, s_lscan);
+    const uint32_t nlist = block_leaf_round(P, base, nl, small, s_list, s_lscan, gridDim.x);
     for (uint32_t li = 0; li < nlist; ++li) {
         const uint32_t t = s_list[li];
         const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
