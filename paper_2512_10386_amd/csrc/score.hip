@@ -611,16 +611,28 @@ template <class KG, class IG>
 __device__ void topl_cut(KG key, IG tie_idx_of, uint32_t n1, uint32_t m, unsigned long long* theta,
                          uint32_t* idx_cut, uint32_t* s_hist, uint32_t* s_sel, uint32_t* s_cnt) {
     const unsigned long long th = block_select<unsigned long long>(key, n1, n1 - m, s_hist, s_sel);
-    if (threadIdx.x == 0) *s_cnt = 0;
+    uint32_t* const s_eq = s_sel + SEL_SCRATCH - 1;  // free between selects
+    if (threadIdx.x == 0) { *s_cnt = 0; *s_eq = 0; }
     __syncthreads();
-    uint32_t g = 0;
-    for (uint32_t i = threadIdx.x; i < n1; i += blockDim.x) g += key(i) > th ? 1u : 0u;
+    uint32_t g = 0, e = 0;
+    for (uint32_t i = threadIdx.x; i < n1; i += blockDim.x) {
+        const unsigned long long kv = key(i);
+        g += kv > th ? 1u : 0u;
+        e += kv == th ? 1u : 0u;
+    }
     g = wave_sum(g);
+    e = wave_sum(e);
     if ((threadIdx.x & 63) == 0 && g) atomicAdd(s_cnt, g);
+    if ((threadIdx.x & 63) == 0 && e) atomicAdd(s_eq, e);
     __syncthreads();
     const uint32_t need = m - *s_cnt;
-    auto tie = [&](uint32_t i) -> uint32_t { return key(i) == th ? tie_idx_of(i) : 0xFFFFFFFFu; };
-    *idx_cut = block_select<uint32_t>(tie, n1, need - 1, s_hist, s_sel);
+    if (*s_eq == need) {
+        // every key equal to theta is kept (the usual case: one such key)
+        *idx_cut = 0xFFFFFFFFu;
+    } else {
+        auto tie = [&](uint32_t i) -> uint32_t { return key(i) == th ? tie_idx_of(i) : 0xFFFFFFFFu; };
+        *idx_cut = block_select<uint32_t>(tie, n1, need - 1, s_hist, s_sel);
+    }
     *theta = th;
 }
 
