@@ -370,24 +370,40 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
     __shared__ uint32_t s_foff[SORT_FOFF_LDS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int shift = 8 * pass;
+    // this digit's total over the pass, needed only after the ranking: read first
+    const uint32_t hv = hist[tid];
     // frame passes of batches with few frames search the offsets in LDS
     const bool foff_lds = pass >= SORT_PASSES && nf < SORT_FOFF_LDS;
     if (foff_lds)
         for (uint32_t i = tid; i <= nf; i += SORT_BLOCK) s_foff[i] = foff[i];
     for (int i = tid; i < (SORT_BLOCK / 64) * 256; i += SORT_BLOCK) (&s_w[0][0])[i] = 0u;
-    if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    const uint32_t tbase = tile * (SORT_BLOCK * ITEMS) + wave * (64 * ITEMS);
 
     uint64_t key[ITEMS];
     uint32_t val[ITEMS], dig[ITEMS], rank[ITEMS];
+    auto load_tile = [&](uint32_t tl) {
+        const uint32_t tb = tl * (SORT_BLOCK * ITEMS) + wave * (64 * ITEMS);
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t pos = tb + i * 64 + lane;
+            const bool ok = pos < n;
+            key[i] = ok ? kin[pos] : 0ull;
+            val[i] = ok ? vin[pos] : 0u;
+        }
+    };
+    // The tile order of the look-back is the order of the tile counter; the
+    // workgroups normally take it in launch order, so the tile of this
+    // workgroup's index is loaded while the counter is read, and loaded again
+    // only if the counter gave another one.
+    load_tile(blockIdx.x);
+    if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    if (tile != blockIdx.x) load_tile(tile);
+    const uint32_t tbase = tile * (SORT_BLOCK * ITEMS) + wave * (64 * ITEMS);
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         uint32_t pos = tbase + i * 64 + lane;
         bool ok = pos < n;
-        key[i] = ok ? kin[pos] : 0ull;
-        val[i] = ok ? vin[pos] : 0u;
         uint32_t d;
         if (pass < SORT_PASSES) {
             d = (uint32_t)((key[i] >> shift) & 255u);
@@ -435,10 +451,11 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
     // look-back over earlier tiles, digit by digit
     uint32_t* st = status + (size_t)tile * 256 + tid;
     uint32_t excl = 0;
-    if (tile == 0) {
-        st_relaxed_agent(st, LB_FLAG_PRE | tcnt);
-    } else {
-        st_relaxed_agent(st, LB_FLAG_AGG | tcnt);
+    st_relaxed_agent(st, (tile == 0 ? LB_FLAG_PRE : LB_FLAG_AGG) | tcnt);
+    // global base of each digit (while the earlier tiles publish theirs)
+    uint32_t total;
+    const uint32_t gex = block_excl_scan(hv, s_scan, &total);
+    if (tile != 0) {
         // LB_WINDOW predecessors per round trip; consume ready words nearest
         // first until an inclusive prefix, stop at the first one not ready
         int j = (int)tile - 1;
@@ -474,9 +491,6 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
         }
         st_relaxed_agent(st, LB_FLAG_PRE | ((excl + tcnt) & LB_VALUE));
     }
-    // global base of each digit
-    uint32_t total;
-    uint32_t gex = block_excl_scan(hist[tid], s_scan, &total);
     s_base[tid] = gex + excl;
     if constexpr (ITEMS >= 16) {
         // Large tiles: stage the tile in LDS in digit order, then write each

@@ -21,6 +21,14 @@ namespace gdn {
 // transpose in between (padded one word per 32 against bank conflicts).
 __device__ __forceinline__ uint32_t scan_lds_at(uint32_t e) { return e + (e >> 5); }
 
+// True for a getter whose get() also stores outputs: its elements are read
+// one by one once the tile is known (its stores keep its loads in order, and
+// made before the tile counter is read they would delay it).
+template <class Get>
+struct ScanGetWrites {
+    static constexpr bool value = false;
+};
+
 template <int ITEMS, class Get, class Emit, class Fin>
 __global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(Get get, Emit emit, Fin fin,
                                                           const uint32_t* n_dev, uint32_t n_host,
@@ -33,7 +41,40 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(Get get, Emit emit, Fi
     __shared__ uint32_t s_pre[TILE + TILE / 32];
     const uint32_t n = n_dev ? *n_dev : n_host;
     const uint32_t ntiles = (n + TILE - 1) / TILE;
-    for (;;) {
+    // Workgroups normally take the tile counter in launch order: when the
+    // count is known on the host, the elements of the tile of this
+    // workgroup's index are read while the counter is, and kept if the
+    // counter gives that tile (read again otherwise).
+    // The values are read into registers first and stored to LDS after, and
+    // every read is made (past the end, of the last element, then dropped), so
+    // a thread's reads, and the loads inside each get(), are in flight
+    // together.
+    constexpr bool writes = ScanGetWrites<Get>::value;
+    auto read_tile = [&](uint32_t tbase, uint32_t* r) {
+        if constexpr (writes) {
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t idx = tbase + (uint32_t)i * SCAN_BLOCK + threadIdx.x;
+                r[i] = idx < n ? get(idx) : 0u;
+            }
+            return;
+        }
+        if (n == 0u) {
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) r[i] = 0u;
+            return;
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t idx = tbase + (uint32_t)i * SCAN_BLOCK + threadIdx.x;
+            const uint32_t v = get(idx < n ? idx : n - 1u);
+            r[i] = idx < n ? v : 0u;
+        }
+    };
+    const bool guess = !writes && n_dev == nullptr;
+    uint32_t gv[ITEMS];
+    if (guess) read_tile(blockIdx.x * TILE, gv);
+    for (bool first = true;; first = false) {
     if (threadIdx.x == 0) s_tile = atomicAdd(tile_ctr, 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
@@ -42,12 +83,9 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(Get get, Emit emit, Fi
         return;
     }
     const uint32_t tbase = tile * TILE;
+    if (!(first && guess && tile == blockIdx.x)) read_tile(tbase, gv);
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t e = (uint32_t)i * SCAN_BLOCK + threadIdx.x;
-        const uint32_t idx = tbase + e;
-        s_val[scan_lds_at(e)] = idx < n ? get(idx) : 0u;
-    }
+    for (int i = 0; i < ITEMS; ++i) s_val[scan_lds_at((uint32_t)i * SCAN_BLOCK + threadIdx.x)] = gv[i];
     __syncthreads();
     uint32_t v[ITEMS];
     uint32_t sum = 0;

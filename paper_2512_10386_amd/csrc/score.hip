@@ -881,6 +881,10 @@ struct PackedKeepGet {
         return k;
     }
 };
+template <>
+struct ScanGetWrites<PackedKeepGet> {
+    static constexpr bool value = true;
+};
 struct KeepEmit {
     uint32_t* kept_idx;
     __device__ void operator()(uint32_t i, uint32_t ex, uint32_t f) const {
