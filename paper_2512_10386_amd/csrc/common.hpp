@@ -252,6 +252,25 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 // Block exclusive scan of one value per thread (blockDim multiple of 64, <= 1024).
 // `smem` needs blockDim/64 + 1 words. Returns the exclusive prefix; *total gets
 // the block sum. Contains __syncthreads.
+// Workgroups are dealt to the chip's eight XCDs in turn (workgroup b runs on
+// XCD b % 8). xcd_part gives the workgroups of one XCD one contiguous eighth
+// of [0, n) to stride through: a kernel over sorted positions that gathers
+// from, or scatters to, input order then touches only the lines of its own
+// part's few frames, which stay in its XCD's L2 instead of being fetched by
+// all eight. The grid must hold a whole number of workgroups per XCD
+// (xcd_grid).
+constexpr unsigned N_XCD = 8;
+struct XcdPart {
+    uint32_t first, end, step;
+};
+__device__ __forceinline__ XcdPart xcd_part(uint32_t n) {
+    const uint32_t per = (n + N_XCD - 1u) / N_XCD;
+    const uint32_t lo = min(n, (blockIdx.x % N_XCD) * per);
+    return XcdPart{lo + (blockIdx.x / N_XCD) * blockDim.x + threadIdx.x, min(n, lo + per),
+                   (gridDim.x / N_XCD) * blockDim.x};
+}
+inline unsigned xcd_grid(unsigned blocks) { return (blocks + N_XCD - 1u) / N_XCD * N_XCD; }
+
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* smem, uint32_t* total) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     uint32_t inc = wave_incl_scan(v);

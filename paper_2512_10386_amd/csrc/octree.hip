@@ -87,7 +87,8 @@ __device__ __forceinline__ int leaf_level_of(const Plan& P, uint32_t s, uint32_t
 // The boundary tests run one thread per position (each is a chain of
 // dependent loads); the scan then only reads the flags. The same pass
 // gathers the points' coordinates into sorted order (pos4: x, y, z and the
-// original index's bits).
+// original index's bits); each XCD takes one eighth of the positions, so a
+// frame's coordinates are fetched into one XCD's L2.
 __global__ __launch_bounds__(256) void boundary_flag_kernel(Plan P, uint32_t cap, const float* __restrict__ xyz) {
     // batches of fewer than SORT_FOFF_LDS frames search the offsets in LDS
     __shared__ uint32_t s_foff[SORT_FOFF_LDS];
@@ -96,7 +97,8 @@ __global__ __launch_bounds__(256) void boundary_flag_kernel(Plan P, uint32_t cap
         for (uint32_t i = threadIdx.x; i <= P.nf; i += blockDim.x) s_foff[i] = P.foff[i];
         __syncthreads();
     }
-    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < P.n; j += gridDim.x * blockDim.x) {
+    const XcdPart R = xcd_part(P.n);
+    for (uint32_t j = R.first; j < R.end; j += R.step) {
         const uint32_t i = P.idx_a[j];
         P.pos4[j] = make_float4(xyz[3 * (size_t)i], xyz[3 * (size_t)i + 1], xyz[3 * (size_t)i + 2], __uint_as_float(i));
         uint32_t f, fs, fe;
@@ -121,7 +123,8 @@ struct FlagGet {
 void launch_leaves(const Plan& P, const Params& prm, const float* xyz, hipStream_t st) {
     unsigned blocks = (P.n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(boundary_flag_kernel, dim3(blocks), dim3(256), 0, st, P, (uint32_t)prm.leaf_cap, xyz);
+    hipLaunchKernelGGL(boundary_flag_kernel, dim3(xcd_grid(blocks)), dim3(256), 0, st, P, (uint32_t)prm.leaf_cap,
+                       xyz);
     BoundaryEmit e{P.leaf_of, P.leaf_begin};
     BoundaryFin f{P.ctr, P.leaf_begin, P.n};
     launch_scan(FlagGet{P.bflag}, e, f, nullptr, P.n, P.scan_status, &P.ctr->scan_tile_ctr[0], &P.ctr->status, st);

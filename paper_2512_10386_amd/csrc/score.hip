@@ -854,8 +854,11 @@ struct KeepGet {
 // from the records as it loads them (coalesced).
 constexpr uint32_t PACKED_OUT_MIN_N = 1u << 20;
 
+// (each XCD takes one eighth of the positions, so the lines of a frame's
+// records are written whole in one XCD's L2)
 __global__ __launch_bounds__(256) void outputs_pack_kernel(Plan P) {
-    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < P.n; s += gridDim.x * blockDim.x) {
+    const XcdPart R = xcd_part(P.n);
+    for (uint32_t s = R.first; s < R.end; s += R.step) {
         uint32_t st = 0;
         float sc = -1.0f;
         if (P.p1[s]) {
@@ -936,7 +939,7 @@ void launch_outputs(const Plan& P, uint8_t* keep, float* score, uint8_t* stage, 
     uint32_t* const sstat = P.scan_status + 2 * (size_t)P.scan_tiles;
     uint32_t* const sctr = &P.ctr->scan_tile_ctr[2];
     if (P.n > PACKED_OUT_MIN_N) {
-        hipLaunchKernelGGL(outputs_pack_kernel, dim3(blocks), dim3(256), 0, st, P);
+        hipLaunchKernelGGL(outputs_pack_kernel, dim3(xcd_grid(blocks)), dim3(256), 0, st, P);
         const PackedKeepGet get{P.outrec, keep, score, stage};
         if (P.nf == 1)
             launch_scan(get, KeepEmit{kept_idx}, KeepFin{P.ctr, n_kept}, nullptr, P.n, sstat, sctr, &P.ctr->status, st);
