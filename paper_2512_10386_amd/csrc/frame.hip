@@ -106,6 +106,39 @@ __device__ __forceinline__ void bbox_reduce_wave(float* mn, float* mx, uint32_t&
     }
 }
 
+// Adds the points [lo, hi) to a lane's box (non-finite points are counted
+// in `bad` instead), lane l taking points lo + l, lo + l + 64, ... in that
+// order; BBOX_U loads per lane are issued before any is used (a lane past hi
+// reads the last point and drops it). With fid, also records frame f of each
+// point.
+constexpr int BBOX_U = 8;
+__device__ __forceinline__ void bbox_add_range(const float* __restrict__ xyz, uint32_t lo, uint32_t hi,
+                                               uint32_t lane, float* mn, float* mx, uint32_t& bad, uint32_t* fid,
+                                               uint32_t f) {
+    for (uint32_t i0 = lo + lane; i0 < hi; i0 += 64u * BBOX_U) {
+        float x[BBOX_U], y[BBOX_U], z[BBOX_U];
+#pragma unroll
+        for (int u = 0; u < BBOX_U; ++u) {
+            const size_t j = min(i0 + 64u * (uint32_t)u, hi - 1u);
+            x[u] = xyz[3 * j];
+            y[u] = xyz[3 * j + 1];
+            z[u] = xyz[3 * j + 2];
+        }
+#pragma unroll
+        for (int u = 0; u < BBOX_U; ++u) {
+            const uint32_t i = i0 + 64u * (uint32_t)u;
+            const bool in = i < hi;
+            const bool fin = isfinite(x[u]) && isfinite(y[u]) && isfinite(z[u]);
+            const bool ok = in && fin;
+            mn[0] = fminf(mn[0], ok ? x[u] : INFINITY); mx[0] = fmaxf(mx[0], ok ? x[u] : -INFINITY);
+            mn[1] = fminf(mn[1], ok ? y[u] : INFINITY); mx[1] = fmaxf(mx[1], ok ? y[u] : -INFINITY);
+            mn[2] = fminf(mn[2], ok ? z[u] : INFINITY); mx[2] = fmaxf(mx[2], ok ? z[u] : -INFINITY);
+            bad += (in && !fin) ? 1u : 0u;
+            if (fid && in) fid[i] = f;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void bbox_kernel(const float* __restrict__ xyz, Plan P, bool direct,
                                                    uint32_t chunk) {
     __shared__ uint32_t s_foff[MAX_FRAMES + 1];
@@ -126,17 +159,7 @@ __global__ __launch_bounds__(256) void bbox_kernel(const float* __restrict__ xyz
             const uint32_t hi = f == f1 ? end : min(end, s_foff[f + 1]);
             float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
             uint32_t bad = 0;
-            for (uint32_t i = lo + lane; i < hi; i += 64u) {
-                const float x = xyz[3 * (size_t)i], y = xyz[3 * (size_t)i + 1], z = xyz[3 * (size_t)i + 2];
-                if (isfinite(x) && isfinite(y) && isfinite(z)) {
-                    mn[0] = fminf(mn[0], x); mx[0] = fmaxf(mx[0], x);
-                    mn[1] = fminf(mn[1], y); mx[1] = fmaxf(mx[1], y);
-                    mn[2] = fminf(mn[2], z); mx[2] = fmaxf(mx[2], z);
-                } else {
-                    ++bad;
-                }
-                if (nf > 1) P.fid[i] = f;
-            }
+            bbox_add_range(xyz, lo, hi, lane, mn, mx, bad, nf > 1 ? P.fid : nullptr, f);
             bbox_reduce_wave(mn, mx, bad);
             if (f0 == f1 && !direct) {
                 // whole chunk in one frame: ordered-uint max of -min / max, bad count
@@ -173,19 +196,8 @@ __global__ __launch_bounds__(256) void bbox_one_kernel(const float* __restrict__
     const uint32_t n = P.n, nchunks = (n + chunk - 1) / chunk;
     float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     uint32_t bad = 0;
-    for (uint32_t c = wid; c < nchunks; c += nw) {
-        const uint32_t end = min(n, (c + 1u) * chunk);
-        for (uint32_t i = c * chunk + lane; i < end; i += 64u) {
-            const float x = xyz[3 * (size_t)i], y = xyz[3 * (size_t)i + 1], z = xyz[3 * (size_t)i + 2];
-            if (isfinite(x) && isfinite(y) && isfinite(z)) {
-                mn[0] = fminf(mn[0], x); mx[0] = fmaxf(mx[0], x);
-                mn[1] = fminf(mn[1], y); mx[1] = fmaxf(mx[1], y);
-                mn[2] = fminf(mn[2], z); mx[2] = fmaxf(mx[2], z);
-            } else {
-                ++bad;
-            }
-        }
-    }
+    for (uint32_t c = wid; c < nchunks; c += nw)
+        bbox_add_range(xyz, c * chunk, min(n, (c + 1u) * chunk), lane, mn, mx, bad, nullptr, 0u);
     bbox_reduce_wave(mn, mx, bad);
     if (lane == 0u) {
         for (int a = 0; a < 3; ++a) {
@@ -308,6 +320,7 @@ __global__ __launch_bounds__(256) void frame_const_kernel(Plan P, double min_lea
 // Keys (quantised with the point's own frame constants), the identity
 // payload and the digit histograms of the sort: key digits 4..7, then the
 // frame id digits of a batch. A single frame computes its constants per block.
+constexpr uint32_t MORTON_U = 8;
 __global__ __launch_bounds__(256) void morton_kernel(const float* __restrict__ xyz, Plan P, double min_leaf_side) {
     __shared__ FrameConst s_fc;
     __shared__ uint32_t s_hist[SORT_PASSES_MAX][256];
@@ -318,18 +331,60 @@ __global__ __launch_bounds__(256) void morton_kernel(const float* __restrict__ x
         if (blockIdx.x == 0) *P.fc = s_fc;
     }
     __syncthreads();
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint32_t f = nf > 1 ? P.fid[i] : 0u;
-        const FrameConst& fc = nf > 1 ? P.fc[f] : s_fc;
-        const uint32_t qx = quantise(xyz[3 * (size_t)i], fc.lo[0], fc.scale);
-        const uint32_t qy = quantise(xyz[3 * (size_t)i + 1], fc.lo[1], fc.scale);
-        const uint32_t qz = quantise(xyz[3 * (size_t)i + 2], fc.lo[2], fc.scale);
-        const uint64_t key = morton3(qx, qy, qz);
-        P.keys_src[i] = key;
-        P.idx_src[i] = i;
+    // MORTON_U points per thread at a time, their loads (and a batch's frame
+    // constants) issued before any is used (a point past n reads the last
+    // one and is dropped)
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const float c0 = s_fc.lo[0], c1 = s_fc.lo[1], c2 = s_fc.lo[2];
+    const double csc = s_fc.scale;
+    for (uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += MORTON_U * stride) {
+        float x[MORTON_U], y[MORTON_U], z[MORTON_U];
+        uint32_t f[MORTON_U];
 #pragma unroll
-        for (int p = SORT_SHORT_FIRST; p < SORT_PASSES; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
-        for (uint32_t p = SORT_PASSES; p < nh; ++p) atomicAdd(&s_hist[p][(f >> (8 * (p - SORT_PASSES))) & 255u], 1u);
+        for (int u = 0; u < MORTON_U; ++u) {
+            const uint32_t j = min(i0 + (uint32_t)u * stride, n - 1u);
+            x[u] = xyz[3 * (size_t)j];
+            y[u] = xyz[3 * (size_t)j + 1];
+            z[u] = xyz[3 * (size_t)j + 2];
+            f[u] = nf > 1 ? P.fid[j] : 0u;
+        }
+        float l0[MORTON_U], l1[MORTON_U], l2[MORTON_U];
+        double sc[MORTON_U];
+#pragma unroll
+        for (int u = 0; u < MORTON_U; ++u) {
+            if (nf > 1) {
+                const FrameConst& fc = P.fc[f[u]];
+                l0[u] = fc.lo[0];
+                l1[u] = fc.lo[1];
+                l2[u] = fc.lo[2];
+                sc[u] = fc.scale;
+            } else {
+                l0[u] = c0;
+                l1[u] = c1;
+                l2[u] = c2;
+                sc[u] = csc;
+            }
+        }
+        // (an empty statement taking the loaded values keeps the compiler from
+        // moving each load into the branch of its point)
+#pragma unroll
+        for (int u = 0; u < MORTON_U; ++u) asm volatile("" ::"v"(x[u]), "v"(y[u]), "v"(z[u]), "v"(f[u]));
+#pragma unroll
+        for (int u = 0; u < MORTON_U; ++u) {
+            const uint32_t i = i0 + (uint32_t)u * stride;
+            if (i >= n) break;
+            const uint32_t qx = quantise(x[u], l0[u], sc[u]);
+            const uint32_t qy = quantise(y[u], l1[u], sc[u]);
+            const uint32_t qz = quantise(z[u], l2[u], sc[u]);
+            const uint64_t key = morton3(qx, qy, qz);
+            P.keys_src[i] = key;
+            P.idx_src[i] = i;
+#pragma unroll
+            for (int p = SORT_SHORT_FIRST; p < SORT_PASSES; ++p)
+                atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
+            for (uint32_t p = SORT_PASSES; p < nh; ++p)
+                atomicAdd(&s_hist[p][(f[u] >> (8 * (p - SORT_PASSES))) & 255u], 1u);
+        }
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < nh * 256u; i += blockDim.x) {
