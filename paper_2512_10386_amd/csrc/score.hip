@@ -56,8 +56,23 @@ struct Dens {
     bool short_list;  // fewer than k candidates
 };
 
-__device__ __forceinline__ Dens density_at(const Plan& P, const float* __restrict__ xyz, uint32_t k, uint32_t qi) {
-    const uint4 kr = P.krec[qi];
+// What the density of a query starts from: its k-th neighbour record and the
+// coordinates of the query and of that neighbour (the query's again when it
+// has none), all loaded at once.
+struct DensIn {
+    uint4 kr;
+    float4 cq, cj;
+};
+__device__ __forceinline__ DensIn density_load(const Plan& P, uint32_t qi) {
+    DensIn d;
+    d.kr = P.krec[qi];
+    d.cq = P.cand4[qi];
+    d.cj = P.cand4[d.kr.x < P.n ? d.kr.x : qi];
+    return d;
+}
+
+__device__ __forceinline__ Dens density_finish(const Plan& P, uint32_t k, uint32_t qi, const DensIn& in) {
+    const uint4 kr = in.kr;
     const uint32_t jk = kr.x;
     Dens out;
     out.r2 = __uint_as_float(kr.z);
@@ -67,20 +82,19 @@ __device__ __forceinline__ Dens density_at(const Plan& P, const float* __restric
         out.r64 = INFINITY;
     } else {
         // the query's coordinates: cand4 holds bit copies of the input
-        const float4 cq = P.cand4[qi];
-        const double xi = cq.x, yi = cq.y, zi = cq.z;
-        // neighbour at P1 position j: its sorted copy of the input coordinates
-        auto d2_to = [&](uint32_t j) -> double {
-            const float4 cj = P.cand4[j];
+        const double xi = in.cq.x, yi = in.cq.y, zi = in.cq.z;
+        // a neighbour's sorted copy of the input coordinates
+        auto d2_of = [&](const float4 cj) -> double {
             const double dx = (double)cj.x - xi;
             const double dy = (double)cj.y - yi;
             const double dz = (double)cj.z - zi;
             return dx * dx + dy * dy + dz * dz;
         };
+        auto d2_to = [&](uint32_t j) -> double { return d2_of(P.cand4[j]); };
         const float thr = out.r2 * (1.0f - 1.0f / 65536.0f);
         double m2 = 0.0;
         if (k == 1u || __uint_as_float(kr.y) < thr) {
-            if (jk < P.n) m2 = fmax(m2, d2_to(jk));
+            if (jk < P.n) m2 = fmax(m2, d2_of(in.cj));
         } else {
             const uint32_t* nb = P.nbr + (size_t)qi * k;
             const float* d2 = P.nbr_d2 + (size_t)qi * k;
@@ -99,6 +113,11 @@ __device__ __forceinline__ Dens density_at(const Plan& P, const float* __restric
     P.rho_c[qi] = out.rho;
     P.r64_c[qi] = out.r64;
     return out;
+}
+
+__device__ __forceinline__ Dens density_at(const Plan& P, const float* __restrict__ xyz, uint32_t k, uint32_t qi) {
+    (void)xyz;
+    return density_finish(P, k, qi, density_load(P, qi));
 }
 
 // ---------------------------------------------------------------- block radix select
@@ -215,6 +234,7 @@ struct LdsBits {
 };
 
 constexpr uint32_t SEL_LDS_MAX = 2048;  // leaves up to this size are selected from LDS
+constexpr uint32_t SEL_BATCH_MAX = 1024;  // leaves up to this size: each thread loads its points at once
 constexpr uint32_t SMALL_LEAF = 256;    // leaves up to this size: one wave (4 values per lane), no LDS
 constexpr uint32_t SMALL_PATH_MIN_N = 1u << 20;  // the wave path is used above this many points
 
@@ -310,6 +330,70 @@ __global__ __launch_bounds__(SEL_BLOCK) void leaf_select_kernel(Plan P, Params p
         }
         float cut = 0.0f;
         double med = 0.0;
+        if (n1 <= SEL_BATCH_MAX) {
+            // point i = threadIdx.x + u * SEL_BLOCK of the leaf in slot u of
+            // each thread, every load of a pass issued first (a slot past n1
+            // loads the last point and is dropped)
+            constexpr int SU = SEL_BATCH_MAX / SEL_BLOCK;
+            {
+                DensIn din[SU];
+#pragma unroll
+                for (int u = 0; u < SU; ++u)
+                    din[u].kr = P.krec[qb + min(threadIdx.x + (uint32_t)u * SEL_BLOCK, n1 - 1u)];
+#pragma unroll
+                for (int u = 0; u < SU; ++u) {
+                    const uint32_t qi = qb + min(threadIdx.x + (uint32_t)u * SEL_BLOCK, n1 - 1u);
+                    din[u].cq = P.cand4[qi];
+                    din[u].cj = P.cand4[din[u].kr.x < P.n ? din[u].kr.x : qi];
+                }
+                // (an empty statement taking the loaded values keeps the compiler
+                // from moving each load into the branch of its slot)
+#pragma unroll
+                for (int u = 0; u < SU; ++u) asm volatile("" ::"v"(din[u].kr.x), "v"(din[u].cq.x), "v"(din[u].cj.x));
+#pragma unroll
+                for (int u = 0; u < SU; ++u) {
+                    const uint32_t i = threadIdx.x + (uint32_t)u * SEL_BLOCK;
+                    if (i >= n1) break;
+                    const Dens dn = density_finish(P, (uint32_t)k, qb + i, din[u]);
+                    if (role == 0u) s_r2[i] = __float_as_uint(dn.r2);
+                    else s_rho[i] = (unsigned long long)__double_as_longlong(dn.rho);
+                }
+            }
+            __syncthreads();
+            if (role == 0u) {
+                cut = leaf_cut(LdsBits<uint32_t>{s_r2}, n1, prm.rho_percentile, s_hist, s_sel);
+                uint32_t kx[SU];
+#pragma unroll
+                for (int u = 0; u < SU; ++u) kx[u] = P.krec[qb + min(threadIdx.x + (uint32_t)u * SEL_BLOCK, n1 - 1u)].x;
+#pragma unroll
+                for (int u = 0; u < SU; ++u) {
+                    const uint32_t i = threadIdx.x + (uint32_t)u * SEL_BLOCK;
+                    if (i >= n1) break;
+                    P.p2[qb + i] = (kx[u] != NO_NBR && __uint_as_float(s_r2[i]) <= cut) ? 1 : 0;
+                }
+                if (threadIdx.x == 0) P.leaf_r2cut[t] = cut;
+            } else {
+                leaf_median(LdsBits<unsigned long long>{s_rho}, n1, &med, s_hist, s_sel);
+                const double den = med * med + prm.eps;
+                const double ha = prm.alpha / 2.0;
+                double r64[SU];
+#pragma unroll
+                for (int u = 0; u < SU; ++u) r64[u] = P.r64_c[qb + min(threadIdx.x + (uint32_t)u * SEL_BLOCK, n1 - 1u)];
+#pragma unroll
+                for (int u = 0; u < SU; ++u) {
+                    const uint32_t i = threadIdx.x + (uint32_t)u * SEL_BLOCK;
+                    if (i >= n1) break;
+                    const double rho = __longlong_as_double((long long)s_rho[i]);
+                    const double sr = prm.sigma * r64[u];
+                    P.afac_c[qb + i] = make_double2(pow_ha<SQRT>(rho / den, ha), 1.0 / (2.0 * sr * sr));
+                    // rho_j^(alpha/2) of Eq. 17's factored density weight, by P1 position
+                    P.gpow_p[qb + i] = pow_ha<SQRT>(rho, ha);
+                }
+                if (threadIdx.x == 0) P.leaf_rho_med[t] = med;
+            }
+            __syncthreads();
+            continue;
+        }
         if (n1 <= SEL_LDS_MAX) {
             for (uint32_t i = threadIdx.x; i < n1; i += blockDim.x) {
                 const Dens dn = density_at(P, xyz, (uint32_t)k, qb + i);
@@ -592,16 +676,18 @@ void launch_score(const Plan& P, const Params& prm, hipStream_t st) {
 // original index asc); a NaN score ranks below every number. The m-th largest
 // score key is found by radix select, remaining ties by a select on indices.
 
+__device__ __forceinline__ unsigned long long score_key(bool p2, double f) {
+    if (!p2) return 0ull;
+    if (isnan(f)) return 1ull;
+    return (unsigned long long)__double_as_longlong(f) + 2ull;
+}
 struct ScoreKey {
     const double* score;
     const uint8_t* p2;
     uint32_t qb;
     __device__ unsigned long long operator()(uint32_t i) const {
         const uint32_t qi = qb + i;
-        if (!p2[qi]) return 0ull;
-        const double f = score[qi];
-        if (isnan(f)) return 1ull;
-        return (unsigned long long)__double_as_longlong(f) + 2ull;
+        return p2[qi] ? score_key(true, score[qi]) : 0ull;
     }
 };
 
@@ -658,6 +744,69 @@ __global__ __launch_bounds__(SEL_BLOCK) void topl_kernel(Plan P, double lambda, 
         const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
         const uint32_t n1 = qe - qb;
         if (small && n1 <= SMALL_LEAF) continue;  // topl_small_kernel
+        if (n1 <= SEL_BATCH_MAX) {
+            // point i = threadIdx.x + u * SEL_BLOCK of the leaf in slot u of
+            // each thread: every load first (a slot past n1 loads the last
+            // point and is dropped), keys and indices staged in LDS and kept
+            // in registers for the stage codes, |P2| counted on the way
+            constexpr int SU = SEL_BATCH_MAX / SEL_BLOCK;
+            uint32_t p2v[SU], ix[SU];
+            double sv[SU];
+            if (threadIdx.x == 0) s_cnt = 0;
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const uint32_t qi = qb + min(threadIdx.x + (uint32_t)u * SEL_BLOCK, n1 - 1u);
+                p2v[u] = P.p2[qi];
+                sv[u] = P.score_c[qi];
+                ix[u] = __float_as_uint(P.cand4[qi].w);
+            }
+            // (an empty statement taking the loaded values keeps the compiler
+            // from moving each load into the branch of its slot)
+#pragma unroll
+            for (int u = 0; u < SU; ++u) asm volatile("" ::"v"(p2v[u]), "v"(sv[u]), "v"(ix[u]));
+            unsigned long long kv[SU];
+            uint32_t c = 0;
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const uint32_t i = threadIdx.x + (uint32_t)u * SEL_BLOCK;
+                kv[u] = score_key(p2v[u] != 0u, sv[u]);
+                if (i < n1) {
+                    s_key[i] = kv[u];
+                    s_idx[i] = ix[u];
+                    c += p2v[u] != 0u ? 1u : 0u;
+                }
+            }
+            c = wave_sum(c);
+            __syncthreads();  // s_cnt cleared
+            if ((threadIdx.x & 63) == 0 && c) atomicAdd(&s_cnt, c);
+            __syncthreads();
+            const uint32_t n2 = s_cnt;
+            uint32_t m = 0;
+            if (n2 > 0) {
+                const double mf = ceil(lambda * (double)n2);
+                m = mf >= (double)n2 ? n2 : (uint32_t)mf;
+            }
+            unsigned long long theta = ~0ull;
+            uint32_t idx_cut = 0;
+            if (m > 0)
+                topl_cut(LdsBits<unsigned long long>{s_key}, LdsBits<uint32_t>{s_idx}, n1, m, &theta, &idx_cut,
+                         s_hist, s_sel, &s_cnt);
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const uint32_t i = threadIdx.x + (uint32_t)u * SEL_BLOCK;
+                if (i >= n1) break;
+                uint8_t st = 1;
+                if (p2v[u]) {
+                    const bool kept = m > 0 && (kv[u] > theta || (kv[u] == theta && ix[u] <= idx_cut));
+                    st = kept ? 3 : 2;
+                }
+                P.stage_c[qb + i] = st;
+            }
+            if (threadIdx.x == 0) P.leaf_m[t] = m;
+            __syncthreads();
+            continue;
+        }
+        // larger leaves
         if (threadIdx.x == 0) s_cnt = 0;
         __syncthreads();
         uint32_t c = 0;
