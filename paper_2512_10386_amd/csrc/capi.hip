@@ -388,13 +388,14 @@ static gdn_status run(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int64
     if (ce) (void)hipEventRecord(ce->ev[2], st);
     gdn::launch_knn_merge(P, prm.k, ctx->num_cus, st);
     gdn::launch_leaf_select(P, prm, xyz, st);
+    bool written = false;  // outputs already written by the top-lambda pass
     if (prm.stages & GDN_STAGE_SCORE) {
         gdn::launch_score(P, prm, st);
-        gdn::launch_topl(P, prm, st);
+        written = gdn::launch_topl(P, prm, keep, score, stage, st);
     } else {
         gdn::launch_keep_p2(P, st);
     }
-    gdn::launch_outputs(P, keep, score, stage, kept_idx, n_kept, st);
+    gdn::launch_outputs(P, keep, score, stage, kept_idx, n_kept, st, written);
     if (ce) (void)hipEventRecord(ce->ev[3], st);
 
     hipError_t e = hipGetLastError();

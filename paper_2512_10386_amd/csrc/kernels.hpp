@@ -31,10 +31,12 @@ void launch_knn_merge(const Plan& P, int k, int num_cus, hipStream_t st);
 // score.hip: density with percentile/median, score, top-lambda, outputs
 void launch_leaf_select(const Plan& P, const Params& prm, const float* xyz, hipStream_t st);
 void launch_score(const Plan& P, const Params& prm, hipStream_t st);
-void launch_topl(const Plan& P, const Params& prm, hipStream_t st);
+// Returns true when top-lambda also wrote keep, score and stage (single
+// frames); launch_outputs then only builds the kept list.
+bool launch_topl(const Plan& P, const Params& prm, uint8_t* keep, float* score, uint8_t* stage, hipStream_t st);
 void launch_keep_p2(const Plan& P, hipStream_t st);
 void launch_outputs(const Plan& P, uint8_t* keep, float* score, uint8_t* stage,
-                    uint32_t* kept_idx, int64_t* n_kept, hipStream_t st);
+                    uint32_t* kept_idx, int64_t* n_kept, hipStream_t st, bool written = false);
 void launch_write_zero_count(int64_t* n_kept, uint32_t nf, hipStream_t st);
 
 // fit.hip: score-fit loss and gradient over the last pass's intermediates

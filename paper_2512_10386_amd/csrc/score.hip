@@ -237,6 +237,7 @@ constexpr uint32_t SEL_LDS_MAX = 2048;  // leaves up to this size are selected f
 constexpr uint32_t SEL_BATCH_MAX = 1024;  // leaves up to this size: each thread loads its points at once
 constexpr uint32_t SMALL_LEAF = 256;    // leaves up to this size: one wave (4 values per lane), no LDS
 constexpr uint32_t SMALL_PATH_MIN_N = 1u << 20;  // the wave path is used above this many points
+constexpr uint32_t PACKED_OUT_MIN_N = 1u << 20;  // above: outputs scattered as packed records
 
 struct R2Bits {
     const float* r2k;
@@ -728,7 +729,21 @@ struct CandIdx {
     __device__ uint32_t operator()(uint32_t i) const { return __float_as_uint(cand4[qb + i].w); }
 };
 
-__global__ __launch_bounds__(SEL_BLOCK) void topl_kernel(Plan P, double lambda, bool small) {
+// Optional outputs (single frames, every leaf handled here): keep, score and
+// stage in input order for every point of each leaf, as outputs_kernel
+// writes them, so that pass is not needed.
+struct ToplOut {
+    uint8_t* keep;
+    float* score;
+    uint8_t* stage;
+    __device__ void put(uint32_t i, uint8_t st, double sc) const {
+        keep[i] = st == 3;
+        score[i] = st >= 2 ? (float)sc : -1.0f;
+        if (stage) stage[i] = st;
+    }
+};
+
+__global__ __launch_bounds__(SEL_BLOCK) void topl_kernel(Plan P, double lambda, bool small, ToplOut out) {
     __shared__ uint32_t s_hist[256];
     __shared__ uint32_t s_sel[SEL_SCRATCH];
     __shared__ uint32_t s_cnt;
@@ -741,9 +756,40 @@ __global__ __launch_bounds__(SEL_BLOCK) void topl_kernel(Plan P, double lambda, 
     const uint32_t nlist = block_leaf_round(P, base, nl, small, s_list, s_lscan, gridDim.x);
     for (uint32_t li = 0; li < nlist; ++li) {
         const uint32_t t = s_list[li];
-        const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
+        const uint32_t lb = P.leaf_begin[t], le = P.leaf_begin[t + 1];
+        const uint32_t qb = P.p1pos[lb], qe = P.p1pos[le];
         const uint32_t n1 = qe - qb;
         if (small && n1 <= SMALL_LEAF) continue;  // topl_small_kernel
+        // outputs of the leaf's points outside P1 (stage 0): for leaves of up to
+        // 4 * SEL_BLOCK points their flags and indices are read here, beside
+        // the P1 reads below, and written once those are in
+        constexpr int NU = 4;
+        const uint32_t nt = le - lb;
+        const bool outs_b = out.keep && nt <= (uint32_t)NU * SEL_BLOCK;
+        uint32_t f1[NU], oi[NU];
+        if (outs_b) {
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const uint32_t s = lb + min(threadIdx.x + (uint32_t)u * SEL_BLOCK, nt - 1u);
+                f1[u] = P.p1[s];
+                oi[u] = P.idx_a[s];
+            }
+        }
+        auto put_outside_p1 = [&]() {
+            if (outs_b) {
+#pragma unroll
+                for (int u = 0; u < NU; ++u)
+                    if (threadIdx.x + (uint32_t)u * SEL_BLOCK < nt && !f1[u]) out.put(oi[u], 0, 0.0);
+            } else if (out.keep) {
+                for (uint32_t s = lb + threadIdx.x; s < le; s += SEL_BLOCK)
+                    if (!P.p1[s]) out.put(P.idx_a[s], 0, 0.0);
+            }
+        };
+        if (n1 == 0) {
+            put_outside_p1();
+            if (threadIdx.x == 0) P.leaf_m[t] = 0;
+            continue;
+        }
         if (n1 <= SEL_BATCH_MAX) {
             // point i = threadIdx.x + u * SEL_BLOCK of the leaf in slot u of
             // each thread: every load first (a slot past n1 loads the last
@@ -764,6 +810,7 @@ __global__ __launch_bounds__(SEL_BLOCK) void topl_kernel(Plan P, double lambda, 
             // from moving each load into the branch of its slot)
 #pragma unroll
             for (int u = 0; u < SU; ++u) asm volatile("" ::"v"(p2v[u]), "v"(sv[u]), "v"(ix[u]));
+            put_outside_p1();
             unsigned long long kv[SU];
             uint32_t c = 0;
 #pragma unroll
@@ -801,12 +848,14 @@ __global__ __launch_bounds__(SEL_BLOCK) void topl_kernel(Plan P, double lambda, 
                     st = kept ? 3 : 2;
                 }
                 P.stage_c[qb + i] = st;
+                if (out.keep) out.put(ix[u], st, sv[u]);
             }
             if (threadIdx.x == 0) P.leaf_m[t] = m;
             __syncthreads();
             continue;
         }
         // larger leaves
+        put_outside_p1();
         if (threadIdx.x == 0) s_cnt = 0;
         __syncthreads();
         uint32_t c = 0;
@@ -846,6 +895,7 @@ __global__ __launch_bounds__(SEL_BLOCK) void topl_kernel(Plan P, double lambda, 
                 st = kept ? 3 : 2;
             }
             P.stage_c[qi] = st;
+            if (out.keep) out.put(__float_as_uint(P.cand4[qi].w), st, st >= 2 ? P.score_c[qi] : 0.0);
         }
         if (threadIdx.x == 0) P.leaf_m[t] = m;
         __syncthreads();
@@ -954,13 +1004,13 @@ void launch_keep_p2(const Plan& P, hipStream_t st) {
     hipLaunchKernelGGL(keep_p2_kernel, dim3(blocks), dim3(256), 0, st, P);
 }
 
-void launch_topl(const Plan& P, const Params& prm, hipStream_t st) {
+bool launch_topl(const Plan& P, const Params& prm, uint8_t* keep, float* score, uint8_t* stage, hipStream_t st) {
     if (!std::isnan(prm.log_thr)) {
         unsigned blocks = (P.n + 255) / 256;
         if (blocks > 4096) blocks = 4096;
         if (blocks == 0) blocks = 1;
         hipLaunchKernelGGL(threshold_kernel, dim3(blocks), dim3(256), 0, st, P, prm.log_thr);
-        return;
+        return false;
     }
     const bool small = P.n > SMALL_PATH_MIN_N;
     if (small) {
@@ -970,7 +1020,12 @@ void launch_topl(const Plan& P, const Params& prm, hipStream_t st) {
     }
     unsigned blocks = P.n < 2048 ? P.n : 2048;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(topl_kernel, dim3(blocks), dim3(SEL_BLOCK), 0, st, P, prm.keep_ratio, small);
+    // up to 2^20 points every leaf passes through topl_kernel, which then
+    // writes the outputs too (large inputs scatter them as packed records)
+    const bool write = !small && P.n <= PACKED_OUT_MIN_N;
+    const ToplOut out{write ? keep : nullptr, score, stage};
+    hipLaunchKernelGGL(topl_kernel, dim3(blocks), dim3(SEL_BLOCK), 0, st, P, prm.keep_ratio, small, out);
+    return write;
 }
 
 // ---------------------------------------------------------------- outputs
@@ -1000,11 +1055,9 @@ struct KeepGet {
 // scatters one 8-byte record per point to its original index (one random
 // line per point instead of one per output array), and the keep scan, which
 // reads every point in input order anyway, writes the three output arrays
-// from the records as it loads them (coalesced).
-constexpr uint32_t PACKED_OUT_MIN_N = 1u << 20;
-
-// (each XCD takes one eighth of the positions, so the lines of a frame's
-// records are written whole in one XCD's L2)
+// from the records as it loads them (coalesced). Each XCD takes one eighth of
+// the positions, so the lines of a frame's records are written whole in one
+// XCD's L2.
 __global__ __launch_bounds__(256) void outputs_pack_kernel(Plan P) {
     const XcdPart R = xcd_part(P.n);
     for (uint32_t s = R.first; s < R.end; s += R.step) {
@@ -1082,7 +1135,7 @@ __global__ __launch_bounds__(256) void kept_frames_kernel(Plan P, const uint8_t*
 }
 
 void launch_outputs(const Plan& P, uint8_t* keep, float* score, uint8_t* stage, uint32_t* kept_idx,
-                    int64_t* n_kept, hipStream_t st) {
+                    int64_t* n_kept, hipStream_t st, bool written) {
     unsigned blocks = (P.n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     uint32_t* const sstat = P.scan_status + 2 * (size_t)P.scan_tiles;
@@ -1096,7 +1149,7 @@ void launch_outputs(const Plan& P, uint8_t* keep, float* score, uint8_t* stage, 
             launch_scan(get, BatchKeepEmit{P.keep_ex}, BatchKeepFin{P.ctr, P.keep_ex, P.n}, nullptr, P.n, sstat, sctr,
                         &P.ctr->status, st);
     } else {
-        hipLaunchKernelGGL(outputs_kernel, dim3(blocks), dim3(256), 0, st, P, keep, score, stage);
+        if (!written) hipLaunchKernelGGL(outputs_kernel, dim3(blocks), dim3(256), 0, st, P, keep, score, stage);
         if (P.nf == 1)
             launch_scan(KeepGet{keep}, KeepEmit{kept_idx}, KeepFin{P.ctr, n_kept}, nullptr, P.n, sstat, sctr,
                         &P.ctr->status, st);
