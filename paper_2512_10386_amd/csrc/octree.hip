@@ -394,13 +394,17 @@ struct P1Emit {
     float4* cand4;
     uint32_t* cand_leaf;
     uint32_t* inv_p1;
-    __device__ void operator()(uint32_t s, uint32_t ex, uint32_t f) const {
+    struct Pre {
+        float4 c;
+        uint32_t leaf;
+    };
+    __device__ Pre pre(uint32_t s) const { return Pre{pos4[s], leaf_of[s]}; }
+    __device__ void operator()(uint32_t s, uint32_t ex, uint32_t f, const Pre& r) const {
         p1pos[s] = ex;
         if (f) {
-            const float4 c = pos4[s];
-            cand4[ex] = c;
-            cand_leaf[ex] = leaf_of[s];
-            inv_p1[__float_as_uint(c.w)] = ex;
+            cand4[ex] = r.c;
+            cand_leaf[ex] = r.leaf;
+            inv_p1[__float_as_uint(r.c.w)] = ex;
         }
     }
 };

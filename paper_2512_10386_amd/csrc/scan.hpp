@@ -8,6 +8,8 @@
 // launch can hang. The status words must be zero before the launch.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace gdn {
@@ -27,6 +29,19 @@ __device__ __forceinline__ uint32_t scan_lds_at(uint32_t e) { return e + (e >> 5
 template <class Get>
 struct ScanGetWrites {
     static constexpr bool value = false;
+};
+
+// An emitter may split off its reads: with a member type Pre, pre(i) reads
+// what emitting element i needs and operator()(i, ex, v, pre) writes, so
+// the scan makes all of a thread's reads before any of its writes (which
+// would otherwise keep the next element's reads waiting).
+template <class Emit, class = void>
+struct ScanEmitPre {
+    static constexpr bool value = false;
+};
+template <class Emit>
+struct ScanEmitPre<Emit, std::void_t<typename Emit::Pre>> {
+    static constexpr bool value = true;
 };
 
 template <int ITEMS, class Get, class Emit, class Fin>
@@ -146,11 +161,27 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(Get get, Emit emit, Fi
         run += v[i];
     }
     __syncthreads();
+    if constexpr (ScanEmitPre<Emit>::value) {
+        // (an element past n reads element n - 1 and is dropped)
+        typename Emit::Pre pre[ITEMS];
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t e = (uint32_t)i * SCAN_BLOCK + threadIdx.x;
-        const uint32_t idx = tbase + e;
-        if (idx < n) emit(idx, s_pre[scan_lds_at(e)], s_val[scan_lds_at(e)]);
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t idx = tbase + (uint32_t)i * SCAN_BLOCK + threadIdx.x;
+            pre[i] = emit.pre(idx < n ? idx : n - 1u);
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t e = (uint32_t)i * SCAN_BLOCK + threadIdx.x;
+            const uint32_t idx = tbase + e;
+            if (idx < n) emit(idx, s_pre[scan_lds_at(e)], s_val[scan_lds_at(e)], pre[i]);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t e = (uint32_t)i * SCAN_BLOCK + threadIdx.x;
+            const uint32_t idx = tbase + e;
+            if (idx < n) emit(idx, s_pre[scan_lds_at(e)], s_val[scan_lds_at(e)]);
+        }
     }
     if (tile == ntiles - 1 && threadIdx.x == 0) fin(s_excl + agg);
     __syncthreads();  // s_tile, s_excl and the LDS tile are reused by the next tile
