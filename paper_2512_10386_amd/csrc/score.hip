@@ -498,6 +498,22 @@ __global__ __launch_bounds__(256) void leaf_select_small_kernel(Plan P, Params p
         WaveVals r2v, rhov;
         double r64v[4];
         bool shortv[4];
+        // every load of the four points first (a slot past n1 loads the last
+        // point and is dropped): the stores of one point's density would
+        // otherwise hold the next point's loads back
+        DensIn din[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) din[j].kr = P.krec[qb + min((uint32_t)j * 64u + lane, n1 - 1u)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t qi = qb + min((uint32_t)j * 64u + lane, n1 - 1u);
+            din[j].cq = P.cand4[qi];
+            din[j].cj = P.cand4[din[j].kr.x < P.n ? din[j].kr.x : qi];
+        }
+        // (an empty statement taking the loaded values keeps the compiler from
+        // moving each load into the branch of its slot)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) asm volatile("" ::"v"(din[j].kr.x), "v"(din[j].cq.x), "v"(din[j].cj.x));
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t i = (uint32_t)j * 64u + lane;
@@ -506,7 +522,7 @@ __global__ __launch_bounds__(256) void leaf_select_small_kernel(Plan P, Params p
             r64v[j] = 0.0;
             shortv[j] = true;
             if (i < n1) {
-                const Dens dn = density_at(P, xyz, (uint32_t)k, qb + i);
+                const Dens dn = density_finish(P, (uint32_t)k, qb + i, din[j]);
                 r2v.v[j] = (unsigned long long)__float_as_uint(dn.r2);
                 rhov.v[j] = (unsigned long long)__double_as_longlong(dn.rho);
                 r64v[j] = dn.r64;
@@ -916,17 +932,33 @@ __global__ __launch_bounds__(256) void topl_small_kernel(Plan P, double lambda) 
         const uint32_t qb = P.p1pos[P.leaf_begin[t]], qe = P.p1pos[P.leaf_begin[t + 1]];
         const uint32_t n1 = qe - qb;
         if (n1 > SMALL_LEAF) continue;
-        const ScoreKey sk{P.score_c, P.p2, qb};
         WaveVals kv;
         uint32_t oi[4];
         uint32_t n2 = 0;
+        // flags, scores and indices of the four points read at once (a slot
+        // past n1 reads the last point and is dropped; an empty leaf reads none)
+        uint32_t p2v[4] = {0u, 0u, 0u, 0u}, ixv[4] = {0u, 0u, 0u, 0u};
+        double sv[4] = {0.0, 0.0, 0.0, 0.0};
+        if (n1 > 0) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t qi = qb + min((uint32_t)j * 64u + lane, n1 - 1u);
+                p2v[j] = P.p2[qi];
+                sv[j] = P.score_c[qi];
+                ixv[j] = __float_as_uint(P.cand4[qi].w);
+            }
+            // (an empty statement taking the loaded values keeps the compiler
+            // from moving each load into the branch of its slot)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) asm volatile("" ::"v"(p2v[j]), "v"(sv[j]), "v"(ixv[j]));
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t i = (uint32_t)j * 64u + lane;
             const bool in = i < n1;
-            kv.v[j] = in ? sk(i) : 0ull;
-            oi[j] = in ? __float_as_uint(P.cand4[qb + i].w) : 0xFFFFFFFFu;
-            n2 += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in && P.p2[qb + i]));
+            kv.v[j] = in ? score_key(p2v[j] != 0u, sv[j]) : 0ull;
+            oi[j] = in ? ixv[j] : 0xFFFFFFFFu;
+            n2 += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in && p2v[j] != 0u));
         }
         uint32_t m = 0;
         if (n2 > 0) {
@@ -975,7 +1007,7 @@ __global__ __launch_bounds__(256) void topl_small_kernel(Plan P, double lambda) 
         for (int j = 0; j < 4; ++j) {
             const uint32_t i = (uint32_t)j * 64u + lane;
             const bool kept = m > 0 && (kv.v[j] > theta || (kv.v[j] == theta && (!ties_cut || below[j] < need)));
-            if (i < n1) P.stage_c[qb + i] = P.p2[qb + i] ? (kept ? 3 : 2) : 1;
+            if (i < n1) P.stage_c[qb + i] = p2v[j] ? (kept ? 3 : 2) : 1;
         }
         if (lane == 0) P.leaf_m[t] = m;
     }
