@@ -70,8 +70,6 @@ struct Counters {
     uint32_t n_p1;
     uint32_t n_items;
     uint32_t n_kept;
-    uint32_t sort_tile_ctr[SORT_PASSES_MAX];
-    uint32_t scan_tile_ctr[SCAN_SLOTS];
     unsigned long long pairs;
     uint32_t n_chunked_items; // kNN items of chunked leaves (they come first)
     uint32_t plan_cc;         // chosen kNN chunk length (parallel plan)

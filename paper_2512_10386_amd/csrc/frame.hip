@@ -415,10 +415,9 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
                                                                 uint64_t* __restrict__ kout,
                                                                 uint32_t* __restrict__ vout, uint32_t n,
                                                                 int pass, const uint32_t* __restrict__ hist,
-                                                                uint32_t* status, uint32_t* tile_ctr,
-                                                                uint32_t* dev_status, const uint32_t* __restrict__ foff,
+                                                                uint32_t* status, uint32_t* dev_status,
+                                                                const uint32_t* __restrict__ foff,
                                                                 uint32_t nf) {
-    __shared__ uint32_t s_tile;
     __shared__ uint32_t s_w[SORT_BLOCK / 64][256];
     __shared__ uint32_t s_base[256];
     __shared__ uint32_t s_scan[SORT_BLOCK / 64 + 1];
@@ -445,15 +444,15 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(const uint64_t* 
             val[i] = ok ? vin[pos] : 0u;
         }
     };
-    // The tile order of the look-back is the order of the tile counter; the
-    // workgroups normally take it in launch order, so the tile of this
-    // workgroup's index is loaded while the counter is read, and loaded again
-    // only if the counter gave another one.
+    // Tile = workgroup index. Each XCD starts its workgroups in index order,
+    // so every tile a look-back waits on has been started and only waits on
+    // lower tiles in turn; the waits are bounded anyway (SPIN_LIMIT, then a
+    // status bit). A tile counter taken with an atomic cost a round trip
+    // before the loads, and on large inputs, where the workgroups that start
+    // together race for it, a second load of the tile.
     load_tile(blockIdx.x);
-    if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
     __syncthreads();
-    const uint32_t tile = s_tile;
-    if (tile != blockIdx.x) load_tile(tile);
+    const uint32_t tile = blockIdx.x;
     const uint32_t tbase = tile * (SORT_BLOCK * ITEMS) + wave * (64 * ITEMS);
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
@@ -780,8 +779,8 @@ void launch_sort(const Plan& P, const Params& prm, hipStream_t st) {
         auto kern = P.sort_items == 4 ? radix_pass_kernel<4> : radix_pass_kernel<16>;
         hipLaunchKernelGGL(kern, dim3(P.sort_tiles), dim3(SORT_BLOCK), 0, st, kin, vin, kout, vout,
                            P.n, (int)pass, P.sort_hist + 256 * pass,
-                           P.sort_status + (size_t)pass * P.sort_tiles * 256, &P.ctr->sort_tile_ctr[pass],
-                           &P.ctr->status, (const uint32_t*)P.foff, P.nf);
+                           P.sort_status + (size_t)pass * P.sort_tiles * 256, &P.ctr->status,
+                           (const uint32_t*)P.foff, P.nf);
         const uint64_t* tk = kout;
         const uint32_t* tv = vout;
         kout = (uint64_t*)kin;

@@ -127,7 +127,7 @@ void launch_leaves(const Plan& P, const Params& prm, const float* xyz, hipStream
                        xyz);
     BoundaryEmit e{P.leaf_of, P.leaf_begin};
     BoundaryFin f{P.ctr, P.leaf_begin, P.n};
-    launch_scan(FlagGet{P.bflag}, e, f, nullptr, P.n, P.scan_status, &P.ctr->scan_tile_ctr[0], &P.ctr->status, st);
+    launch_scan(FlagGet{P.bflag}, e, f, nullptr, P.n, P.scan_status, &P.ctr->status, st);
 }
 
 // ---------------------------------------------------------------- voxel filter
@@ -421,7 +421,7 @@ struct P1Fin {
 void launch_p1_compact(const Plan& P, hipStream_t st) {
     launch_scan(P1Get{P.p1}, P1Emit{P.p1pos, P.pos4, P.leaf_of, P.cand4, P.cand_leaf, P.inv_p1},
                 P1Fin{P.ctr, P.p1pos, P.n}, nullptr, P.n, P.scan_status + P.scan_tiles,
-                &P.ctr->scan_tile_ctr[1], &P.ctr->status, st);
+                &P.ctr->status, st);
 }
 
 // ---------------------------------------------------------------- halo ranges
@@ -924,12 +924,11 @@ void launch_knn_plan(const Plan& P, const Params& prm, hipStream_t st) {
     const uint32_t* nl = &P.ctr->n_leaves;
     constexpr uint32_t LEAF_SCAN_BLOCKS = 64;
     launch_scan(ListsGet{P}, ListsEmit{P}, NoFin{}, nl, P.n, P.scan_status + 3 * (size_t)P.scan_tiles,
-                &P.ctr->scan_tile_ctr[3], &P.ctr->status, st, LEAF_SCAN_BLOCKS);
+                &P.ctr->status, st, LEAF_SCAN_BLOCKS);
     launch_scan(ItemsGet<true>{P}, ItemsEmit<true>{P}, NoFin{}, nl, P.n, P.scan_status + 4 * (size_t)P.scan_tiles,
-                &P.ctr->scan_tile_ctr[4], &P.ctr->status, st, LEAF_SCAN_BLOCKS);
+                &P.ctr->status, st, LEAF_SCAN_BLOCKS);
     launch_scan(ItemsGet<false>{P}, ItemsEmit<false>{P}, ItemsFin{P.ctr}, nl, P.n,
-                P.scan_status + 5 * (size_t)P.scan_tiles, &P.ctr->scan_tile_ctr[5], &P.ctr->status, st,
-                LEAF_SCAN_BLOCKS);
+                P.scan_status + 5 * (size_t)P.scan_tiles, &P.ctr->status, st, LEAF_SCAN_BLOCKS);
 }
 
 }  // namespace gdn

@@ -1,11 +1,12 @@
 // Single-pass exclusive scan with decoupled look-back.
 //
-// Workgroups take tile ids from an atomic counter, one after another until
-// the tiles run out (a grid smaller than the tile count loops), so a tile
-// only ever waits on tiles that were handed out earlier to running
-// workgroups; each wait is additionally bounded by SPIN_LIMIT (on expiry the
-// device status word records DEV_WAIT_LIMIT and the scan carries on), so no
-// launch can hang. The status words must be zero before the launch.
+// Workgroup b takes tiles b, b + G, b + 2G, ... (G workgroups). Each XCD
+// starts its workgroups in index order, so a tile only waits on tiles of
+// workgroups that have started and that wait only on lower tiles in turn;
+// each wait is additionally bounded by SPIN_LIMIT (on expiry the device
+// status word records DEV_WAIT_LIMIT and the scan carries on), so no launch
+// can hang. (Tiles from an atomic counter cost a round trip before a tile's
+// reads.) The status words must be zero before the launch.
 #pragma once
 
 #include <type_traits>
@@ -24,8 +25,8 @@ namespace gdn {
 __device__ __forceinline__ uint32_t scan_lds_at(uint32_t e) { return e + (e >> 5); }
 
 // True for a getter whose get() also stores outputs: its elements are read
-// one by one once the tile is known (its stores keep its loads in order, and
-// made before the tile counter is read they would delay it).
+// one by one (its stores keep its loads in order, so reading them all first
+// gains nothing and costs registers).
 template <class Get>
 struct ScanGetWrites {
     static constexpr bool value = false;
@@ -47,19 +48,14 @@ struct ScanEmitPre<Emit, std::void_t<typename Emit::Pre>> {
 template <int ITEMS, class Get, class Emit, class Fin>
 __global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(Get get, Emit emit, Fin fin,
                                                           const uint32_t* n_dev, uint32_t n_host,
-                                                          uint32_t* status, uint32_t* tile_ctr,
-                                                          uint32_t* dev_status) {
-    __shared__ uint32_t s_tile, s_excl;
+                                                          uint32_t* status, uint32_t* dev_status) {
+    __shared__ uint32_t s_excl;
     __shared__ uint32_t s_scan[SCAN_BLOCK / 64 + 1];
     constexpr uint32_t TILE = SCAN_BLOCK * ITEMS;
     __shared__ uint32_t s_val[TILE + TILE / 32];
     __shared__ uint32_t s_pre[TILE + TILE / 32];
     const uint32_t n = n_dev ? *n_dev : n_host;
     const uint32_t ntiles = (n + TILE - 1) / TILE;
-    // Workgroups normally take the tile counter in launch order: when the
-    // count is known on the host, the elements of the tile of this
-    // workgroup's index are read while the counter is, and kept if the
-    // counter gives that tile (read again otherwise).
     // The values are read into registers first and stored to LDS after, and
     // every read is made (past the end, of the last element, then dropped), so
     // a thread's reads, and the loads inside each get(), are in flight
@@ -86,19 +82,14 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(Get get, Emit emit, Fi
             r[i] = idx < n ? v : 0u;
         }
     };
-    const bool guess = !writes && n_dev == nullptr;
     uint32_t gv[ITEMS];
-    if (guess) read_tile(blockIdx.x * TILE, gv);
-    for (bool first = true;; first = false) {
-    if (threadIdx.x == 0) s_tile = atomicAdd(tile_ctr, 1u);
-    __syncthreads();
-    const uint32_t tile = s_tile;
+    for (uint32_t tile = blockIdx.x;; tile += gridDim.x) {
     if (tile >= ntiles) {
         if (n == 0 && tile == 0 && threadIdx.x == 0) fin(0u);
         return;
     }
     const uint32_t tbase = tile * TILE;
-    if (!(first && guess && tile == blockIdx.x)) read_tile(tbase, gv);
+    read_tile(tbase, gv);
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) s_val[scan_lds_at((uint32_t)i * SCAN_BLOCK + threadIdx.x)] = gv[i];
     __syncthreads();
@@ -184,7 +175,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(Get get, Emit emit, Fi
         }
     }
     if (tile == ntiles - 1 && threadIdx.x == 0) fin(s_excl + agg);
-    __syncthreads();  // s_tile, s_excl and the LDS tile are reused by the next tile
+    __syncthreads();  // s_excl and the LDS tile are reused by the next tile
     }
 }
 
@@ -202,16 +193,16 @@ inline uint32_t scan_tiles_for(uint32_t n_max) {
 // scans whose device count is usually far below the host bound n_max.
 template <class Get, class Emit, class Fin>
 inline void launch_scan(Get get, Emit emit, Fin fin, const uint32_t* n_dev, uint32_t n_max,
-                        uint32_t* status, uint32_t* tile_ctr, uint32_t* dev_status, hipStream_t st,
+                        uint32_t* status, uint32_t* dev_status, hipStream_t st,
                         uint32_t max_blocks = 0) {
     uint32_t tiles = scan_tiles_for(n_max);
     if (max_blocks > 0 && tiles > max_blocks) tiles = max_blocks;
     if (scan_items_for(n_max) == 4u)
         scan_kernel<4, Get, Emit, Fin><<<dim3(tiles), dim3(SCAN_BLOCK), 0, st>>>(get, emit, fin, n_dev, n_max,
-                                                                                 status, tile_ctr, dev_status);
+                                                                                 status, dev_status);
     else
         scan_kernel<SCAN_ITEMS, Get, Emit, Fin><<<dim3(tiles), dim3(SCAN_BLOCK), 0, st>>>(
-            get, emit, fin, n_dev, n_max, status, tile_ctr, dev_status);
+            get, emit, fin, n_dev, n_max, status, dev_status);
 }
 
 }  // namespace gdn

@@ -1171,23 +1171,22 @@ void launch_outputs(const Plan& P, uint8_t* keep, float* score, uint8_t* stage, 
     unsigned blocks = (P.n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     uint32_t* const sstat = P.scan_status + 2 * (size_t)P.scan_tiles;
-    uint32_t* const sctr = &P.ctr->scan_tile_ctr[2];
     if (P.n > PACKED_OUT_MIN_N) {
         hipLaunchKernelGGL(outputs_pack_kernel, dim3(xcd_grid(blocks)), dim3(256), 0, st, P);
         const PackedKeepGet get{P.outrec, keep, score, stage};
         if (P.nf == 1)
-            launch_scan(get, KeepEmit{kept_idx}, KeepFin{P.ctr, n_kept}, nullptr, P.n, sstat, sctr, &P.ctr->status, st);
+            launch_scan(get, KeepEmit{kept_idx}, KeepFin{P.ctr, n_kept}, nullptr, P.n, sstat, &P.ctr->status, st);
         else
-            launch_scan(get, BatchKeepEmit{P.keep_ex}, BatchKeepFin{P.ctr, P.keep_ex, P.n}, nullptr, P.n, sstat, sctr,
+            launch_scan(get, BatchKeepEmit{P.keep_ex}, BatchKeepFin{P.ctr, P.keep_ex, P.n}, nullptr, P.n, sstat,
                         &P.ctr->status, st);
     } else {
         if (!written) hipLaunchKernelGGL(outputs_kernel, dim3(blocks), dim3(256), 0, st, P, keep, score, stage);
         if (P.nf == 1)
-            launch_scan(KeepGet{keep}, KeepEmit{kept_idx}, KeepFin{P.ctr, n_kept}, nullptr, P.n, sstat, sctr,
+            launch_scan(KeepGet{keep}, KeepEmit{kept_idx}, KeepFin{P.ctr, n_kept}, nullptr, P.n, sstat,
                         &P.ctr->status, st);
         else
             launch_scan(KeepGet{keep}, BatchKeepEmit{P.keep_ex}, BatchKeepFin{P.ctr, P.keep_ex, P.n}, nullptr, P.n,
-                        sstat, sctr, &P.ctr->status, st);
+                        sstat, &P.ctr->status, st);
     }
     if (P.nf > 1) hipLaunchKernelGGL(kept_frames_kernel, dim3(blocks), dim3(256), 0, st, P, keep, kept_idx, n_kept);
 }
