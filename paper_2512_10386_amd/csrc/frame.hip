@@ -705,9 +705,13 @@ __device__ __forceinline__ uint32_t cell_lower_bound(const uint64_t* keys, uint3
 // position that starts a deep cell marks (deepf = 2) the start of that cell
 // and of each non-empty neighbouring cell in its frame. The marks are plain
 // stores of one value, so cells marked twice need no atomics.
+// LDS: the frame offsets are staged in LDS (batches of fewer than
+// SORT_FOFF_LDS frames), fixed at compile time so that they are read with LDS
+// or global instructions, not generic ones.
+template <bool LDS>
 __global__ __launch_bounds__(SEG_BLOCK) void deep_mark_kernel(Plan P, uint32_t cap) {
     __shared__ uint32_t s_foff[SORT_FOFF_LDS];  // batches of fewer frames search the offsets here
-    const bool lds = P.nf > 1u && P.nf < SORT_FOFF_LDS;
+    constexpr bool lds = LDS;
     if (lds)
         for (uint32_t i = threadIdx.x; i <= P.nf; i += blockDim.x) s_foff[i] = P.foff[i];
     __syncthreads();
@@ -737,6 +741,7 @@ __global__ __launch_bounds__(SEG_BLOCK) void deep_mark_kernel(Plan P, uint32_t c
 // read keys of a cell another block is sorting compare cell prefixes only,
 // which the sort does not change; a mark is only read by the thread of its
 // own position, and only that cell's block rewrites it.
+template <bool LDS>
 __global__ __launch_bounds__(SEG_BLOCK) void deep_cells_kernel(Plan P, uint32_t cap) {
     __shared__ uint32_t s_base[256];
     __shared__ uint32_t s_w[SEG_BLOCK / 64][256];
@@ -745,7 +750,7 @@ __global__ __launch_bounds__(SEG_BLOCK) void deep_cells_kernel(Plan P, uint32_t 
     __shared__ uint8_t s_deep[SEG_BLOCK];
     __shared__ uint32_t s_nseg;
     __shared__ uint32_t s_foff[SORT_FOFF_LDS];  // batches of fewer frames search the offsets here
-    const bool lds = P.nf > 1u && P.nf < SORT_FOFF_LDS;
+    constexpr bool lds = LDS;
     if (lds)
         for (uint32_t i = threadIdx.x; i <= P.nf; i += blockDim.x) s_foff[i] = P.foff[i];
     for (uint32_t base = blockIdx.x * SEG_BLOCK; base < P.n; base += gridDim.x * SEG_BLOCK) {
@@ -791,8 +796,11 @@ void launch_sort(const Plan& P, const Params& prm, hipStream_t st) {
     unsigned blocks = (P.n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(deep_mark_kernel, dim3(blocks), dim3(SEG_BLOCK), 0, st, P, (uint32_t)prm.leaf_cap);
-    hipLaunchKernelGGL(deep_cells_kernel, dim3(blocks), dim3(SEG_BLOCK), 0, st, P, (uint32_t)prm.leaf_cap);
+    const bool lds = P.nf > 1u && P.nf < SORT_FOFF_LDS;
+    hipLaunchKernelGGL(lds ? deep_mark_kernel<true> : deep_mark_kernel<false>, dim3(blocks), dim3(SEG_BLOCK), 0, st, P,
+                       (uint32_t)prm.leaf_cap);
+    hipLaunchKernelGGL(lds ? deep_cells_kernel<true> : deep_cells_kernel<false>, dim3(blocks), dim3(SEG_BLOCK), 0, st,
+                       P, (uint32_t)prm.leaf_cap);
 }
 
 }  // namespace gdn

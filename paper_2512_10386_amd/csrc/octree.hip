@@ -89,10 +89,15 @@ __device__ __forceinline__ int leaf_level_of(const Plan& P, uint32_t s, uint32_t
 // gathers the points' coordinates into sorted order (pos4: x, y, z and the
 // original index's bits); each XCD takes one eighth of the positions, so a
 // frame's coordinates are fetched into one XCD's L2.
+// LDS: the batch's frame offsets are staged in LDS (fewer than SORT_FOFF_LDS
+// frames); a compile-time choice, so that the offsets are read with LDS or
+// with global instructions rather than generic ones through a pointer that
+// may be either.
+template <bool LDS>
 __global__ __launch_bounds__(256) void boundary_flag_kernel(Plan P, uint32_t cap, const float* __restrict__ xyz) {
     // batches of fewer than SORT_FOFF_LDS frames search the offsets in LDS
     __shared__ uint32_t s_foff[SORT_FOFF_LDS];
-    const bool lds = P.nf > 1u && P.nf < SORT_FOFF_LDS;
+    constexpr bool lds = LDS;
     if (lds) {
         for (uint32_t i = threadIdx.x; i <= P.nf; i += blockDim.x) s_foff[i] = P.foff[i];
         __syncthreads();
@@ -123,7 +128,9 @@ struct FlagGet {
 void launch_leaves(const Plan& P, const Params& prm, const float* xyz, hipStream_t st) {
     unsigned blocks = (P.n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(boundary_flag_kernel, dim3(xcd_grid(blocks)), dim3(256), 0, st, P, (uint32_t)prm.leaf_cap,
+    const bool lds = P.nf > 1u && P.nf < SORT_FOFF_LDS;
+    hipLaunchKernelGGL(lds ? boundary_flag_kernel<true> : boundary_flag_kernel<false>, dim3(xcd_grid(blocks)), dim3(256),
+                       0, st, P, (uint32_t)prm.leaf_cap,
                        xyz);
     BoundaryEmit e{P.leaf_of, P.leaf_begin};
     BoundaryFin f{P.ctr, P.leaf_begin, P.n};
@@ -460,6 +467,7 @@ constexpr int HALO_LEAVES = 8;  // leaves per 256-thread block (32 threads each,
 // it (clipped to the grid and to the frame), then the non-empty ranges are
 // sorted by rank counting and runs of touching ranges merged with ballots;
 // the result is the leaf's candidate ranges in P1 order.
+template <bool LDS>
 __global__ __launch_bounds__(256) void halo_kernel(Plan P, uint32_t cap) {
     __shared__ uint2 s_r[HALO_LEAVES][32];
     __shared__ uint2 s_s[HALO_LEAVES][32];
@@ -470,7 +478,7 @@ __global__ __launch_bounds__(256) void halo_kernel(Plan P, uint32_t cap) {
     const unsigned long long half = (lane & 32u) ? 0xFFFFFFFF00000000ull : 0x00000000FFFFFFFFull;
     const unsigned long long below = lane == 0u ? 0ull : (~0ull >> (64u - lane));
     __shared__ uint32_t s_foff[SORT_FOFF_LDS];  // batches of fewer frames search the offsets here
-    const bool lds = P.nf > 1u && P.nf < SORT_FOFF_LDS;
+    constexpr bool lds = LDS;
     if (lds)
         for (uint32_t i = threadIdx.x; i <= P.nf; i += blockDim.x) s_foff[i] = P.foff[i];
     __syncthreads();
@@ -552,7 +560,9 @@ void launch_halo(const Plan& P, const Params& prm, hipStream_t st) {
     unsigned blocks = (P.n + HALO_LEAVES - 1) / HALO_LEAVES;
     if (blocks > 2048) blocks = 2048;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(halo_kernel, dim3(blocks), dim3(256), 0, st, P, (uint32_t)prm.leaf_cap);
+    const bool lds = P.nf > 1u && P.nf < SORT_FOFF_LDS;
+    hipLaunchKernelGGL(lds ? halo_kernel<true> : halo_kernel<false>, dim3(blocks), dim3(256), 0, st, P,
+                       (uint32_t)prm.leaf_cap);
 }
 
 // ---------------------------------------------------------------- kNN plan
