@@ -361,8 +361,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(frames are independent; see the design notes on sharding).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(frames are independent, so several GPUs would each take whole frames).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

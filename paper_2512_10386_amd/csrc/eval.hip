@@ -53,7 +53,7 @@ __global__ __launch_bounds__(NN_BLOCK) void nn_kernel(const float* __restrict__ 
         __syncthreads();
         for (uint32_t e = 0; e < tn; ++e) {
             const float dx = sx[e] - ax, dy = sy[e] - ay, dz = sz[e] - az;
-            const float d = (dx * dx + dy * dy) + dz * dz;  // no contraction in this build
+            const float d = (dx * dx + dy * dy) + dz * dz;  // compiled without contraction (no FMA)
             if (d < best) {
                 best = d;
                 bi = t0 + e;
