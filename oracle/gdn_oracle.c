@@ -14,8 +14,7 @@
  *   -> per-leaf median density (Eq. 16) -> dual-weight score (Eq. 15-21)
  *   -> per-leaf top-lambda retention and union of leaves (Eq. 22).
  *
- * Readings taken where the paper is silent (each is listed with its reason in
- * the design notes of the repository):
+ * Readings taken where the paper is silent:
  *   - octree root = cube of side S = largest bbox extent at the bbox minimum;
  *     21-bit-per-axis Morton keys, x in the lowest bit; a node splits while it
  *     holds more than leaf_cap points and is above the depth limit;
