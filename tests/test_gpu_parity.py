@@ -133,6 +133,19 @@ def test_many_leaves_in_one_frame(den, oracle):
     assert ref["n_leaves"] > 2048
 
 
+def test_leaves_without_p1_points(den, oracle):
+    """Leaves none of whose points pass the occupancy filter (no P1 point),
+    beside leaves with P1 points: the selects skip them and their points
+    come out with stage 0, against the oracle."""
+    rng = np.random.default_rng(77)
+    dense = rng.normal(0.0, 0.02, size=(6000, 3))
+    sparse = rng.uniform(-10.0, 10.0, size=(600, 3))
+    xyz = np.concatenate([dense, sparse]).astype(np.float32)
+    g, ref = check(den, oracle, xyz, k=8, leaf_cap=32, min_vox_count=3)
+    p1_per_leaf = np.bincount(ref["leaf_of"], weights=ref["p1"], minlength=ref["n_leaves"])
+    assert (p1_per_leaf == 0).any() and (p1_per_leaf > 0).any()
+
+
 @pytest.mark.parametrize("chunk", [4096, 16384])
 def test_big_leaves_chunked_candidates(den, oracle, chunk):
     xyz, _ = synth.uniform_cube(10, 60000)
