@@ -372,9 +372,11 @@ static gdn_status run(gdn_ctx* ctx, const gdn_params* p, const float* xyz, int64
         (void)hipEventRecord(ce->ev[0], st);
     }
 
-    gdn::launch_zero(P, st);
+    // a plain single-frame call clears the zeroed block inside the box kernel
+    const bool clear_in_bbox = !frame_off && gdn::bbox_one_frame(P);
+    if (!clear_in_bbox) gdn::launch_zero(P, st);
     if (frame_off) gdn::launch_frames(P, frame_off, st);
-    gdn::launch_bbox(P, xyz, st);
+    gdn::launch_bbox(P, xyz, st, clear_in_bbox);
     gdn::launch_morton(P, prm, xyz, st);
     gdn::launch_sort(P, prm, st);
     gdn::launch_leaves(P, prm, xyz, st);

@@ -184,16 +184,30 @@ __global__ __launch_bounds__(256) void bbox_kernel(const float* __restrict__ xyz
     }
 }
 
-// A single frame with few points: each wave reduces its 512-point chunks,
-// the block combines its four waves in LDS and adds one box per block with
-// atomics (a quarter of the atomics of one box per wave, all of them on the
-// same six words, which is what bounds the one-box-per-wave form).
-__global__ __launch_bounds__(256) void bbox_one_kernel(const float* __restrict__ xyz, Plan P, uint32_t chunk) {
+// A single frame with few points: each wave reduces its 512-point chunks and
+// the block combines its four waves; each block writes its box (ordered-uint
+// max of -min and max) and non-finite count to bbox_part[block], which the
+// Morton kernel folds (no atomics, so the accumulators need no clearing). On a
+// plain call the blocks also clear the workspace's zeroed block (counters,
+// histograms, look-back status words: nothing here uses them) and write the
+// one-frame offset table, in place of a separate fill launch.
+__global__ __launch_bounds__(256) void bbox_one_kernel(const float* __restrict__ xyz, Plan P, uint32_t chunk,
+                                                       bool clear) {
     __shared__ float s_mn[4][3], s_mx[4][3];
     __shared__ uint32_t s_bad[4];
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
     const uint32_t n = P.n, nchunks = (n + chunk - 1) / chunk;
+    if (clear) {
+        uint4* z = (uint4*)P.zero_begin;
+        const size_t n16 = P.zero_bytes / 16;
+        for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
+            z[i] = make_uint4(0u, 0u, 0u, 0u);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            P.foff[0] = 0u;
+            P.foff[1] = n;
+        }
+    }
     float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     uint32_t bad = 0;
     for (uint32_t c = wid; c < nchunks; c += nw)
@@ -207,7 +221,7 @@ __global__ __launch_bounds__(256) void bbox_one_kernel(const float* __restrict__
         s_bad[wave] = bad;
     }
     __syncthreads();
-    FrameStat* fs = P.fstat;
+    uint32_t* part = P.bbox_part + 8 * (size_t)blockIdx.x;
     if (threadIdx.x < 3u) {
         const uint32_t a = threadIdx.x;
         float lo = s_mn[0][a], hi = s_mx[0][a];
@@ -215,18 +229,10 @@ __global__ __launch_bounds__(256) void bbox_one_kernel(const float* __restrict__
             lo = fminf(lo, s_mn[w][a]);
             hi = fmaxf(hi, s_mx[w][a]);
         }
-        if (lo <= hi) {
-            atomicMax(&fs->bbox_nmin[a], ~f32_ordered(lo));
-            atomicMax(&fs->bbox_max[a], f32_ordered(hi));
-        }
+        part[a] = lo <= hi ? ~f32_ordered(lo) : 0u;
+        part[3 + a] = lo <= hi ? f32_ordered(hi) : 0u;
     }
-    if (threadIdx.x == 3u) {
-        const uint32_t b = s_bad[0] + s_bad[1] + s_bad[2] + s_bad[3];
-        if (b) {
-            atomicAdd(&fs->nonfinite, b);
-            atomicOr(&P.ctr->status, DEV_NONFINITE);
-        }
-    }
+    if (threadIdx.x == 3u) part[6] = s_bad[0] + s_bad[1] + s_bad[2] + s_bad[3];
 }
 
 // One wave per frame: fold the frame's whole chunks into its accumulators.
@@ -260,18 +266,24 @@ __global__ __launch_bounds__(256) void bbox_fold_kernel(Plan P) {
     }
 }
 
-void launch_bbox(const Plan& P, const float* xyz, hipStream_t st) {
-    // few points: 512-point chunks (one wave each, enough waves to cover the
-    // load latency) that all add their boxes with atomics (no fold launch);
-    // otherwise BBOX_CHUNK chunks and the fold
-    const bool direct = P.n <= (1u << 20);
-    const uint32_t chunk = direct ? 512u : BBOX_CHUNK;
+// Few points: 512-point chunks (one wave each, enough waves to cover the
+// load latency); otherwise BBOX_CHUNK chunks and the fold.
+static bool bbox_direct(const Plan& P) { return P.n <= (1u << 20); }
+static unsigned bbox_blocks(const Plan& P) {
+    const uint32_t chunk = bbox_direct(P) ? 512u : BBOX_CHUNK;
     const uint32_t nchunks = (P.n + chunk - 1) / chunk;
     unsigned blocks = (nchunks + 3) / 4;
     if (blocks > 2048) blocks = 2048;
-    if (blocks == 0) blocks = 1;
-    if (direct && P.nf == 1) {
-        hipLaunchKernelGGL(bbox_one_kernel, dim3(blocks), dim3(256), 0, st, xyz, P, chunk);
+    return blocks ? blocks : 1u;
+}
+bool bbox_one_frame(const Plan& P) { return bbox_direct(P) && P.nf == 1; }
+
+void launch_bbox(const Plan& P, const float* xyz, hipStream_t st, bool clear) {
+    const bool direct = bbox_direct(P);
+    const uint32_t chunk = direct ? 512u : BBOX_CHUNK;
+    const unsigned blocks = bbox_blocks(P);
+    if (bbox_one_frame(P)) {
+        hipLaunchKernelGGL(bbox_one_kernel, dim3(blocks), dim3(256), 0, st, xyz, P, chunk, clear);
         return;
     }
     hipLaunchKernelGGL(bbox_kernel, dim3(blocks), dim3(256), 0, st, xyz, P, direct, chunk);
@@ -321,12 +333,46 @@ __global__ __launch_bounds__(256) void frame_const_kernel(Plan P, double min_lea
 // payload and the digit histograms of the sort: key digits 4..7, then the
 // frame id digits of a batch. A single frame computes its constants per block.
 constexpr uint32_t MORTON_U = 8;
-__global__ __launch_bounds__(256) void morton_kernel(const float* __restrict__ xyz, Plan P, double min_leaf_side) {
+// nparts > 0: a single frame whose box is in nparts per-block records of
+// bbox_one_kernel, folded here by every block (block 0 also stores the
+// frame's statistics and constants and flags non-finite input).
+__global__ __launch_bounds__(256) void morton_kernel(const float* __restrict__ xyz, Plan P, double min_leaf_side,
+                                                     uint32_t nparts) {
     __shared__ FrameConst s_fc;
+    __shared__ FrameStat s_stat;
     __shared__ uint32_t s_hist[SORT_PASSES_MAX][256];
     const uint32_t n = P.n, nf = P.nf, nh = P.sort_passes;
     for (uint32_t i = threadIdx.x; i < nh * 256u; i += blockDim.x) (&s_hist[0][0])[i] = 0u;
-    if (nf == 1 && threadIdx.x == 0) {
+    if (nf == 1 && nparts > 0 && threadIdx.x < 64u) {
+        const uint32_t lane = threadIdx.x;
+        uint32_t v[7] = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
+        for (uint32_t c = lane; c < nparts; c += 64u) {
+            const uint32_t* part = P.bbox_part + 8 * (size_t)c;
+#pragma unroll
+            for (int a = 0; a < 6; ++a) v[a] = max(v[a], part[a]);
+            v[6] += part[6];
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+            for (int a = 0; a < 6; ++a) v[a] = max(v[a], (uint32_t)__shfl_xor((int)v[a], o, 64));
+            v[6] += (uint32_t)__shfl_xor((int)v[6], o, 64);
+        }
+        if (lane == 0) {
+            for (int a = 0; a < 3; ++a) {
+                s_stat.bbox_nmin[a] = v[a];
+                s_stat.bbox_max[a] = v[3 + a];
+            }
+            s_stat.nonfinite = v[6];
+            s_stat.pad = 0u;
+            frame_consts(&s_stat, min_leaf_side, &s_fc);
+            if (blockIdx.x == 0) {
+                *P.fstat = s_stat;
+                *P.fc = s_fc;
+                if (v[6]) atomicOr(&P.ctr->status, DEV_NONFINITE);
+            }
+        }
+    } else if (nf == 1 && threadIdx.x == 0) {
         frame_consts(P.fstat, min_leaf_side, &s_fc);
         if (blockIdx.x == 0) *P.fc = s_fc;
     }
@@ -397,7 +443,8 @@ void launch_morton(const Plan& P, const Params& prm, const float* xyz, hipStream
     if (P.nf > 1) hipLaunchKernelGGL(frame_const_kernel, dim3(1), dim3(256), 0, st, P, prm.min_leaf_side);
     unsigned blocks = (P.n + 2047) / 2048;
     if (blocks > 512) blocks = 512;
-    hipLaunchKernelGGL(morton_kernel, dim3(blocks), dim3(256), 0, st, xyz, P, prm.min_leaf_side);
+    const uint32_t nparts = bbox_one_frame(P) ? bbox_blocks(P) : 0u;
+    hipLaunchKernelGGL(morton_kernel, dim3(blocks), dim3(256), 0, st, xyz, P, prm.min_leaf_side, nparts);
 }
 
 // ---------------------------------------------------------------- radix sort

@@ -11,7 +11,10 @@ namespace gdn {
 // the re-sort of deep level-10 cells)
 void launch_zero(const Plan& P, hipStream_t st);
 void launch_frames(const Plan& P, const int64_t* frame_off, hipStream_t st);
-void launch_bbox(const Plan& P, const float* xyz, hipStream_t st);
+// A single frame of up to 2^20 points: one box kernel that can also clear
+// the zeroed block (clear: the fill launch is skipped).
+bool bbox_one_frame(const Plan& P);
+void launch_bbox(const Plan& P, const float* xyz, hipStream_t st, bool clear = false);
 void launch_morton(const Plan& P, const Params& prm, const float* xyz, hipStream_t st);
 void launch_sort(const Plan& P, const Params& prm, hipStream_t st);
 
