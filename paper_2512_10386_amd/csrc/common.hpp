@@ -28,7 +28,7 @@ constexpr int SORT_SHORT_FIRST = 4;
 static_assert(3 * (MORTON_BITS - SORT_SHORT_LEVEL) >= 8 * SORT_SHORT_FIRST, "short sort must hold the cell prefix");
 static_assert(SORT_SHORT_FIRST % 2 == 0, "skipped passes keep the ping-pong parity");
 constexpr uint32_t MAX_FRAMES = 4096;         // frames per batched call (frame table staged in LDS)
-constexpr int SCAN_BLOCK = 256;
+constexpr int SCAN_BLOCK = 512;                // look-back scan workgroup (fewer tiles to look back over than 256)
 constexpr int SCAN_ITEMS = 16;
 constexpr uint32_t SCAN_SMALL_N = 1u << 20;   // scans up to this size: 4 items per thread
 constexpr int SCAN_SLOTS = 6;                 // scans per call: leaves, P1, keep, 3 kNN plan scans
